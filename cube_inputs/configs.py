@@ -1,0 +1,67 @@
+"""Workload parameters of the synthetic boxes.
+
+Units: lengths in mean inter-particle spacings (box side L = n_side), time in
+units of the dynamical time, particle mass 1.
+
+The three single-box workloads:
+
+* ``c1``  -- 32^3 particles, one periodic tile, fine mesh 64^3 (2 cells per
+  spacing), coarse mesh 16^3, P(k) ~ k^-2 Zel'dovich ICs at rms displacement
+  0.2 spacing, one step.
+* ``c2``  -- 256^3 particles, 4^3 tiles of 64^3 particles, fine mesh per tile
+  128^3 plus a 16-cell buffer per face (160^3 FFT box), coarse mesh 64^3,
+  P(k) ~ k^-2 at rms 0.5, ten steps.
+* ``c3``  -- 1024^3 particles, 16^3 tiles of 64^3 particles, same tile box
+  as c2, coarse mesh 512^3, P(k) ~ k^-1.5 at rms 2 spacings, twenty steps.
+
+Plus small geometry variants used by the parity tests (several tiles with a
+ragged particle distribution at a size the oracle finishes in seconds).
+"""
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class BoxSpec:
+    name: str
+    n_side: int            # particles per dimension
+    tiles_per_dim: int     # n_t
+    fine_per_spacing: int  # f: fine cells per particle spacing
+    coarse_ratio: int      # r: fine cells per coarse cell
+    buffer_fine: int       # b: tile buffer in fine cells (0 when n_t == 1)
+    r_cut_fine: int        # a: force-split radius in fine cells
+    dt: float              # float32-representable time step
+    v_headroom: float      # velocity-scale headroom h_v
+    spectral_index: float  # density power-spectrum slope n, P ~ k^n
+    rms_disp: float        # rms |psi| of the Zel'dovich displacement
+    seed: int
+    steps: int
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+    @property
+    def n_particles(self) -> int:
+        return self.n_side ** 3
+
+
+DT = float(np.float32(0.05))
+
+CONFIGS = {
+    "c1": BoxSpec("c1", 32, 1, 2, 4, 0, 12, DT, 2.0, -2.0, 0.2, 1001, 1),
+    "c2": BoxSpec("c2", 256, 4, 2, 8, 16, 12, DT, 2.0, -2.0, 0.5, 1002, 10),
+    "c3": BoxSpec("c3", 1024, 16, 2, 4, 16, 12, DT, 2.0, -1.5, 2.0, 1003, 20),
+    # c2's tile geometry (160^3 tile box, r = 8, b = 16) on a box the oracle
+    # runs in seconds: 2^3 tiles of 64^3 particles.
+    "c2s": BoxSpec("c2s", 128, 2, 2, 8, 16, 12, DT, 2.0, -2.0, 0.5, 1012, 3),
+    # c3's tile geometry (r = 4, b = 16) on 2^3 tiles of 64^3 particles.
+    "c3s": BoxSpec("c3s", 128, 2, 2, 4, 16, 12, DT, 2.0, -1.5, 2.0, 1013, 2),
+    # a small tiled box: 4^3 tiles of 16^3 particles (tile box 32 + 2*16).
+    "t4": BoxSpec("t4", 64, 4, 2, 4, 16, 12, DT, 2.0, -2.0, 0.7, 1021, 3),
+}
+
+
+def config(name: str) -> BoxSpec:
+    return CONFIGS[name]

@@ -1,0 +1,98 @@
+"""Seeded Zel'dovich initial conditions (Sec. IV-A: the initial positions and
+velocities come from the Zel'dovich approximation).
+
+Recipe (static background, units of the dynamical time, so the growing mode
+grows as e^t and its velocity equals its displacement):
+
+1. Gaussian white noise on the n^3 lattice from ``numpy.random.default_rng(seed)``
+   (PCG64), array axes ordered (z, y, x) so x is fastest in memory.
+2. Forward real FFT; multiply by k^(n/2) so the density spectrum is P ~ k^n;
+   zero the k = 0 mode and every Nyquist plane.
+3. Displacement psi_hat = i k delta_hat / k^2 (so that delta = -div psi),
+   inverse FFT per component.
+4. Rescale psi so that the rms of the 3-D |psi| equals the target.
+5. Positions x = q + psi (mod L) with lattice points q = i + 1/2; velocities
+   v = psi * exp(-dt/2) (the leapfrog velocity half a step before t = 0).
+
+Particles are returned in lattice order p = ix + n*(iy + n*iz).  The arrays are
+float32: both the HIP library and the oracle encode these exact values.
+"""
+
+import numpy as np
+
+
+def _fft_module():
+    try:
+        import scipy.fft as sfft
+        return sfft, {"workers": -1}
+    except Exception:  # pragma: no cover - scipy is present in this image
+        return np.fft, {}
+
+
+def zeldovich_ics(n: int, spectral_index: float, rms_disp: float, seed: int,
+                  dt: float):
+    """Return (pos, vel), each float32 of shape (n^3, 3), lattice order."""
+    fft, kw = _fft_module()
+    # float64 arithmetic below 512^3, float32 above (memory); deterministic either way
+    real_t = np.float64 if n <= 256 else np.float32
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((n, n, n), dtype=real_t)      # axes (z, y, x)
+    dk = fft.rfftn(noise, **kw)
+    del noise
+    kz = np.fft.fftfreq(n, d=1.0 / n).astype(real_t)          # integer mode numbers
+    ky = kz
+    kx = np.fft.rfftfreq(n, d=1.0 / n).astype(real_t)
+    two_pi_over_l = real_t(2.0 * np.pi / n)
+    KZ = kz[:, None, None] * two_pi_over_l
+    KY = ky[None, :, None] * two_pi_over_l
+    KX = kx[None, None, :] * two_pi_over_l
+    k2 = KX * KX + KY * KY + KZ * KZ
+    k2[0, 0, 0] = 1.0
+    amp = k2 ** real_t(spectral_index / 4.0)                  # |k|^(n/2)
+    amp[0, 0, 0] = 0.0
+    nyq = n // 2
+    if n % 2 == 0:
+        amp[nyq, :, :] = 0.0
+        amp[:, nyq, :] = 0.0
+        amp[:, :, nyq] = 0.0
+    dk *= amp
+    del amp
+    inv_k2 = (1.0 / k2).astype(real_t)
+    del k2
+    psi = np.empty((3, n, n, n), dtype=real_t)
+    for c, K in enumerate((KX, KY, KZ)):
+        comp = dk * (1j * K * inv_k2)
+        psi[c] = fft.irfftn(comp, s=(n, n, n), **kw)
+        del comp
+    del dk, inv_k2
+    rms = np.sqrt(np.mean(np.sum(psi.astype(np.float64) ** 2, axis=0)))
+    psi *= real_t(rms_disp / rms)
+    # lattice order p = ix + n*(iy + n*iz): flatten (z, y, x) arrays in C order
+    psi_flat = psi.reshape(3, -1).T.astype(np.float64)         # (N, 3) x,y,z
+    del psi
+    idx = np.arange(n, dtype=np.float64) + 0.5
+    qz, qy, qx = np.meshgrid(idx, idx, idx, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
+    del qx, qy, qz
+    pos = np.mod(q + psi_flat, float(n))
+    pos = pos.astype(np.float32)
+    pos[pos >= np.float32(n)] = np.float32(0.0)               # mod can round up to L
+    vel = (psi_flat * np.exp(-0.5 * dt)).astype(np.float32)
+    return pos, vel
+
+
+def plane_wave_ics(n: int, amplitude: float, dt: float, mode: int = 1):
+    """A single Zel'dovich plane wave along x: psi = A sin(2 pi mode q_x / L) e_x.
+
+    Returns (q, pos, vel) as float64 arrays of shape (n^3, 3): the lattice
+    points, the displaced positions and the half-step-back growing-mode
+    velocities.  Used for the dynamics pins (exact solution before shell
+    crossing)."""
+    idx = np.arange(n, dtype=np.float64) + 0.5
+    qz, qy, qx = np.meshgrid(idx, idx, idx, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
+    psi = np.zeros_like(q)
+    psi[:, 0] = amplitude * np.sin(2.0 * np.pi * mode * q[:, 0] / n)
+    pos = np.mod(q + psi, float(n))
+    vel = psi * np.exp(-0.5 * dt)
+    return q, pos, vel

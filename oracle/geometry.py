@@ -1,0 +1,115 @@
+"""Box geometry and the canonical cell order.
+
+Sec. II (two-level decomposition): the volume is cut into cubic tiles; the
+short-range PM of a tile runs on a mesh enlarged by the cut-off radius on every
+face.  Sec. III-A: particles are stored cell-ordered on the coarse mesh.
+
+Readings: R1 units (lengths in particle spacings), R3 cell-centred
+meshes aligned at the origin, R5 canonical order = tile-major (tile index x
+fastest), then cells x-fastest inside the tile, R11 tile box F = T + 2b.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Box:
+    n_side: int
+    tiles_per_dim: int
+    fine_per_spacing: int
+    coarse_ratio: int
+    buffer_fine: int
+    r_cut_fine: int
+    dt: float
+    v_headroom: float = 2.0
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.n_side, spec.tiles_per_dim, spec.fine_per_spacing,
+                   spec.coarse_ratio, spec.buffer_fine, spec.r_cut_fine,
+                   float(spec.dt), float(spec.v_headroom))
+
+    # ---- derived sizes -------------------------------------------------
+    @property
+    def h(self) -> float:             # fine cell size in spacings
+        return 1.0 / self.fine_per_spacing
+
+    @property
+    def H(self) -> float:             # coarse cell size in spacings
+        return self.coarse_ratio / self.fine_per_spacing
+
+    @property
+    def n_fine(self) -> int:          # fine cells per box side
+        return self.n_side * self.fine_per_spacing
+
+    @property
+    def n_coarse(self) -> int:        # N_c
+        return self.n_fine // self.coarse_ratio
+
+    @property
+    def T(self) -> int:               # tile side, fine cells
+        return self.n_fine // self.tiles_per_dim
+
+    @property
+    def Tc(self) -> int:              # tile side, coarse cells
+        return self.T // self.coarse_ratio
+
+    @property
+    def F(self) -> int:               # tile FFT box side, fine cells
+        return self.T + 2 * self.buffer_fine
+
+    @property
+    def halo_c(self) -> int:          # buffer in coarse cells
+        return self.buffer_fine // self.coarse_ratio
+
+    @property
+    def n_cells(self) -> int:
+        return self.n_coarse ** 3
+
+    @property
+    def n_tiles(self) -> int:
+        return self.tiles_per_dim ** 3
+
+    def validate(self):
+        f, r, b, a = (self.fine_per_spacing, self.coarse_ratio,
+                      self.buffer_fine, self.r_cut_fine)
+        assert self.n_fine % r == 0 and self.n_fine % self.tiles_per_dim == 0
+        assert self.T % r == 0 and b % r == 0
+        if self.tiles_per_dim == 1:
+            assert b == 0 and 2 * a < self.F
+        else:
+            # R11: a + 3 <= b keeps every target's stencil inside the exact
+            # part of the tile box
+            assert a <= b - 3
+            assert self.F // r <= self.n_coarse
+        return self
+
+    # ---- canonical order (R5) ------------------------------------------
+    def canon(self, cx, cy, cz):
+        """Canonical index of coarse cell (cx, cy, cz); arrays allowed."""
+        Tc, nt = self.Tc, self.tiles_per_dim
+        cx = np.asarray(cx, dtype=np.int64)
+        cy = np.asarray(cy, dtype=np.int64)
+        cz = np.asarray(cz, dtype=np.int64)
+        tile = (cx // Tc) + nt * ((cy // Tc) + nt * (cz // Tc))
+        local = (cx % Tc) + Tc * ((cy % Tc) + Tc * (cz % Tc))
+        return tile * Tc ** 3 + local
+
+    def cell_of_canon(self, c):
+        """Inverse of canon: (cx, cy, cz) arrays."""
+        Tc, nt = self.Tc, self.tiles_per_dim
+        c = np.asarray(c, dtype=np.int64)
+        tile, local = np.divmod(c, Tc ** 3)
+        tx = tile % nt
+        ty = (tile // nt) % nt
+        tz = tile // (nt * nt)
+        lx = local % Tc
+        ly = (local // Tc) % Tc
+        lz = local // (Tc * Tc)
+        return tx * Tc + lx, ty * Tc + ly, tz * Tc + lz
+
+    def tile_coords(self, t):
+        nt = self.tiles_per_dim
+        return t % nt, (t // nt) % nt, t // (nt * nt)

@@ -1,0 +1,72 @@
+"""One time step on the compressed state: force, kick, drift, recount, compact.
+
+Integrator (R8): kick-drift leapfrog on (x_n, v_{n-1/2}):
+    v_{n+1/2} = v_{n-1/2} + a(x_n) dt,    x_{n+1} = x_n + v_{n+1/2} dt.
+
+Kick and velocity requantisation (R6, R7, R17):
+    s' = pow2ceil(h_v M s / 127)            (M = max|u| after the previous kick)
+    u' = clamp(rint((u s + a dt) / s'), -127, 127),  M' = max|u'|.
+
+Drift in cell-local quanta (Eq. (2), R15): per axis
+    X  = m + 1/2 + ((u' s') (256 / H)) dt
+    q  = floor(X),  carry = floor(q / 256),  m' = q - 256 carry,
+    n_c' = (n_c + carry) mod N_c.
+The product is exact in float64 (an 8-bit integer times powers of two times
+the 24-bit dt), so positions never pass through rounded global coordinates.
+
+Recount and compaction (Sec. III-A cell-ordered storage, R16): the new counts
+are a histogram of the new cells, and particles are reordered by a stable
+counting sort of the old order by new canonical cell.
+
+Pins: the dynamics tests (Zel'dovich plane wave, leapfrog order) exercise the
+same kick/drift through the float-state twin in float_mode.py; the compaction
+is pinned by brute force (tests/test_oracle_step.py).
+"""
+
+import numpy as np
+
+from . import codec
+from .pm import Solver
+
+
+def kick(box, state, acc):
+    s_new = codec.next_velocity_scale(box, state.s, state.M)
+    v = state.u.T.astype(np.float64) * state.s + acc * box.dt
+    w = np.rint(v / s_new)
+    sat = int(np.count_nonzero(np.abs(w) > 127.0))
+    u_new = np.clip(w, -127.0, 127.0).astype(np.int64)       # (N, 3)
+    M_new = int(np.max(np.abs(u_new))) if u_new.size else 0
+    return u_new, s_new, M_new, sat
+
+
+def drift(box, state, u_new, s_new):
+    """New global quanta (N, 3) and the per-particle carries."""
+    m = state.m.T.astype(np.float64)                          # (N, 3)
+    D = (u_new.astype(np.float64) * s_new) * (256.0 / box.H) * box.dt
+    X = (m + 0.5) + D
+    q = np.floor(X).astype(np.int64)
+    carry = np.floor_divide(q, 256)
+    m_new = q - 256 * carry
+    Q_old = state.quanta()
+    cell_old = Q_old // 256
+    cell_new = np.mod(cell_old + carry, box.n_coarse)
+    return 256 * cell_new + m_new, carry
+
+
+def step(solver: Solver, state, workers=None, return_info=False):
+    box = solver.box
+    acc = solver.forces(state, workers=workers)
+    u_new, s_new, M_new, sat = kick(box, state, acc)
+    Q_new, carry = drift(box, state, u_new, s_new)
+    new = codec.build_state(box, Q_new, u_new, s_new, M_new, state.ids,
+                            state.step + 1, state.saturations + sat)
+    if return_info:
+        return new, {"acc": acc, "max_carry": int(np.max(np.abs(carry))) if carry.size else 0,
+                     "saturations": sat}
+    return new
+
+
+def run(solver: Solver, state, nsteps: int, workers=None):
+    for _ in range(nsteps):
+        state = step(solver, state, workers=workers)
+    return state
