@@ -1,0 +1,200 @@
+/*
+ * cube.h -- C ABI of libcube.so, an MI355X (gfx950) implementation of the
+ * per-step force-and-update loop of CUBE's two-level particle-mesh (PMPM)
+ * method on fixed-point-compressed particles (Cheng et al., arXiv:2003.03931).
+ *
+ * What one step computes (Sec. II and Sec. III-A of the paper):
+ *   decode the 1-byte cell-relative position offsets (Eq. (2)) of particles
+ *   stored cell-ordered with a per-cell count; deposit mass by cloud-in-cell
+ *   onto one global periodic coarse mesh and onto the fine mesh of every tile
+ *   (tile plus buffer); solve Poisson on each mesh by FFT, Green's-function
+ *   multiply and inverse FFT (Eq. (1) with the force-split kernels);
+ *   difference the potentials, interpolate the force back to the particles,
+ *   kick and requantise the 1-byte velocities, drift and requantise the
+ *   1-byte positions, then recount and stably compact the particles by cell.
+ *
+ * Conventions (units, codec details, Green's functions, integrator, order)
+ * are the readings listed with the library's design notes; in brief:
+ * lengths in mean inter-particle spacings, particle mass 1, lap(phi) = rho - 1,
+ * positions x = (256 n_c + m + 1/2) H / 256 (0-based n_c, H the coarse cell
+ * size), velocities v = u * s with int8 u and a power-of-two scale s per box,
+ * kick-drift leapfrog, canonical cell order tile-major then x-fastest.
+ *
+ * Every entry point returns a cube_status (0 == CUBE_OK); no C++ exception
+ * crosses this boundary.  cube_last_error() returns a thread-local message
+ * describing the last failure on the calling thread.  All device work is
+ * enqueued on the stream given to cube_init.  A context is used by one host
+ * thread at a time.
+ */
+#ifndef CUBE_H
+#define CUBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CUBE_OK = 0,
+    CUBE_INVALID = 1,      /* bad descriptor, geometry or argument; ctx unchanged     */
+    CUBE_OOM = 2,          /* device allocation failed; ctx unchanged                 */
+    CUBE_DEVICE = 3,       /* HIP runtime error; ctx is poisoned (only destroy valid) */
+    CUBE_NOT_READY = 4,    /* reserved for asynchronous queries                       */
+    CUBE_OVERFLOW = 5,     /* an exact accumulator would overflow                     */
+    CUBE_UNSUPPORTED = 6   /* mesh side not factorable by the FFT radices             */
+} cube_status;
+
+typedef enum {
+    CUBE_FP32 = 0          /* FP32 meshes and force (the only precision built)        */
+} cube_precision;
+
+/*
+ * Box geometry (Sec. II: coarse mesh, tiles with buffers; Sec. III-A: the
+ * coarse mesh also defines the position codec).
+ *   n_side            particles per dimension; box side L = n_side spacings.
+ *   tiles_per_dim     n_t; the fine meshes are per tile.  1 = one periodic tile.
+ *   fine_per_spacing  f, fine cells per spacing (power of two).
+ *   coarse_ratio      r, fine cells per coarse cell (power of two, 2..16).
+ *   buffer_fine       b, tile buffer in fine cells (multiple of r; 0 if n_t == 1).
+ *   r_cut_fine        a, force-split radius in fine cells; needs a <= b - 3
+ *                     (n_t > 1) or 2a < tile side (n_t == 1).
+ *   dt                time step (units of the dynamical time).
+ *   v_headroom        h_v >= 1, velocity-scale headroom (2 is the default).
+ *   precision         cube_precision.
+ *   with_ids          nonzero: carry a uint32 particle id plane (tests only; not
+ *                     part of the 6 bytes per particle).
+ *   tiles_per_batch   tiles whose fine meshes are in flight at once (0 = auto).
+ * Derived: coarse cells per side N_c = n_side f / r, tile side T = n_side f / n_t
+ * fine cells, tile FFT box F = T + 2b; every FFT side must factor into 2,3,5,7.
+ */
+typedef struct {
+    int32_t n_side;
+    int32_t tiles_per_dim;
+    int32_t fine_per_spacing;
+    int32_t coarse_ratio;
+    int32_t buffer_fine;
+    int32_t r_cut_fine;
+    float dt;
+    float v_headroom;
+    int32_t precision;
+    int32_t with_ids;
+    int32_t tiles_per_batch;
+    int32_t reserved;
+} cube_box_desc;
+
+typedef struct cube_ctx cube_ctx;
+
+/*
+ * Caller-owned buffers describing a compressed state (Sec. III-A: six 1-byte
+ * integers per particle plus the per-cell counts).  Used by cube_get_state
+ * (library copies out) and cube_set_state (library copies in).
+ *   m[3]      uint8 position offsets per axis, n_particles each, canonical order.
+ *   u[3]      int8 velocity codes per axis, n_particles each.
+ *   counts    int32 particle count per coarse cell, N_c^3 entries, canonical
+ *             cell order (tile-major, tile index x-fastest; x-fastest inside).
+ *   ids       uint32 ids (only with with_ids; may be NULL otherwise).
+ *   s_v       velocity scale (a power of two), M_u = max |u| of the stored u,
+ *             step = number of steps taken.
+ *   on_device nonzero: the pointers are device pointers, else host pointers.
+ */
+typedef struct {
+    int64_t n_particles;
+    int64_t n_cells;
+    uint8_t* m[3];
+    int8_t* u[3];
+    int32_t* counts;
+    uint32_t* ids;
+    double s_v;
+    int32_t max_u;
+    int32_t on_device;
+    int64_t step;
+} cube_state_view;
+
+/* FP64 diagnostics of the current state (mass and momentum sums, energies)
+ * plus counters accumulated by cube_pm_step. */
+typedef struct {
+    int64_t mass;              /* sum of counts (exact)                              */
+    double momentum[3];        /* sum of decoded velocities, FP64                    */
+    double kinetic;            /* 1/2 sum v^2, FP64                                  */
+    double potential;          /* 1/2 sum phi(x_i), FP64 sum of FP32 potentials      */
+    int64_t saturations;       /* velocity components clamped to +-127 so far        */
+    int32_t max_carry;         /* largest |cell carry| of the last step              */
+    int32_t max_u;             /* max |u| of the state                               */
+    double s_v;                /* velocity scale of the state                        */
+    int64_t step;              /* steps taken                                        */
+    double last_step_ms;       /* host wall time of the last cube_pm_step call / step */
+} cube_diag;
+
+/* Thread-local description of the last failure (empty if none). */
+const char* cube_last_error(void);
+
+/* Create a context for one box: validates the geometry, allocates the state,
+ * the meshes and the workspace with hipMalloc on the current device, builds
+ * the FFT twiddles (FP64-derived) and the Green's tables (FP64).  hip_stream
+ * is a hipStream_t (NULL = the default stream).  The state starts empty (all
+ * counts zero) until cube_compress or cube_set_state.  Errors: CUBE_INVALID,
+ * CUBE_UNSUPPORTED, CUBE_OOM, CUBE_DEVICE. */
+cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** out);
+
+/* Free everything owned by the context (NULL is ignored). */
+void cube_destroy(cube_ctx* ctx);
+
+/* Encode float positions/velocities of n = n_side^3 particles in any order
+ * into the compressed state (Eq. (2); velocity scale from the maximum speed
+ * with the headroom).  pos[i*3+k] in spacings (wrapped periodically), vel in
+ * spacings per unit time.  on_device: pointers are device (else host) memory.
+ * Particles are ordered by canonical cell, stably with respect to the input
+ * order; ids (if enabled) are the input indices.  Synchronises the stream. */
+cube_status cube_compress(cube_ctx* ctx, const float* pos, const float* vel,
+                          int64_t n, int32_t on_device);
+
+/* Decode the state to float positions/velocities in canonical order (exact:
+ * bin centres and u * s).  Same layout as cube_compress.  Synchronises. */
+cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
+                            int32_t on_device);
+
+/* Advance the state by nsteps kick-drift steps.  Enqueued on the context
+ * stream; returns after the last step's completion flag is read back (one
+ * small device-to-host copy per step).  CUBE_OVERFLOW if an exact fixed-point
+ * accumulator would overflow (the state is then the one before that step). */
+cube_status cube_pm_step(cube_ctx* ctx, int32_t nsteps);
+
+/* Acceleration of every particle at the current state, no update.
+ * acc[i*3+k], canonical order, float32.  Synchronises. */
+cube_status cube_forces(cube_ctx* ctx, float* acc, int32_t on_device);
+
+/* Copy the state out to / in from caller buffers (see cube_state_view).
+ * set_state validates that the counts sum to n_particles.  Synchronises. */
+cube_status cube_get_state(cube_ctx* ctx, cube_state_view* view);
+cube_status cube_set_state(cube_ctx* ctx, const cube_state_view* view);
+
+/* FP64 diagnostics (mass, momentum, kinetic and potential energy, counters).
+ * Synchronises. */
+cube_status cube_diagnostics(cube_ctx* ctx, cube_diag* out);
+
+/* Matter power spectrum of the current state: CIC on a mesh of one cell per
+ * spacing, delta = rho - 1, P = L^3 |DFT(delta)|^2 / N_cells^2 averaged over
+ * shells j = round(|n|), 1 <= j < n_side/4.  Host arrays of nbins entries
+ * (nbins must be n_side/4 - 1).  Synchronises. */
+cube_status cube_power_spectrum(cube_ctx* ctx, int32_t nbins, double* k,
+                                double* pk, int64_t* nmodes);
+
+/* Test hook: write an intermediate mesh of the current state into a caller
+ * device buffer of float32.  what: 0 coarse density rho_c - 1 (N_c^3),
+ * 1 coarse potential (N_c^3), 2 fine density of tile `tile` (F^3),
+ * 3 fine potential of tile `tile` (F^3).  Layout [z][y][x], x fastest. */
+cube_status cube_debug_mesh(cube_ctx* ctx, int32_t what, int32_t tile, float* out);
+
+/* Utility: in-place unnormalised 3-D complex FFT of an n^3 interleaved
+ * (re, im) float32 device array, [z][y][x] layout, sign -1 (inverse = 0) or
+ * +1 (inverse = 1), using the library's LDS Stockham kernels.  n must factor
+ * into the supported radices (CUBE_UNSUPPORTED otherwise).  hip_stream may be
+ * NULL.  Synchronises. */
+cube_status cube_fft3d(int32_t n, float* data, int32_t inverse, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUBE_H */

@@ -1,0 +1,114 @@
+"""ctypes binding of libcube.so (the C ABI declared in include/cube.h).
+
+Argument marshalling only: every stage of the particle-mesh step runs in the
+library's HIP kernels.  Importing this module fails loudly if the shared
+library has not been built; there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcube.so")
+
+CUBE_OK = 0
+STATUS = {0: "OK", 1: "INVALID", 2: "OOM", 3: "DEVICE", 4: "NOT_READY", 5: "OVERFLOW", 6: "UNSUPPORTED"}
+
+
+class CubeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cube status {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BoxDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_side", ctypes.c_int32),
+        ("tiles_per_dim", ctypes.c_int32),
+        ("fine_per_spacing", ctypes.c_int32),
+        ("coarse_ratio", ctypes.c_int32),
+        ("buffer_fine", ctypes.c_int32),
+        ("r_cut_fine", ctypes.c_int32),
+        ("dt", ctypes.c_float),
+        ("v_headroom", ctypes.c_float),
+        ("precision", ctypes.c_int32),
+        ("with_ids", ctypes.c_int32),
+        ("tiles_per_batch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class StateView(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int64),
+        ("n_cells", ctypes.c_int64),
+        ("m", ctypes.c_void_p * 3),
+        ("u", ctypes.c_void_p * 3),
+        ("counts", ctypes.c_void_p),
+        ("ids", ctypes.c_void_p),
+        ("s_v", ctypes.c_double),
+        ("max_u", ctypes.c_int32),
+        ("on_device", ctypes.c_int32),
+        ("step", ctypes.c_int64),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_int64),
+        ("momentum", ctypes.c_double * 3),
+        ("kinetic", ctypes.c_double),
+        ("potential", ctypes.c_double),
+        ("saturations", ctypes.c_int64),
+        ("max_carry", ctypes.c_int32),
+        ("max_u", ctypes.c_int32),
+        ("s_v", ctypes.c_double),
+        ("step", ctypes.c_int64),
+        ("last_step_ms", ctypes.c_double),
+    ]
+
+
+# exported symbol -> (restype, argtypes); mirrors include/cube.h
+SIGNATURES = {
+    "cube_last_error": (ctypes.c_char_p, []),
+    "cube_init": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_destroy": (None, [ctypes.c_void_p]),
+    "cube_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int32]),
+    "cube_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_int32]),
+    "cube_pm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cube_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "cube_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StateView)]),
+    "cube_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StateView)]),
+    "cube_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
+    "cube_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "cube_debug_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "cube_fft3d": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libcube.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != CUBE_OK:
+        msg = load().cube_last_error()
+        raise CubeError(status, msg.decode() if msg else "")

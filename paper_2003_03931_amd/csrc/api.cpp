@@ -1,0 +1,736 @@
+// C ABI of libcube.so: context lifetime, device memory, and the order of the
+// kernels in one particle-mesh step (Sec. II two-level PM on the compressed
+// particles of Sec. III-A).
+//
+// Step order (every stage is a HIP kernel on the context stream):
+//   prologue (velocity scale for the coming kick)
+//   clear new counts
+//   coarse deposit -> coarse FFT / x G_c / inverse FFT           (global mesh)
+//   for each batch of tiles (fine meshes in flight):
+//       fine deposit -> fine FFT / x G_f / inverse FFT -> gather+kick+drift+count
+//   scan new counts -> new offsets
+//   compaction (fast pull path, or the sorted general path)
+//   epilogue (commit scale and max|u|), swap counts/offsets
+// Particle buffers: A holds the state; the update writes B at the same index;
+// compaction moves B back into A in the new order.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cube.h"
+#include "internal.h"
+
+using namespace cube;
+
+namespace {
+
+thread_local std::string g_err;
+
+cube_status fail(cube_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define CUBE_HIP(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            return fail(CUBE_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+        }                                                                                      \
+    } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct cube_ctx {
+    Geom g{};
+    cube_box_desc desc{};
+    hipStream_t stream = nullptr;
+    bool poisoned = false;
+    bool has_state = false;
+    std::vector<void*> allocs;
+
+    Planes A{}, B{};
+    uint8_t* dir = nullptr;
+    uint32_t* far_key = nullptr;
+    int32_t* counts = nullptr;
+    int32_t* offsets = nullptr;
+    int32_t* counts_new = nullptr;
+    int32_t* offsets_new = nullptr;
+    StepScalars* sc = nullptr;
+    StepScalars* sc_host = nullptr;   // pinned
+
+    float2* coarse = nullptr;
+    double* coarse_green = nullptr;
+    float2* tw_coarse = nullptr;
+    float* fine_pairs = nullptr;
+    float* fine_green = nullptr;
+    float2* tw_fine = nullptr;
+    void* scan_ws = nullptr;
+    double* partial = nullptr;
+    int64_t partial_len = 0;
+    double* reduced = nullptr;
+    int batch = 1;
+
+    int64_t step = 0;
+    double last_step_ms = 0.0;
+
+    ~cube_ctx() {
+        if (sc_host) hipHostFree(sc_host);
+        for (void* p : allocs) hipFree(p);
+    }
+
+    cube_status alloc(void** p, size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CUBE_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                      hipGetErrorString(e));
+        }
+        allocs.push_back(*p);
+        return CUBE_OK;
+    }
+    template <class T>
+    cube_status alloc_n(T** p, int64_t n) {
+        return alloc(reinterpret_cast<void**>(p), (size_t)n * sizeof(T));
+    }
+};
+
+namespace {
+
+cube_status validate(const cube_box_desc* d, Geom* out) {
+    if (!d) return fail(CUBE_INVALID, "null descriptor");
+    Geom g{};
+    g.ns = d->n_side;
+    g.f = d->fine_per_spacing;
+    g.r = d->coarse_ratio;
+    g.nt = d->tiles_per_dim;
+    g.b = d->buffer_fine;
+    g.a = d->r_cut_fine;
+    if (g.ns <= 0 || g.nt <= 0 || g.a <= 0) return fail(CUBE_INVALID, "sizes must be positive");
+    if (!is_pow2(g.f) || !is_pow2(g.r) || g.r < 2 || g.r > 16 || g.r < g.f)
+        return fail(CUBE_INVALID, "fine_per_spacing and coarse_ratio must be powers of two, 2 <= r <= 16, r >= f");
+    const int64_t nfine = (int64_t)g.ns * g.f;
+    if (nfine % g.r || nfine % g.nt) return fail(CUBE_INVALID, "n_side*f must be divisible by r and n_t");
+    g.Nc = (int)(nfine / g.r);
+    g.T = (int)(nfine / g.nt);
+    if (g.T % g.r) return fail(CUBE_INVALID, "tile side must be a multiple of r");
+    g.Tc = g.T / g.r;
+    if (g.b % g.r) return fail(CUBE_INVALID, "buffer must be a multiple of r");
+    if (g.nt == 1) {
+        if (g.b != 0) return fail(CUBE_INVALID, "a single periodic tile has no buffer");
+        if (2 * g.a >= g.T) return fail(CUBE_INVALID, "r_cut must be below half the box");
+        g.F = g.T;
+        g.periodic = 1;
+    } else {
+        if (g.a > g.b - 3) return fail(CUBE_INVALID, "tiles need r_cut <= buffer - 3");
+        g.F = g.T + 2 * g.b;
+        g.periodic = 0;
+        if (g.F / g.r > g.Nc) return fail(CUBE_INVALID, "tile box larger than the periodic box");
+    }
+    g.Fc = g.F / g.r;
+    g.hc = g.b / g.r;
+    g.log2D = 9 - ilog2(g.r);
+    g.ncells = (int64_t)g.Nc * g.Nc * g.Nc;
+    g.n = (int64_t)g.ns * g.ns * g.ns;
+    g.ntiles = g.nt * g.nt * g.nt;
+    if (g.n >= (int64_t)1 << 31) return fail(CUBE_INVALID, "more than 2^31 - 1 particles");
+    if (g.Nc % 4 || g.Nc < 10) return fail(CUBE_INVALID, "coarse mesh side must be a multiple of 4 and >= 12");
+    if (!fft_supported(g.Nc) || !fft_supported(g.F))
+        return fail(CUBE_UNSUPPORTED, "mesh side not supported by the FFT radix plans");
+    if (!(d->dt > 0.0f) || !(d->v_headroom >= 1.0f)) return fail(CUBE_INVALID, "need dt > 0 and v_headroom >= 1");
+    if (d->precision != CUBE_FP32) return fail(CUBE_UNSUPPORTED, "only the FP32 precision is built");
+    *out = g;
+    return CUBE_OK;
+}
+
+cube_status check_ctx(cube_ctx* c) {
+    if (!c) return fail(CUBE_INVALID, "null context");
+    if (c->poisoned) return fail(CUBE_DEVICE, "context poisoned by an earlier device error");
+    return CUBE_OK;
+}
+
+cube_status launch_status(cube_ctx* c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return fail(CUBE_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return CUBE_OK;
+}
+
+cube_status sync(cube_ctx* c) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return fail(CUBE_DEVICE, std::string("stream: ") + hipGetErrorString(e));
+    }
+    return launch_status(c);
+}
+
+// coarse potential into ctx->coarse (real part)
+void coarse_potential(cube_ctx* c) {
+    const Geom& g = c->g;
+    launch_coarse_deposit(g, c->offsets, c->A, c->coarse, nullptr, c->stream);
+    fft3d_convolve(c->coarse, g.Nc, 1, c->tw_coarse, c->coarse_green, 1, c->stream);
+}
+
+// fine potentials of tiles [t0, t0 + nt) into ctx->fine_pairs
+void fine_potential(cube_ctx* c, int t0, int nt) {
+    const Geom& g = c->g;
+    const int pairs = (nt + 1) / 2;
+    if (nt & 1) {
+        // the last pair carries one tile: its other lane must be finite (zero)
+        const int64_t cube3 = (int64_t)g.F * g.F * g.F;
+        hipMemsetAsync(c->fine_pairs + (int64_t)(pairs - 1) * 2 * cube3, 0, 2 * cube3 * sizeof(float), c->stream);
+    }
+    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_pairs, nullptr, c->stream);
+    fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0, c->stream);
+}
+
+GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
+    GatherArgs a{};
+    a.g = c->g;
+    a.offsets = c->offsets;
+    a.in = c->A;
+    a.out = c->B;
+    a.dir = c->dir;
+    a.far_key = c->far_key;
+    a.counts_new = c->counts_new;
+    a.fine_pairs = c->fine_pairs;
+    a.coarse = c->coarse;
+    a.sc = c->sc;
+    a.dt = c->desc.dt;
+    a.tile0 = t0;
+    a.ntiles = nt;
+    a.mode = mode;
+    return a;
+}
+
+cube_status ensure_partial(cube_ctx* c, int64_t n) {
+    if (c->partial_len >= n) return CUBE_OK;
+    double* p = nullptr;
+    cube_status st = c->alloc_n(&p, n);
+    if (st != CUBE_OK) return st;
+    c->partial = p;
+    c->partial_len = n;
+    return CUBE_OK;
+}
+
+cube_status run_step(cube_ctx* c) {
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    launch_step_prologue(c->sc, c->desc.v_headroom, s);
+    launch_fill_i32(c->counts_new, 0, g.ncells, s);
+    coarse_potential(c);
+    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+        const int nt = std::min(c->batch, g.ntiles - t0);
+        fine_potential(c, t0, nt);
+        GatherArgs a = gather_args(c, GATHER_STEP, t0, nt);
+        launch_gather(a, s);
+    }
+    exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s);
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
+    cube_status st = sync(c);
+    if (st != CUBE_OK) return st;
+    if (c->sc_host->far_count == 0) {
+        launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, c->B, c->A, s);
+    } else {
+        // general path: stable sort of the new keys (temporary buffers)
+        uint32_t *key = nullptr, *idx = nullptr, *kt = nullptr, *it = nullptr;
+        void* ws = nullptr;
+        std::vector<void*> tmp;
+        auto grab = [&](void** p, size_t bytes) -> hipError_t {
+            hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+            if (e == hipSuccess) tmp.push_back(*p);
+            return e;
+        };
+        const size_t nb = (size_t)g.n * sizeof(uint32_t);
+        if (grab((void**)&key, nb) != hipSuccess || grab((void**)&idx, nb) != hipSuccess ||
+            grab((void**)&kt, nb) != hipSuccess || grab((void**)&it, nb) != hipSuccess ||
+            grab(&ws, sort_workspace_bytes(g.n)) != hipSuccess) {
+            for (void* p : tmp) hipFree(p);
+            (void)hipGetLastError();
+            return fail(CUBE_OOM, "general compaction: out of memory");
+        }
+        launch_general_keys(g, c->offsets, c->dir, c->far_key, key, idx, s);
+        stable_sort_pairs(key, idx, kt, it, g.n, ilog2((int)std::min<int64_t>(g.ncells, 1 << 30)) + 1, ws, s);
+        launch_permute_planes(idx, c->B, c->A, g.n, s);
+        st = sync(c);
+        for (void* p : tmp) hipFree(p);
+        if (st != CUBE_OK) return st;
+    }
+    launch_step_epilogue(c->sc, s);
+    std::swap(c->counts, c->counts_new);
+    std::swap(c->offsets, c->offsets_new);
+    c->step += 1;
+    return launch_status(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cube_last_error(void) { return g_err.c_str(); }
+
+cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** out) {
+    if (!out) return fail(CUBE_INVALID, "null output pointer");
+    *out = nullptr;
+    Geom g;
+    cube_status st = validate(desc, &g);
+    if (st != CUBE_OK) return st;
+    cube_ctx* c = new (std::nothrow) cube_ctx();
+    if (!c) return fail(CUBE_OOM, "host allocation failed");
+    c->g = g;
+    c->desc = *desc;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = g.n;
+    int batch = desc->tiles_per_batch > 0 ? desc->tiles_per_batch : 64;
+    batch = std::min(batch, g.ntiles);
+    c->batch = std::max(1, batch);
+
+#define CUBE_TRY(x)              \
+    do {                         \
+        cube_status s_ = (x);    \
+        if (s_ != CUBE_OK) {     \
+            delete c;            \
+            return s_;           \
+        }                        \
+    } while (0)
+
+    uint8_t* planes = nullptr;
+    CUBE_TRY(c->alloc_n(&planes, 12 * n));
+    for (int k = 0; k < 3; ++k) {
+        c->A.m[k] = planes + k * n;
+        c->A.u[k] = reinterpret_cast<int8_t*>(planes + (3 + k) * n);
+        c->B.m[k] = planes + (6 + k) * n;
+        c->B.u[k] = reinterpret_cast<int8_t*>(planes + (9 + k) * n);
+    }
+    if (desc->with_ids) {
+        CUBE_TRY(c->alloc_n(&c->A.ids, n));
+        CUBE_TRY(c->alloc_n(&c->B.ids, n));
+    }
+    CUBE_TRY(c->alloc_n(&c->dir, n));
+    CUBE_TRY(c->alloc_n(&c->far_key, n));
+    CUBE_TRY(c->alloc_n(&c->counts, g.ncells + 16));
+    CUBE_TRY(c->alloc_n(&c->offsets, g.ncells + 16));
+    CUBE_TRY(c->alloc_n(&c->counts_new, g.ncells + 16));
+    CUBE_TRY(c->alloc_n(&c->offsets_new, g.ncells + 16));
+    CUBE_TRY(c->alloc_n(&c->sc, 1));
+    CUBE_TRY(c->alloc(&c->scan_ws, scan_workspace_bytes(g.ncells + 16)));
+    CUBE_TRY(c->alloc_n(&c->coarse, g.ncells));
+    const int64_t Mc = g.Nc / 2 + 1, Mf = g.F / 2 + 1;
+    CUBE_TRY(c->alloc_n(&c->coarse_green, Mc * Mc * Mc));
+    CUBE_TRY(c->alloc_n(&c->tw_coarse, g.Nc));
+    const int64_t fcube = (int64_t)g.F * g.F * g.F;
+    CUBE_TRY(c->alloc_n(&c->fine_pairs, (int64_t)((c->batch + 1) / 2) * 2 * fcube));
+    CUBE_TRY(c->alloc_n(&c->fine_green, Mf * Mf * Mf));
+    CUBE_TRY(c->alloc_n(&c->tw_fine, g.F));
+    CUBE_TRY(c->alloc_n(&c->reduced, 64));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), sizeof(StepScalars)) != hipSuccess) {
+        c->sc_host = nullptr;
+        delete c;
+        return fail(CUBE_OOM, "pinned host allocation failed");
+    }
+    std::memset(c->sc_host, 0, sizeof(StepScalars));
+    c->sc_host->s = 1.0;
+    void* gws = nullptr;
+    CUBE_TRY(c->alloc(&gws, fine_green_workspace_bytes(g)));
+
+    // empty state, tables, twiddles
+    hipStream_t s = c->stream;
+    launch_fill_i32(c->counts, 0, g.ncells + 16, s);
+    launch_fill_i32(c->offsets, 0, g.ncells + 16, s);
+    if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s) != hipSuccess) {
+        delete c;
+        return fail(CUBE_DEVICE, "initial scalar copy failed");
+    }
+    build_coarse_green(g, c->coarse_green, s);
+    build_fine_green(g, c->fine_green, gws, s);
+    fft_make_twiddles(g.Nc, c->tw_coarse, s);
+    fft_make_twiddles(g.F, c->tw_fine, s);
+    if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+        delete c;
+        return fail(CUBE_DEVICE, "initialisation kernels failed");
+    }
+#undef CUBE_TRY
+    *out = c;
+    return CUBE_OK;
+}
+
+void cube_destroy(cube_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64_t n, int32_t on_device) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    if (n != g.n || !pos || !vel) return fail(CUBE_INVALID, "compress needs n_side^3 particles");
+    hipStream_t s = c->stream;
+    std::vector<void*> tmp;
+    auto grab = [&](void** p, size_t bytes) -> bool {
+        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        tmp.push_back(*p);
+        return true;
+    };
+    auto release = [&]() {
+        for (void* p : tmp) hipFree(p);
+        tmp.clear();
+    };
+    const float* dpos = pos;
+    const float* dvel = vel;
+    float *hp = nullptr, *hv = nullptr;
+    uint32_t *key = nullptr, *idx = nullptr, *kt = nullptr, *it = nullptr, *qp = nullptr, *vmax = nullptr;
+    void* ws = nullptr;
+    const size_t fb = (size_t)n * 3 * sizeof(float), ub = (size_t)n * sizeof(uint32_t);
+    if (!on_device) {
+        if (!grab((void**)&hp, fb) || !grab((void**)&hv, fb)) {
+            release();
+            return fail(CUBE_OOM, "compress: staging allocation failed");
+        }
+        if (hipMemcpyAsync(hp, pos, fb, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(hv, vel, fb, hipMemcpyHostToDevice, s) != hipSuccess) {
+            release();
+            c->poisoned = true;
+            return fail(CUBE_DEVICE, "compress: upload failed");
+        }
+        dpos = hp;
+        dvel = hv;
+    }
+    if (!grab((void**)&key, ub) || !grab((void**)&idx, ub) || !grab((void**)&kt, ub) || !grab((void**)&it, ub) ||
+        !grab((void**)&qp, ub) || !grab((void**)&vmax, 256) || !grab(&ws, sort_workspace_bytes(n))) {
+        release();
+        return fail(CUBE_OOM, "compress: workspace allocation failed");
+    }
+    launch_encode_keys(g, dpos, key, qp, idx, n, s);
+    hipMemsetAsync(vmax, 0, sizeof(uint32_t), s);
+    launch_absmax_f32(dvel, 3 * n, vmax, s);
+    uint32_t vbits = 0;
+    hipMemcpyAsync(&vbits, vmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    st = sync(c);
+    if (st != CUBE_OK) {
+        release();
+        return st;
+    }
+    float vmaxf;
+    std::memcpy(&vmaxf, &vbits, sizeof(float));
+    double s0 = 1.0;
+    if (vmaxf > 0.0f) {
+        const double x = (double)c->desc.v_headroom * (double)vmaxf / 127.0;
+        int e;
+        const double m = std::frexp(x, &e);
+        s0 = (m == 0.5) ? std::ldexp(1.0, e - 1) : std::ldexp(1.0, e);
+    }
+    int bits = ilog2((int)std::min<int64_t>(g.ncells, (int64_t)1 << 30));
+    if (((int64_t)1 << bits) < g.ncells) ++bits;
+    if (bits < 1) bits = 1;
+    stable_sort_pairs(key, idx, kt, it, n, bits, ws, s);
+    launch_fill_i32(c->counts, 0, g.ncells + 16, s);
+    launch_count_keys(key, n, c->counts, s);
+    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s);
+    StepScalars init{};
+    init.s = s0;
+    init.s_next = s0;
+    *c->sc_host = init;
+    hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s);
+    launch_scatter_compressed(g, idx, qp, dvel, s0, c->A, c->counts, c->sc, n, s);
+    st = sync(c);
+    release();
+    if (st != CUBE_OK) return st;
+    c->has_state = true;
+    c->step = 0;
+    return CUBE_OK;
+}
+
+cube_status cube_decompress(cube_ctx* c, float* pos, float* vel, int64_t n, int32_t on_device) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    if (n != g.n || !pos || !vel) return fail(CUBE_INVALID, "decompress needs n_side^3 particles");
+    hipStream_t s = c->stream;
+    float *dp = pos, *dv = vel;
+    const size_t fb = (size_t)n * 3 * sizeof(float);
+    if (!on_device) {
+        if (hipMalloc(&dp, fb) != hipSuccess) return fail(CUBE_OOM, "decompress staging");
+        if (hipMalloc(&dv, fb) != hipSuccess) {
+            hipFree(dp);
+            return fail(CUBE_OOM, "decompress staging");
+        }
+    }
+    launch_decode(g, c->offsets, c->A, c->sc, dp, dv, s);
+    if (!on_device) {
+        hipMemcpyAsync(pos, dp, fb, hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(vel, dv, fb, hipMemcpyDeviceToHost, s);
+    }
+    st = sync(c);
+    if (!on_device) {
+        hipFree(dp);
+        hipFree(dv);
+    }
+    return st;
+}
+
+cube_status cube_pm_step(cube_ctx* c, int32_t nsteps) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (nsteps < 0) return fail(CUBE_INVALID, "negative step count");
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < nsteps; ++i) {
+        st = run_step(c);
+        if (st != CUBE_OK) return st;
+    }
+    st = sync(c);
+    auto t1 = std::chrono::steady_clock::now();
+    if (nsteps > 0) c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
+    return st;
+}
+
+cube_status cube_forces(cube_ctx* c, float* acc, int32_t on_device) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (!acc) return fail(CUBE_INVALID, "null output");
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    float* dacc = acc;
+    const size_t bytes = (size_t)g.n * 3 * sizeof(float);
+    if (!on_device && hipMalloc(&dacc, bytes) != hipSuccess) return fail(CUBE_OOM, "forces staging");
+    coarse_potential(c);
+    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+        const int nt = std::min(c->batch, g.ntiles - t0);
+        fine_potential(c, t0, nt);
+        GatherArgs a = gather_args(c, GATHER_FORCE, t0, nt);
+        a.acc = dacc;
+        launch_gather(a, s);
+    }
+    if (!on_device) hipMemcpyAsync(acc, dacc, bytes, hipMemcpyDeviceToHost, s);
+    st = sync(c);
+    if (!on_device) hipFree(dacc);
+    return st;
+}
+
+cube_status cube_get_state(cube_ctx* c, cube_state_view* v) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    if (!v || v->n_particles != g.n || v->n_cells != g.ncells) return fail(CUBE_INVALID, "state view size mismatch");
+    hipStream_t s = c->stream;
+    const hipMemcpyKind kind = v->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int k = 0; k < 3; ++k) {
+        if (v->m[k]) CUBE_HIP(hipMemcpyAsync(v->m[k], c->A.m[k], g.n, kind, s));
+        if (v->u[k]) CUBE_HIP(hipMemcpyAsync(v->u[k], c->A.u[k], g.n, kind, s));
+    }
+    if (v->counts) CUBE_HIP(hipMemcpyAsync(v->counts, c->counts, g.ncells * sizeof(int32_t), kind, s));
+    if (v->ids && c->A.ids) CUBE_HIP(hipMemcpyAsync(v->ids, c->A.ids, g.n * sizeof(uint32_t), kind, s));
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    v->s_v = c->sc_host->s;
+    v->max_u = c->sc_host->max_u;
+    v->step = c->step;
+    return CUBE_OK;
+}
+
+cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    if (!v || v->n_particles != g.n || v->n_cells != g.ncells || !v->counts)
+        return fail(CUBE_INVALID, "state view size mismatch");
+    if (!(v->s_v > 0.0) || v->max_u < 0 || v->max_u > 127) return fail(CUBE_INVALID, "bad velocity scale or max_u");
+    for (int k = 0; k < 3; ++k)
+        if (!v->m[k] || !v->u[k]) return fail(CUBE_INVALID, "missing planes");
+    hipStream_t s = c->stream;
+    const hipMemcpyKind kind = v->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int k = 0; k < 3; ++k) {
+        CUBE_HIP(hipMemcpyAsync(c->A.m[k], v->m[k], g.n, kind, s));
+        CUBE_HIP(hipMemcpyAsync(c->A.u[k], v->u[k], g.n, kind, s));
+    }
+    CUBE_HIP(hipMemcpyAsync(c->counts, v->counts, g.ncells * sizeof(int32_t), kind, s));
+    if (c->A.ids) {
+        if (v->ids) CUBE_HIP(hipMemcpyAsync(c->A.ids, v->ids, g.n * sizeof(uint32_t), kind, s));
+        else CUBE_HIP(hipMemsetAsync(c->A.ids, 0, g.n * sizeof(uint32_t), s));
+    }
+    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s);
+    StepScalars init{};
+    init.s = v->s_v;
+    init.s_next = v->s_v;
+    init.max_u = v->max_u;
+    *c->sc_host = init;
+    CUBE_HIP(hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s));
+    int32_t total = -1;
+    CUBE_HIP(hipMemcpyAsync(&total, c->offsets + g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    if (total != g.n) {
+        // never leave offsets that point past the particle arrays
+        launch_fill_i32(c->counts, 0, g.ncells + 16, s);
+        launch_fill_i32(c->offsets, 0, g.ncells + 16, s);
+        c->has_state = false;
+        sync(c);
+        return fail(CUBE_INVALID, "counts do not sum to n_particles");
+    }
+    c->has_state = true;
+    c->step = v->step;
+    return CUBE_OK;
+}
+
+cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (!out) return fail(CUBE_INVALID, "null output");
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    const int chunks = (int)(g.ncells / g.Tc);
+    const int64_t gather_blocks = (int64_t)g.Tc * g.Tc * c->batch;
+    st = ensure_partial(c, std::max<int64_t>(4 * (int64_t)chunks, gather_blocks));
+    if (st != CUBE_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    launch_moments(g, c->offsets, c->A, c->sc, c->partial, chunks, s);
+    launch_reduce_partials(c->partial, chunks, 4, c->reduced, s);
+    double mom[4];
+    CUBE_HIP(hipMemcpyAsync(mom, c->reduced, sizeof(mom), hipMemcpyDeviceToHost, s));
+    int32_t total = 0;
+    CUBE_HIP(hipMemcpyAsync(&total, c->offsets + g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    out->mass = total;
+    out->momentum[0] = mom[0];
+    out->momentum[1] = mom[1];
+    out->momentum[2] = mom[2];
+    out->kinetic = 0.5 * mom[3];
+    out->saturations = c->sc_host->saturations;
+    out->max_carry = c->sc_host->max_carry;
+    out->max_u = c->sc_host->max_u;
+    out->s_v = c->sc_host->s;
+    out->step = c->step;
+    out->last_step_ms = c->last_step_ms;
+    // potential energy: 1/2 sum over particles of phi_f + phi_c at their positions
+    coarse_potential(c);
+    double wsum = 0.0;
+    std::vector<double> part;
+    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+        const int nt = std::min(c->batch, g.ntiles - t0);
+        fine_potential(c, t0, nt);
+        GatherArgs a = gather_args(c, GATHER_POTENTIAL, t0, nt);
+        a.partial = c->partial;
+        launch_gather(a, s);
+        const int64_t np = (int64_t)g.Tc * g.Tc * nt;
+        part.resize(np);
+        CUBE_HIP(hipMemcpyAsync(part.data(), c->partial, np * sizeof(double), hipMemcpyDeviceToHost, s));
+        st = sync(c);
+        if (st != CUBE_OK) return st;
+        for (double v : part) wsum += v;
+    }
+    out->potential = 0.5 * wsum;
+    return CUBE_OK;
+}
+
+cube_status cube_power_spectrum(cube_ctx* c, int32_t nbins, double* k, double* pk, int64_t* nmodes) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    const int n = g.ns;
+    if (nbins != n / 4 - 1 || !k || !pk || !nmodes) return fail(CUBE_INVALID, "nbins must be n_side/4 - 1");
+    if (!fft_supported(n) || g.r < g.f) return fail(CUBE_UNSUPPORTED, "diagnostic mesh size not supported");
+    hipStream_t s = c->stream;
+    float2* mesh = nullptr;
+    float2* tw = nullptr;
+    double* part = nullptr;
+    const int64_t cells = (int64_t)n * n * n;
+    if (hipMalloc(&mesh, cells * sizeof(float2)) != hipSuccess) return fail(CUBE_OOM, "P(k) mesh");
+    if (hipMalloc(&tw, n * sizeof(float2)) != hipSuccess ||
+        hipMalloc(&part, (size_t)n * 3 * nbins * sizeof(double)) != hipSuccess) {
+        hipFree(mesh);
+        if (tw) hipFree(tw);
+        return fail(CUBE_OOM, "P(k) workspace");
+    }
+    fft_make_twiddles(n, tw, s);
+    launch_diag_deposit(g, c->offsets, c->A, mesh, s);
+    fft3d(mesh, n, 1, false, tw, s);
+    launch_power_bins(mesh, n, nbins, part, n, s);
+    std::vector<double> h((size_t)n * 3 * nbins);
+    hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    st = sync(c);
+    hipFree(mesh);
+    hipFree(tw);
+    hipFree(part);
+    if (st != CUBE_OK) return st;
+    for (int j = 0; j < nbins; ++j) {
+        double ps = 0.0, ks = 0.0, cs = 0.0;
+        for (int z = 0; z < n; ++z) {
+            ps += h[(size_t)z * 3 * nbins + j];
+            ks += h[(size_t)z * 3 * nbins + nbins + j];
+            cs += h[(size_t)z * 3 * nbins + 2 * nbins + j];
+        }
+        nmodes[j] = (int64_t)llround(cs);
+        pk[j] = cs > 0 ? ps / cs : 0.0;
+        k[j] = cs > 0 ? ks / cs : 0.0;
+    }
+    return CUBE_OK;
+}
+
+cube_status cube_debug_mesh(cube_ctx* c, int32_t what, int32_t tile, float* out) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    const Geom& g = c->g;
+    if (!out) return fail(CUBE_INVALID, "null output");
+    hipStream_t s = c->stream;
+    if (what == 0 || what == 1) {
+        if (what == 0) launch_coarse_deposit(g, c->offsets, c->A, c->coarse, nullptr, s);
+        else coarse_potential(c);
+        CUBE_HIP(hipMemcpy2DAsync(out, sizeof(float), c->coarse, sizeof(float2), sizeof(float), g.ncells,
+                                  hipMemcpyDeviceToDevice, s));
+    } else if (what == 2 || what == 3) {
+        if (tile < 0 || tile >= g.ntiles) return fail(CUBE_INVALID, "tile out of range");
+        const int64_t fcube = (int64_t)g.F * g.F * g.F;
+        if (what == 2) {
+            CUBE_HIP(hipMemsetAsync(c->fine_pairs, 0, 2 * fcube * sizeof(float), s));
+            launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_pairs, nullptr, s);
+        } else {
+            fine_potential(c, tile, 1);
+        }
+        CUBE_HIP(hipMemcpy2DAsync(out, sizeof(float), c->fine_pairs, 2 * sizeof(float), sizeof(float), fcube,
+                                  hipMemcpyDeviceToDevice, s));
+    } else {
+        return fail(CUBE_INVALID, "unknown mesh");
+    }
+    return sync(c);
+}
+
+cube_status cube_fft3d(int32_t n, float* data, int32_t inverse, void* hip_stream) {
+    if (!data) return fail(CUBE_INVALID, "null data");
+    if (!fft_supported(n)) return fail(CUBE_UNSUPPORTED, "size not supported by the radix plans");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    float2* tw = nullptr;
+    CUBE_HIP(hipMalloc(&tw, n * sizeof(float2)));
+    fft_make_twiddles(n, tw, s);
+    fft3d(reinterpret_cast<float2*>(data), n, 1, inverse != 0, tw, s);
+    hipError_t e = hipStreamSynchronize(s);
+    hipFree(tw);
+    if (e != hipSuccess) return fail(CUBE_DEVICE, hipGetErrorString(e));
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(CUBE_DEVICE, hipGetErrorString(e));
+    return CUBE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Device helpers shared by the kernels of libcube.so (wavefront-64 scans and
+// reductions, checked HIP launches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace cube {
+
+constexpr int kWave = 64;
+
+// Inclusive scan inside one 64-lane wavefront.
+__device__ inline int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the whole block (blockDim.x a multiple of 64, <= 1024).
+// lds needs blockDim.x / 64 + 1 ints.  Returns the exclusive prefix of v and
+// writes the block total to *total.
+__device__ inline int block_exclusive_scan(int v, int* lds, int* total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    int inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) lds[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            int t = lds[w];
+            lds[w] = acc;
+            acc += t;
+        }
+        lds[nw] = acc;
+    }
+    __syncthreads();
+    int res = inc - v + lds[wid];
+    *total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+inline unsigned grid1d(int64_t work, int per_block) {
+    int64_t b = (work + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace cube
+
+namespace cube {
+
+// A chunk is one x-row of coarse cells inside one tile: Tc consecutive cells
+// in canonical order, hence one contiguous particle range.
+struct Chunk {
+    int cx0, cy, cz;   // global coarse coords of the chunk's first cell
+    int64_t c0;        // canonical index of that cell
+    int tile;          // tile index
+    int ly, lz;        // tile-local row coordinates
+};
+
+__device__ inline Chunk chunk_of(const Geom& g, int64_t q) {
+    const int Tc = g.Tc;
+    const int64_t per_tile = (int64_t)Tc * Tc;
+    Chunk c;
+    c.tile = (int)(q / per_tile);
+    const int rem = (int)(q - (int64_t)c.tile * per_tile);
+    c.ly = rem % Tc;
+    c.lz = rem / Tc;
+    const int tx = c.tile % g.nt, ty = (c.tile / g.nt) % g.nt, tz = c.tile / (g.nt * g.nt);
+    c.cx0 = tx * Tc;
+    c.cy = ty * Tc + c.ly;
+    c.cz = tz * Tc + c.lz;
+    c.c0 = q * Tc;
+    return c;
+}
+
+// Index j with offs[j] <= p < offs[j+1] among offs[0..len] (offs[0] <= p < offs[len]).
+__device__ inline int find_cell(const int* offs, int len, int p) {
+    int lo = 0, hi = len;   // invariant offs[lo] <= p < offs[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (offs[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace cube

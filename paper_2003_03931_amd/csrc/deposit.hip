@@ -1,0 +1,197 @@
+// Cloud-in-cell mass assignment (Sec. II: density by interpolating particles
+// onto a mesh; the tile's fine mesh is the tile plus its buffer) on the
+// fixed-point positions of Eq. (2).
+//
+// Owner-computes: every workgroup owns a cube of target cells, pulls the
+// particles of the coarse cells that can reach it (its own plus one coarse
+// cell on each face) straight from the cell-ordered arrays, accumulates the
+// exact CIC weights in LDS as 64-bit integers and writes each target cell
+// once -- no global atomics, bit-reproducible.
+//
+// Exactness: a coordinate in target-cell units is P / D with P = 2(c 256 + m)+1
+// and D = 512 / (target cells per coarse cell), so every CIC weight is an
+// integer multiple of 1/D per axis and of 1/D^3 in 3-D.  The FP32 output is
+// round(acc / D^3 / cell_volume - 1), the single rounding of the exact value.
+#include "common.h"
+
+namespace cube {
+
+namespace {
+
+enum DepositMode { DEP_COARSE = 0, DEP_FINE_TILED = 1, DEP_FINE_PERIODIC = 2, DEP_DIAG = 3 };
+
+constexpr int kDepThreads = 256;
+constexpr int kMaxSrc = 1000;   // (BW / cpc + 2)^3 for the largest source window
+
+template <int BW, int MODE>
+__global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* __restrict__ offsets, Planes p,
+                                                          float* __restrict__ out, int M, int cpc, int log2D,
+                                                          double scale, int tile0) {
+    __shared__ unsigned long long acc[BW * BW * BW];
+    __shared__ int s_start[kMaxSrc];
+    __shared__ int s_pref[kMaxSrc + 1];
+    __shared__ int s_scan[kDepThreads / kWave + 1];
+
+    const int nbx = (M + BW - 1) / BW;
+    const int b = blockIdx.x;
+    const int T0[3] = {(b % nbx) * BW, ((b / nbx) % nbx) * BW, (b / (nbx * nbx)) * BW};
+    const int bw[3] = {min(BW, M - T0[0]), min(BW, M - T0[1]), min(BW, M - T0[2])};
+    int nsa[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nsa[k] = (bw[k] + cpc - 1) / cpc + 2;
+    const int nsrc = nsa[0] * nsa[1] * nsa[2];
+    // source frame origin (coarse cells): one cell before the block
+    const int S0[3] = {T0[0] / cpc - 1, T0[1] / cpc - 1, T0[2] / cpc - 1};
+
+    int tile = 0, box0[3] = {0, 0, 0};
+    if (MODE == DEP_FINE_TILED) {
+        tile = tile0 + blockIdx.y;
+        const int tx = tile % g.nt, ty = (tile / g.nt) % g.nt, tz = tile / (g.nt * g.nt);
+        box0[0] = tx * g.Tc - g.hc;
+        box0[1] = ty * g.Tc - g.hc;
+        box0[2] = tz * g.Tc - g.hc;
+    }
+
+    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) acc[i] = 0ull;
+
+    // per-thread run of up to 4 source cells: counts, then a block scan
+    constexpr int kPer = (kMaxSrc + kDepThreads - 1) / kDepThreads;
+    int my_cnt[kPer];
+    int run = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int s = threadIdx.x * kPer + q;
+        int cnt = 0;
+        if (s < nsrc) {
+            const int rx = s % nsa[0], ry = (s / nsa[0]) % nsa[1], rz = s / (nsa[0] * nsa[1]);
+            int fc[3] = {S0[0] + rx, S0[1] + ry, S0[2] + rz};
+            bool ok = true;
+            if (MODE == DEP_FINE_TILED) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    ok = ok && fc[k] >= 0 && fc[k] < g.Fc;
+                    fc[k] += box0[k];
+                }
+            }
+            if (ok) {
+                const int64_t c = canon(g, wrapi(fc[0], g.Nc), wrapi(fc[1], g.Nc), wrapi(fc[2], g.Nc));
+                const int st = offsets[c];
+                cnt = offsets[c + 1] - st;
+                s_start[s] = st;
+            } else {
+                s_start[s] = 0;
+            }
+        }
+        my_cnt[q] = cnt;
+        run += cnt;
+    }
+    int total;
+    int base = block_exclusive_scan(run, s_scan, &total);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int s = threadIdx.x * kPer + q;
+        if (s < nsrc) s_pref[s] = base;
+        base += my_cnt[q];
+    }
+    if (threadIdx.x == 0) s_pref[nsrc] = total;
+    __syncthreads();
+
+    const int D = 1 << log2D;
+    const int halfD = D >> 1;
+    for (int e = threadIdx.x; e < total; e += kDepThreads) {
+        const int s = find_cell(s_pref, nsrc, e);
+        const int pidx = s_start[s] + (e - s_pref[s]);
+        const int rel[3] = {s % nsa[0] - 1, (s / nsa[0]) % nsa[1] - 1, s / (nsa[0] * nsa[1]) - 1};
+        int i0[3];
+        unsigned w1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int P = 2 * (rel[k] * 256 + (int)p.m[k][pidx]) + 1;   // units of 1/D target cells
+            const int Pm = P - halfD;
+            i0[k] = Pm >> log2D;                                          // floor division
+            w1[k] = (unsigned)(Pm & (D - 1));
+        }
+#pragma unroll
+        for (int oz = 0; oz < 2; ++oz) {
+            const int iz = i0[2] + oz;
+            if (iz < 0 || iz >= bw[2]) continue;
+            const unsigned wz = oz ? w1[2] : (unsigned)D - w1[2];
+#pragma unroll
+            for (int oy = 0; oy < 2; ++oy) {
+                const int iy = i0[1] + oy;
+                if (iy < 0 || iy >= bw[1]) continue;
+                const unsigned wyz = (oy ? w1[1] : (unsigned)D - w1[1]) * wz;
+#pragma unroll
+                for (int ox = 0; ox < 2; ++ox) {
+                    const int ix = i0[0] + ox;
+                    if (ix < 0 || ix >= bw[0]) continue;
+                    const unsigned long long w =
+                        (unsigned long long)(ox ? w1[0] : (unsigned)D - w1[0]) * (unsigned long long)wyz;
+                    if (w) atomicAdd(&acc[(iz * BW + iy) * BW + ix], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // exact value * scale - 1, rounded once to FP32
+    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) {
+        const int ix = i % BW, iy = (i / BW) % BW, iz = i / (BW * BW);
+        if (ix >= bw[0] || iy >= bw[1] || iz >= bw[2]) continue;
+        const float v = (float)((double)acc[i] * scale - 1.0);
+        const int64_t cell = (int64_t)(T0[0] + ix) + (int64_t)M * ((T0[1] + iy) + (int64_t)M * (T0[2] + iz));
+        if (MODE == DEP_FINE_TILED || MODE == DEP_FINE_PERIODIC) {
+            const int k = blockIdx.y;          // tile in batch: pair k/2, lane k%2
+            float* mesh = out + (int64_t)(k >> 1) * 2 * (int64_t)M * M * M;
+            mesh[2 * cell + (k & 1)] = v;
+        } else {
+            out[2 * cell] = v;
+            out[2 * cell + 1] = 0.0f;
+        }
+    }
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, int32_t* /*overflow*/,
+                           hipStream_t s) {
+    constexpr int BW = 8;
+    const int nb = (g.Nc + BW - 1) / BW;
+    // acc in units of 2^-27 particle; density = mass / H^3 with H = r / f
+    const double scale = std::ldexp(1.0, -27) * ((double)g.f * g.f * g.f) / ((double)g.r * g.r * g.r);
+    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s, g, offsets, p,
+                       reinterpret_cast<float*>(mesh), g.Nc, 1, 9, scale, 0);
+}
+
+void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
+                         float* pair_mesh, int32_t* /*overflow*/, hipStream_t s) {
+    constexpr int BW = 16;
+    const int nb = (g.F + BW - 1) / BW;
+    const int log2D = g.log2D;
+    // acc in units of D^-3 fine-cell masses; density = mass / h^3 = mass * f^3
+    const double scale = std::ldexp(1.0, -3 * log2D) * ((double)g.f * g.f * g.f);
+    if (g.periodic)
+        hipLaunchKernelGGL((k_deposit<BW, DEP_FINE_PERIODIC>), dim3(nb * nb * nb, ntiles), dim3(kDepThreads), 0,
+                           s, g, offsets, p, pair_mesh, g.F, g.r, log2D, scale, tile0);
+    else
+        hipLaunchKernelGGL((k_deposit<BW, DEP_FINE_TILED>), dim3(nb * nb * nb, ntiles), dim3(kDepThreads), 0, s,
+                           g, offsets, p, pair_mesh, g.F, g.r, log2D, scale, tile0);
+}
+
+void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, hipStream_t s) {
+    constexpr int BW = 8;
+    const int H = g.r / g.f;                       // diagnostic cells per coarse cell
+    const int nb = (g.ns + BW - 1) / BW;
+    const int log2D = ilog2(512 / H);
+    const double scale = std::ldexp(1.0, -3 * log2D);
+    hipLaunchKernelGGL((k_deposit<BW, DEP_DIAG>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s, g, offsets, p,
+                       reinterpret_cast<float*>(mesh), g.ns, H, log2D, scale, 0);
+}
+
+}  // namespace cube

@@ -1,0 +1,382 @@
+// 3-D complex FFTs for the PM Poisson solves (Sec. II, Eq. (1): the force is
+// a Fourier-space product of the density and a kernel; Sec. IV names MKL FFT
+// for the CPU code -- here every transform is an LDS kernel for gfx950).
+//
+// Design: each workgroup loads W pencils of length N along one axis into LDS
+// (x: W contiguous rows; y, z: W adjacent x-columns, so every global access is
+// a run of W*8 contiguous bytes), runs a self-sorting Stockham transform with
+// radices 2,3,4,5,7,8 in LDS, and writes back.  Twiddles come from a table of
+// exp(-2 pi i k / N) computed in FP64 and rounded once to FP32.  The z pass
+// can fuse forward transform, multiplication by a real even Green's table
+// (stored as one octant) and inverse transform, so a Poisson solve is five
+// sweeps over the mesh: x, y, z+G+z^-1, y^-1, x^-1.
+//
+// Conventions: forward uses exp(-2 pi i jk/N) like numpy; inverse is
+// unnormalised (the 1/N^3 is folded into the Green's tables).
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace cube {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// J(a): multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_j(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---- small DFTs in registers --------------------------------------------
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+    __device__ static void run(float2* a) {
+        float2 t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+    __device__ static void run(float2* a) {
+        const float s3 = 0.86602540378443864676f;
+        float2 t = cadd(a[1], a[2]);
+        float2 m = csub(a[0], cscale(t, 0.5f));
+        float2 d = cscale(mul_j<INV>(csub(a[1], a[2])), s3);
+        a[0] = cadd(a[0], t);
+        a[1] = cadd(m, d);
+        a[2] = csub(m, d);
+    }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+    __device__ static void run(float2* a) {
+        float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        float2 t2 = cadd(a[1], a[3]), t3 = mul_j<INV>(csub(a[1], a[3]));
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, t3);
+        a[3] = csub(t1, t3);
+    }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+    __device__ static void run(float2* a) {
+        const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+        const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+        float2 b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+        float2 d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+        float2 r1 = make_float2(a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y);
+        float2 r2 = make_float2(a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y);
+        float2 i1 = mul_j<INV>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+        float2 i2 = mul_j<INV>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+        a[0] = cadd(a[0], cadd(b1, b2));
+        a[1] = cadd(r1, i1);
+        a[4] = csub(r1, i1);
+        a[2] = cadd(r2, i2);
+        a[3] = csub(r2, i2);
+    }
+};
+
+template <bool INV>
+struct Dft<7, INV> {
+    __device__ static void run(float2* a) {
+        const float c1 = 0.62348980185873353053f, c2 = -0.22252093395631440429f, c3 = -0.90096886790241912624f;
+        const float s1 = 0.78183148246802980871f, s2 = 0.97492791218182360702f, s3 = 0.43388373911755812048f;
+        float2 b1 = cadd(a[1], a[6]), b2 = cadd(a[2], a[5]), b3 = cadd(a[3], a[4]);
+        float2 d1 = csub(a[1], a[6]), d2 = csub(a[2], a[5]), d3 = csub(a[3], a[4]);
+        float2 x0 = a[0];
+        float2 r1 = make_float2(x0.x + c1 * b1.x + c2 * b2.x + c3 * b3.x, x0.y + c1 * b1.y + c2 * b2.y + c3 * b3.y);
+        float2 r2 = make_float2(x0.x + c2 * b1.x + c3 * b2.x + c1 * b3.x, x0.y + c2 * b1.y + c3 * b2.y + c1 * b3.y);
+        float2 r3 = make_float2(x0.x + c3 * b1.x + c1 * b2.x + c2 * b3.x, x0.y + c3 * b1.y + c1 * b2.y + c2 * b3.y);
+        float2 i1 = mul_j<INV>(make_float2(s1 * d1.x + s2 * d2.x + s3 * d3.x, s1 * d1.y + s2 * d2.y + s3 * d3.y));
+        float2 i2 = mul_j<INV>(make_float2(s2 * d1.x - s3 * d2.x - s1 * d3.x, s2 * d1.y - s3 * d2.y - s1 * d3.y));
+        float2 i3 = mul_j<INV>(make_float2(s3 * d1.x - s1 * d2.x + s2 * d3.x, s3 * d1.y - s1 * d2.y + s2 * d3.y));
+        a[0] = cadd(x0, cadd(b1, cadd(b2, b3)));
+        a[1] = cadd(r1, i1);
+        a[6] = csub(r1, i1);
+        a[2] = cadd(r2, i2);
+        a[5] = csub(r2, i2);
+        a[3] = cadd(r3, i3);
+        a[4] = csub(r3, i3);
+    }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+    __device__ static void run(float2* a) {
+        const float c = 0.70710678118654752440f;
+        float2 e[4] = {a[0], a[2], a[4], a[6]};
+        float2 o[4] = {a[1], a[3], a[5], a[7]};
+        Dft<4, INV>::run(e);
+        Dft<4, INV>::run(o);
+        // w^1 = (1 -+ i)/sqrt2, w^2 = -+i, w^3 = (-1 -+ i)/sqrt2
+        float2 w1 = INV ? make_float2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                        : make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+        float2 w2 = mul_j<INV>(o[2]);
+        float2 w3 = INV ? make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                        : make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+        a[0] = cadd(e[0], o[0]);
+        a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], w1);
+        a[5] = csub(e[1], w1);
+        a[2] = cadd(e[2], w2);
+        a[6] = csub(e[2], w2);
+        a[3] = cadd(e[3], w3);
+        a[7] = csub(e[3], w3);
+    }
+};
+
+// ---- one Stockham pass over W pencils in LDS -----------------------------
+// Pencil w occupies lds[w*LDN .. w*LDN+N).  NS = product of the radices of
+// the passes already done.
+template <int N, int W, bool INV, int NS, int R>
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw) {
+    constexpr int LDN = N + 1;
+    constexpr int NB = N / R;
+    constexpr int TOTAL = NB * W;
+    constexpr int IT = (TOTAL + kFftThreads - 1) / kFftThreads;
+    float2 v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kFftThreads;
+        if (TOTAL % kFftThreads == 0 || b < TOTAL) {
+            const int j = b % NB, w = b / NB;
+            const float2* col = lds + w * LDN;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = col[j + r * NB];
+            if (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const float2 t = tw[(r * k) * (N / (NS * R))];
+                    v[it][r] = INV ? cmulc(v[it][r], t) : cmul(v[it][r], t);
+                }
+            }
+            Dft<R, INV>::run(v[it]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kFftThreads;
+        if (TOTAL % kFftThreads == 0 || b < TOTAL) {
+            const int j = b % NB, w = b / NB;
+            const int k = j % NS;
+            float2* col = lds + w * LDN + (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) col[r * NS] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int W, bool INV, int NS>
+__device__ __forceinline__ void run_passes(float2*, const float2*) {}
+
+template <int N, int W, bool INV, int NS, int R, int... Rest>
+__device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw) {
+    stockham_pass<N, W, INV, NS, R>(lds, tw);
+    run_passes<N, W, INV, NS * R, Rest...>(lds, tw);
+}
+
+// Radix plan per supported size.
+template <int N>
+struct Plan;
+#define CUBE_FFT_PLAN(NN, ...)                                                   \
+    template <>                                                                  \
+    struct Plan<NN> {                                                            \
+        template <int W, bool INV>                                               \
+        __device__ static void run(float2* lds, const float2* __restrict__ tw) { \
+            run_passes<NN, W, INV, 1, __VA_ARGS__>(lds, tw);                     \
+        }                                                                        \
+    };
+CUBE_FFT_PLAN(16, 4, 4)
+CUBE_FFT_PLAN(32, 4, 8)
+CUBE_FFT_PLAN(48, 3, 4, 4)
+CUBE_FFT_PLAN(64, 8, 8)
+CUBE_FFT_PLAN(80, 5, 4, 4)
+CUBE_FFT_PLAN(96, 3, 4, 8)
+CUBE_FFT_PLAN(112, 7, 4, 4)
+CUBE_FFT_PLAN(128, 2, 8, 8)
+CUBE_FFT_PLAN(160, 5, 4, 8)
+CUBE_FFT_PLAN(192, 3, 8, 8)
+CUBE_FFT_PLAN(224, 7, 4, 8)
+CUBE_FFT_PLAN(256, 4, 8, 8)
+CUBE_FFT_PLAN(320, 5, 8, 8)
+CUBE_FFT_PLAN(384, 3, 2, 8, 8)
+CUBE_FFT_PLAN(448, 7, 8, 8)
+CUBE_FFT_PLAN(512, 8, 8, 8)
+CUBE_FFT_PLAN(1024, 4, 4, 8, 8)
+#undef CUBE_FFT_PLAN
+
+template <int N>
+constexpr int pencils() { return N <= 256 ? 16 : 8; }
+
+__device__ __forceinline__ int fold(int k, int n) { return k <= n / 2 ? k : n - k; }
+
+// KIND: 0 = x pencils, 1 = y pencils, 2 = z pencils.
+// MODE: 0 forward, 1 inverse, 2 forward * float table * inverse, 3 same with a double table.
+template <int N, int KIND, int MODE>
+__global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, const float2* __restrict__ tw,
+                                                      const void* __restrict__ green) {
+    constexpr int W = pencils<N>();
+    constexpr int LDN = N + 1;
+    __shared__ float2 lds[W * LDN];
+    float2* cube_base = data + (int64_t)blockIdx.y * N * N * N;
+    const int b = blockIdx.x;
+    int64_t base;
+    int64_t stride_i, stride_w;
+    int x0 = 0, yz = 0;
+    if (KIND == 0) {            // rows b*W .. b*W+W-1, each N contiguous
+        base = (int64_t)b * W * N;
+        stride_i = 1;
+        stride_w = N;
+    } else {
+        x0 = (b % (N / W)) * W;
+        yz = b / (N / W);
+        stride_w = 1;
+        if (KIND == 1) {        // along y at fixed z
+            base = x0 + (int64_t)N * N * yz;
+            stride_i = N;
+        } else {                // along z at fixed y
+            base = x0 + (int64_t)N * yz;
+            stride_i = (int64_t)N * N;
+        }
+    }
+    float2* g = cube_base + base;
+    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+        int i, w;
+        if (KIND == 0) { i = e % N; w = e / N; } else { w = e % W; i = e / W; }
+        lds[w * LDN + i] = g[i * stride_i + w * stride_w];
+    }
+    __syncthreads();
+    if (MODE == 1) {
+        Plan<N>::template run<W, true>(lds, tw);
+    } else {
+        Plan<N>::template run<W, false>(lds, tw);
+    }
+    if (MODE >= 2) {
+        // multiply by G(kx, ky, kz): this block holds kz = i, ky = yz, kx = x0 + w
+        constexpr int M = N / 2 + 1;
+        const int fy = fold(yz, N);
+        for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+            const int w = e % W, i = e / W;
+            const int64_t gi = ((int64_t)fold(i, N) * M + fy) * M + fold(x0 + w, N);
+            float2 v = lds[w * LDN + i];
+            if (MODE == 2) {
+                const float gv = static_cast<const float*>(green)[gi];
+                v = make_float2(v.x * gv, v.y * gv);
+            } else {
+                const double gv = static_cast<const double*>(green)[gi];
+                v = make_float2((float)((double)v.x * gv), (float)((double)v.y * gv));
+            }
+            lds[w * LDN + i] = v;
+        }
+        __syncthreads();
+        Plan<N>::template run<W, true>(lds, tw);
+    }
+    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+        int i, w;
+        if (KIND == 0) { i = e % N; w = e / N; } else { w = e % W; i = e / W; }
+        g[i * stride_i + w * stride_w] = lds[w * LDN + i];
+    }
+}
+
+template <int N>
+void launch_pass(float2* data, int batch, int kind, int mode, const float2* tw, const void* green,
+                 hipStream_t s) {
+    constexpr int W = pencils<N>();
+    const unsigned blocks = (unsigned)((int64_t)N * N / W);
+    dim3 grid(blocks, batch), block(kFftThreads);
+#define CUBE_L(K, MO) hipLaunchKernelGGL((k_fft<N, K, MO>), grid, block, 0, s, data, tw, green)
+    if (kind == 0) {
+        if (mode == 0) CUBE_L(0, 0); else CUBE_L(0, 1);
+    } else if (kind == 1) {
+        if (mode == 0) CUBE_L(1, 0); else CUBE_L(1, 1);
+    } else {
+        if (mode == 0) CUBE_L(2, 0);
+        else if (mode == 1) CUBE_L(2, 1);
+        else if (mode == 2) CUBE_L(2, 2);
+        else CUBE_L(2, 3);
+    }
+#undef CUBE_L
+}
+
+using PassFn = void (*)(float2*, int, int, int, const float2*, const void*, hipStream_t);
+
+PassFn pass_for(int n) {
+    switch (n) {
+        case 16: return launch_pass<16>;
+        case 32: return launch_pass<32>;
+        case 48: return launch_pass<48>;
+        case 64: return launch_pass<64>;
+        case 80: return launch_pass<80>;
+        case 96: return launch_pass<96>;
+        case 112: return launch_pass<112>;
+        case 128: return launch_pass<128>;
+        case 160: return launch_pass<160>;
+        case 192: return launch_pass<192>;
+        case 224: return launch_pass<224>;
+        case 256: return launch_pass<256>;
+        case 320: return launch_pass<320>;
+        case 384: return launch_pass<384>;
+        case 448: return launch_pass<448>;
+        case 512: return launch_pass<512>;
+        case 1024: return launch_pass<1024>;
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+bool fft_supported(int n) { return pass_for(n) != nullptr; }
+
+void fft_make_twiddles(int n, float2* dev_table, hipStream_t s) {
+    std::vector<float2> h(n);
+    for (int k = 0; k < n; ++k) {
+        // exact argument reduction: angle = 2 pi k / n in FP64, one rounding to FP32
+        const double ang = 2.0 * M_PI * (double)k / (double)n;
+        h[k] = make_float2((float)std::cos(ang), (float)(-std::sin(ang)));
+    }
+    hipMemcpyAsync(dev_table, h.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
+    hipStreamSynchronize(s);
+}
+
+void fft3d(float2* data, int n, int batch, bool inverse, const float2* tw, hipStream_t s) {
+    PassFn f = pass_for(n);
+    const int mode = inverse ? 1 : 0;
+    f(data, batch, 0, mode, tw, nullptr, s);
+    f(data, batch, 1, mode, tw, nullptr, s);
+    f(data, batch, 2, mode, tw, nullptr, s);
+}
+
+void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void* green_octant, int table_kind,
+                    hipStream_t s) {
+    PassFn f = pass_for(n);
+    f(data, batch, 0, 0, tw, nullptr, s);
+    f(data, batch, 1, 0, tw, nullptr, s);
+    f(data, batch, 2, table_kind == 0 ? 2 : 3, tw, green_octant, s);
+    f(data, batch, 1, 1, tw, nullptr, s);
+    f(data, batch, 0, 1, tw, nullptr, s);
+}
+
+}  // namespace cube

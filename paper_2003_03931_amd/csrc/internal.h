@@ -1,0 +1,153 @@
+// Internal declarations shared by the host orchestration and the kernels of
+// libcube.so.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace cube {
+
+// Box geometry in the integer units the kernels use (Sec. II tiles + buffers,
+// Sec. III-A coarse-cell codec).  All sides are cell counts.
+struct Geom {
+    int ns;        // particles per side
+    int f;         // fine cells per spacing
+    int r;         // fine cells per coarse cell
+    int nt;        // tiles per side
+    int b;         // buffer, fine cells
+    int a;         // split radius, fine cells
+    int Nc;        // coarse cells per side
+    int T;         // tile side, fine cells
+    int Tc;        // tile side, coarse cells
+    int F;         // tile FFT box side, fine cells
+    int Fc;        // tile FFT box side, coarse cells (F / r)
+    int hc;        // buffer in coarse cells (b / r)
+    int log2D;     // log2(512 / r): fine-coordinate fraction bits
+    int periodic;  // 1 when the single tile is the periodic box
+    int64_t ncells;   // Nc^3
+    int64_t n;        // ns^3 particles
+    int ntiles;       // nt^3
+};
+
+// Canonical cell index: tile-major (tile index x fastest), x fastest inside.
+__host__ __device__ inline int64_t canon(const Geom& g, int cx, int cy, int cz) {
+    int tx = cx / g.Tc, ty = cy / g.Tc, tz = cz / g.Tc;
+    int lx = cx - tx * g.Tc, ly = cy - ty * g.Tc, lz = cz - tz * g.Tc;
+    int64_t tile = tx + (int64_t)g.nt * (ty + (int64_t)g.nt * tz);
+    return tile * ((int64_t)g.Tc * g.Tc * g.Tc) + lx + (int64_t)g.Tc * (ly + (int64_t)g.Tc * lz);
+}
+
+__host__ __device__ inline int wrapi(int x, int n) {
+    int m = x % n;
+    return m < 0 ? m + n : m;
+}
+
+// Per-step scalars that live on the device so that nothing syncs mid-step.
+struct StepScalars {
+    double s;            // velocity scale of the state
+    double s_next;       // scale after the coming kick
+    int32_t max_u;       // max |u| of the state
+    int32_t max_u_next;  // accumulated by the kick
+    int32_t far_count;   // particles whose carry exceeds one cell
+    int32_t max_carry;   // max |carry| of the step
+    int64_t saturations; // clamped velocity components (cumulative)
+    int32_t overflow;    // an exact accumulator would overflow
+    int32_t pad;
+};
+
+// Particle planes: m[3] uint8 then u[3] int8, each of capacity n.
+struct Planes {
+    uint8_t* m[3];
+    int8_t* u[3];
+    uint32_t* ids;   // may be null
+};
+
+// ---- scan.hip -----------------------------------------------------------
+// out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.
+size_t scan_workspace_bytes(int64_t n);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s);
+
+// ---- sort.hip -----------------------------------------------------------
+// Stable LSD sort of (key, value) pairs by the low `bits` key bits.
+size_t sort_workspace_bytes(int64_t n);
+void stable_sort_pairs(uint32_t* key, uint32_t* val, uint32_t* key_tmp, uint32_t* val_tmp,
+                       int64_t n, int bits, void* ws, hipStream_t s);
+
+// ---- codec.hip ----------------------------------------------------------
+void launch_encode_keys(const Geom& g, const float* pos, uint32_t* key, uint32_t* qpack,
+                        uint32_t* idx, int64_t n, hipStream_t s);
+void launch_absmax_f32(const float* v, int64_t n, uint32_t* out_bits, hipStream_t s);
+void launch_scatter_compressed(const Geom& g, const uint32_t* perm, const uint32_t* qpack,
+                               const float* vel, double s_v, Planes out, int32_t* counts,
+                               StepScalars* sc, int64_t n, hipStream_t st);
+void launch_decode(const Geom& g, const int32_t* offsets, Planes in, const StepScalars* sc,
+                   float* pos, float* vel, hipStream_t s);
+void launch_count_keys(const uint32_t* key, int64_t n, int32_t* counts, hipStream_t s);
+
+// ---- deposit.hip --------------------------------------------------------
+void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
+                           int32_t* overflow, hipStream_t s);
+void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
+                         float* pair_mesh, int32_t* overflow, hipStream_t s);
+void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
+                         hipStream_t s);
+
+// ---- fft.hip ------------------------------------------------------------
+bool fft_supported(int n);
+// Twiddle table exp(-2 pi i k / n), FP64-derived, n entries (device memory).
+void fft_make_twiddles(int n, float2* dev_table, hipStream_t s);
+// Forward or inverse 3-D transform of `batch` cubes of side n.
+void fft3d(float2* data, int n, int batch, bool inverse, const float2* tw, hipStream_t s);
+// Forward 3-D, multiply by a real octant Green's table, inverse 3-D.
+// table_kind: 0 = float octant (n/2+1)^3, 1 = double octant.
+void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void* green_octant,
+                    int table_kind, hipStream_t s);
+
+// ---- green.hip ----------------------------------------------------------
+// FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).
+void build_coarse_green(const Geom& g, double* octant, hipStream_t s);
+void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s);
+size_t fine_green_workspace_bytes(const Geom& g);
+
+// ---- gather.hip ---------------------------------------------------------
+enum GatherMode { GATHER_STEP = 0, GATHER_FORCE = 1, GATHER_POTENTIAL = 2 };
+struct GatherArgs {
+    Geom g;
+    const int32_t* offsets;
+    Planes in;
+    Planes out;             // GATHER_STEP: updated m', u' at the same index
+    uint8_t* dir;           // GATHER_STEP: move code 0..26, 255 = far mover
+    uint32_t* far_key;      // GATHER_STEP: new canonical cell of far movers
+    int32_t* counts_new;    // GATHER_STEP: histogram of new cells
+    const float* fine_pairs;   // fine potential of the batch (pair-packed)
+    const float2* coarse;      // coarse potential (real part)
+    StepScalars* sc;
+    float* acc;             // GATHER_FORCE: [n][3]
+    double* partial;        // GATHER_POTENTIAL: per-block partial sums
+    float dt;
+    int tile0;
+    int ntiles;
+    int mode;
+};
+void launch_gather(const GatherArgs& a, hipStream_t s);
+
+// ---- compact.hip --------------------------------------------------------
+void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
+                         const uint8_t* dir, Planes src, Planes dst, hipStream_t s);
+void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir,
+                         const uint32_t* far_key, uint32_t* key, uint32_t* idx, hipStream_t s);
+void launch_permute_planes(const uint32_t* perm, Planes src, Planes dst, int64_t n, hipStream_t s);
+
+// ---- step.hip -----------------------------------------------------------
+void launch_step_prologue(StepScalars* sc, float v_headroom, hipStream_t s);
+void launch_step_epilogue(StepScalars* sc, hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,
+                    double* partial, int nblocks, hipStream_t s);
+void launch_reduce_partials(const double* partial, int nblocks, int width, double* out,
+                            hipStream_t s);
+void launch_power_bins(const float2* dk, int n, int nbins, double* partial, int nparts,
+                       hipStream_t s);
+
+}  // namespace cube

@@ -1,0 +1,133 @@
+// Exclusive prefix sum of int32 cell counts -> cell offsets (Sec. III-A: a
+// per-cell count locates each cell's particles in the cell-ordered arrays).
+//
+// Three passes over tiles of 4096 values: per-tile totals, a (recursive) scan
+// of the totals, then a tile-local scan plus the tile's base.  Each thread
+// owns 16 consecutive values so the loads are 64-byte vectors.
+#include "common.h"
+
+namespace cube {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ in,
+                                                             int64_t n, int32_t* __restrict__ sums) {
+    __shared__ int lds[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int acc = 0;
+    if (base + kScanItems <= n) {
+        const int4* p = reinterpret_cast<const int4*>(in + base);
+#pragma unroll
+        for (int i = 0; i < kScanItems / 4; ++i) {
+            int4 q = p[i];
+            acc += q.x + q.y + q.z + q.w;
+        }
+    } else {
+        for (int i = 0; i < kScanItems; ++i)
+            if (base + i < n) acc += in[base + i];
+    }
+    int total;
+    block_exclusive_scan(acc, lds, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in,
+                                                             int64_t n, const int32_t* __restrict__ base_of_tile,
+                                                             int32_t* __restrict__ out) {
+    __shared__ int lds[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    const bool full = base + kScanItems <= n;
+    if (full) {
+        const int4* p = reinterpret_cast<const int4*>(in + base);
+#pragma unroll
+        for (int i = 0; i < kScanItems / 4; ++i) {
+            int4 q = p[i];
+            v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? in[base + i] : 0;
+    }
+    int acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) acc += v[i];
+    int total;
+    int run = block_exclusive_scan(acc, lds, &total) + base_of_tile[blockIdx.x];
+    if (full) {
+        int4* o = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+        for (int i = 0; i < kScanItems / 4; ++i) {
+            int4 q;
+            q.x = run; run += v[4 * i];
+            q.y = run; run += v[4 * i + 1];
+            q.z = run; run += v[4 * i + 2];
+            q.w = run; run += v[4 * i + 3];
+            o[i] = q;
+        }
+    } else {
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < n) out[base + i] = run;
+            run += v[i];
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[n] = base_of_tile[blockIdx.x] + total;
+}
+
+// Single-block scan for short inputs (n <= kScanTile): out[0..n].
+__global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __restrict__ in, int64_t n,
+                                                              int32_t* __restrict__ out) {
+    __shared__ int lds[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        acc += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(acc, lds, &total);
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) out[n] = total;
+}
+
+inline int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
+
+}  // namespace
+
+size_t scan_workspace_bytes(int64_t n) {
+    size_t bytes = 0;
+    int64_t m = n;
+    while (m > kScanTile) {
+        int64_t nb = (m + kScanTile - 1) / kScanTile;
+        bytes += (size_t)(round16(nb) + round16(nb + 1)) * sizeof(int32_t);
+        m = nb;
+    }
+    return bytes + 256;
+}
+
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+    if (n <= kScanTile) {
+        hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kScanThreads), 0, s, in, n, out);
+        return;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    // keep every array 64-byte aligned: the tile kernels use 16-byte vectors
+    int32_t* sums = static_cast<int32_t*>(ws);
+    int32_t* sums_scan = sums + round16(nb);
+    void* rest = sums_scan + round16(nb + 1);
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums);
+    exclusive_scan_i32(sums, sums_scan, nb, rest, s);
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums_scan, out);
+}
+
+}  // namespace cube

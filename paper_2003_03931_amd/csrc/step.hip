@@ -1,0 +1,149 @@
+// Per-step scalar bookkeeping and FP64 diagnostics.
+//
+// Velocity scale update before each kick: s' = pow2ceil(h_v M s / 127) with M
+// the max |u| left by the previous kick (kept at s when M = 0); evaluated in
+// FP64 on the device so a multi-step call never waits for the host.
+// Diagnostics: momentum and kinetic energy of the decoded velocities summed in
+// FP64 in a fixed order (per-chunk partials, then one ordered reduction);
+// power-spectrum shells binned in FP64.
+#include "common.h"
+
+namespace cube {
+
+namespace {
+
+__device__ double pow2ceil_d(double x) {
+    int e;
+    const double m = frexp(x, &e);      // x = m 2^e, m in [0.5, 1)
+    return m == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+}
+
+__global__ void k_prologue(StepScalars* sc, float hv) {
+    if (threadIdx.x != 0) return;
+    const int M = sc->max_u;
+    const double s = sc->s;
+    sc->s_next = (M == 0) ? s : pow2ceil_d(((double)hv * (double)M) * s / 127.0);
+    sc->max_u_next = 0;
+    sc->far_count = 0;
+    sc->max_carry = 0;
+}
+
+__global__ void k_epilogue(StepScalars* sc) {
+    if (threadIdx.x != 0) return;
+    sc->s = sc->s_next;
+    sc->max_u = sc->max_u_next;
+}
+
+__global__ void k_fill(int32_t* p, int32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// per chunk: sum v_x, v_y, v_z, v^2 (v = u s) in FP64
+__global__ __launch_bounds__(256) void k_moments(Geom g, const int32_t* __restrict__ offsets, Planes p,
+                                                 const StepScalars* __restrict__ sc, double* __restrict__ partial) {
+    __shared__ double red[4][256 / kWave];
+    const int64_t c0 = (int64_t)blockIdx.x * g.Tc;
+    const int lo = offsets[c0], hi = offsets[c0 + g.Tc];
+    const double s = sc->s;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double v = (double)p.u[k][i] * s;
+            a[k] += v;
+            a[3] += v * v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum_d(a[k]);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[k][threadIdx.x / kWave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[threadIdx.x][w];
+        partial[(int64_t)blockIdx.x * 4 + threadIdx.x] = t;
+    }
+}
+
+// out[c] = sum_b partial[b * width + c], fixed order
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int nblocks, int width,
+                                                         double* __restrict__ out) {
+    __shared__ double red[256 / kWave];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partial[(int64_t)b * width + c];
+    acc = wave_sum_d(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+        out[c] = t;
+    }
+}
+
+// one block per z-plane: shell sums of |dk|^2 / n^3, mode counts and |k| sums
+__global__ __launch_bounds__(256) void k_power_bins(const float2* __restrict__ dk, int n, int nbins,
+                                                    double* __restrict__ partial) {
+    extern __shared__ double sh[];
+    double* ps = sh;
+    double* ks = sh + nbins;
+    double* cs = sh + 2 * nbins;
+    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) sh[i] = 0.0;
+    __syncthreads();
+    const int z = blockIdx.x;
+    const int mz = z <= n / 2 - 1 ? z : z - n;
+    const double inv_n3 = 1.0 / ((double)n * n * n);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int x = e % n, y = e / n;
+        const int mx = x <= n / 2 - 1 ? x : x - n;
+        const int my = y <= n / 2 - 1 ? y : y - n;
+        const long r2 = (long)mx * mx + (long)my * my + (long)mz * mz;
+        const double r = sqrt((double)r2);
+        const int j = (int)floor(r + 0.5);
+        if (j >= 1 && j <= nbins) {
+            const float2 v = dk[((int64_t)z * n + y) * n + x];
+            const double pw = ((double)v.x * v.x + (double)v.y * v.y) * inv_n3;
+            atomicAdd(&ps[j - 1], pw);
+            atomicAdd(&ks[j - 1], r * (2.0 * M_PI / n));
+            atomicAdd(&cs[j - 1], 1.0);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) partial[(int64_t)z * 3 * nbins + i] = sh[i];
+}
+
+}  // namespace
+
+void launch_step_prologue(StepScalars* sc, float v_headroom, hipStream_t s) {
+    hipLaunchKernelGGL(k_prologue, dim3(1), dim3(64), 0, s, sc, v_headroom);
+}
+
+void launch_step_epilogue(StepScalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, sc);
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    unsigned blocks = grid1d(n, 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, v, n);
+}
+
+void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc, double* partial,
+                    int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, dim3(nblocks), dim3(256), 0, s, g, offsets, p, sc, partial);
+}
+
+void launch_reduce_partials(const double* partial, int nblocks, int width, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(width), dim3(256), 0, s, partial, nblocks, width, out);
+}
+
+void launch_power_bins(const float2* dk, int n, int nbins, double* partial, int /*nparts*/, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_bins, dim3(n), dim3(256), 3 * nbins * sizeof(double), s, dk, n, nbins, partial);
+}
+
+}  // namespace cube
