@@ -58,6 +58,9 @@ CONFIGS = {
     "c2s": BoxSpec("c2s", 128, 2, 2, 8, 16, 12, DT, 2.0, -2.0, 0.5, 1012, 3),
     # c3's tile geometry (r = 4, b = 16) on 2^3 tiles of 64^3 particles.
     "c3s": BoxSpec("c3s", 128, 2, 2, 4, 16, 12, DT, 2.0, -1.5, 2.0, 1013, 2),
+    # the 1024^3 workload's tile geometry (r = 4, b = 16, 160^3 tile box,
+    # 8 particles per coarse cell) on 1/64 of its volume: the CPU-baseline sample.
+    "c3cpu": BoxSpec("c3cpu", 256, 4, 2, 4, 16, 12, DT, 2.0, -1.5, 2.0, 1033, 1),
     # a small tiled box: 4^3 tiles of 16^3 particles (tile box 32 + 2*16).
     "t4": BoxSpec("t4", 64, 4, 2, 4, 16, 12, DT, 2.0, -2.0, 0.7, 1021, 3),
 }

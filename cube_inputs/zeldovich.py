@@ -65,19 +65,22 @@ def zeldovich_ics(n: int, spectral_index: float, rms_disp: float, seed: int,
         psi[c] = fft.irfftn(comp, s=(n, n, n), **kw)
         del comp
     del dk, inv_k2
-    rms = np.sqrt(np.mean(np.sum(psi.astype(np.float64) ** 2, axis=0)))
+    rms = np.sqrt(sum(float(np.sum(psi[c].astype(np.float64) ** 2)) for c in range(3)) / n ** 3)
     psi *= real_t(rms_disp / rms)
-    # lattice order p = ix + n*(iy + n*iz): flatten (z, y, x) arrays in C order
-    psi_flat = psi.reshape(3, -1).T.astype(np.float64)         # (N, 3) x,y,z
-    del psi
-    idx = np.arange(n, dtype=np.float64) + 0.5
-    qz, qy, qx = np.meshgrid(idx, idx, idx, indexing="ij")
-    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
-    del qx, qy, qz
-    pos = np.mod(q + psi_flat, float(n))
-    pos = pos.astype(np.float32)
-    pos[pos >= np.float32(n)] = np.float32(0.0)               # mod can round up to L
-    vel = (psi_flat * np.exp(-0.5 * dt)).astype(np.float32)
+    # lattice order p = ix + n*(iy + n*iz): the (z, y, x) arrays flattened in C order
+    N = n ** 3
+    pos = np.empty((N, 3), dtype=np.float32)
+    vel = np.empty((N, 3), dtype=np.float32)
+    lattice = np.arange(n, dtype=np.float64) + 0.5
+    shape = [(1, 1, n), (1, n, 1), (n, 1, 1)]          # q_x, q_y, q_z broadcasts
+    damp = np.exp(-0.5 * dt)
+    for c in range(3):
+        comp = psi[c].astype(np.float64)
+        x = np.mod(comp + lattice.reshape(shape[c]), float(n)).astype(np.float32)
+        x[x >= np.float32(n)] = np.float32(0.0)                # mod can round up to L
+        pos[:, c] = x.ravel()
+        vel[:, c] = (comp * damp).astype(np.float32).ravel()
+        del comp, x
     return pos, vel
 
 

@@ -193,6 +193,24 @@ cube_status cube_debug_mesh(cube_ctx* ctx, int32_t what, int32_t tile, float* ou
  * NULL.  Synchronises. */
 cube_status cube_fft3d(int32_t n, float* data, int32_t inverse, void* hip_stream);
 
+/* Per-stage timing of cube_pm_step, measured with HIP events recorded on the
+ * context stream around every launch of the stage (profiling adds one event
+ * pair per launch).  `bytes` is the stage's algorithmic traffic summed over
+ * its launches (what the method must move: particle bytes, mesh reads and
+ * writes), so bytes / (total_ms * 1e-3) is its achieved rate. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} cube_stage_stat;
+
+/* Enable (nonzero) or disable profiling; enabling clears the counters. */
+cube_status cube_profile_enable(cube_ctx* ctx, int32_t enable);
+
+/* Copy up to max stage records into out; *n receives the number written. */
+cube_status cube_profile_read(cube_ctx* ctx, cube_stage_stat* out, int32_t max, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

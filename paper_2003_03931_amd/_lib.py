@@ -68,6 +68,15 @@ class Diag(ctypes.Structure):
     ]
 
 
+class StageStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
 # exported symbol -> (restype, argtypes); mirrors include/cube.h
 SIGNATURES = {
     "cube_last_error": (ctypes.c_char_p, []),
@@ -86,6 +95,9 @@ SIGNATURES = {
                                            ctypes.c_void_p]),
     "cube_debug_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "cube_fft3d": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cube_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cube_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StageStat), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None

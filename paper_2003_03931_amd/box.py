@@ -9,7 +9,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import BoxDesc, Diag, StateView, check, load
+from ._lib import BoxDesc, Diag, StageStat, StateView, check, load
 
 CUBE_FP32 = 0
 
@@ -156,6 +156,17 @@ class CubeBox:
         check(self.lib.cube_power_spectrum(self.ctx, nb, k.ctypes.data_as(ctypes.c_void_p),
                                            pk.ctypes.data_as(ctypes.c_void_p), nm.ctypes.data_as(ctypes.c_void_p)))
         return k, pk, nm
+
+    def profile(self, enable=True):
+        check(self.lib.cube_profile_enable(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """[{name, launches, total_ms, bytes}] per stage of cube_pm_step."""
+        buf = (StageStat * 32)()
+        n = ctypes.c_int32()
+        check(self.lib.cube_profile_read(self.ctx, buf, 32, ctypes.byref(n)))
+        return [{"name": buf[i].name.decode(), "launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                 "bytes": buf[i].bytes} for i in range(n.value)]
 
     def debug_mesh(self, what, tile=0):
         t = self.torch

@@ -51,9 +51,76 @@ int ilog2(int v) {
     return l;
 }
 
+enum Stage {
+    ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_XF, ST_FFT_YF, ST_FFT_ZC, ST_FFT_YI, ST_FFT_XI,
+    ST_GATHER, ST_SCAN, ST_COMPACT, NSTAGES
+};
+const char* const kStageNames[NSTAGES] = {
+    "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_fft_x_fwd", "fine_fft_y_fwd",
+    "fine_fft_z_green_inv", "fine_fft_y_inv", "fine_fft_x_inv", "gather_kick_drift", "scan_counts",
+    "compact"};
+
+// HIP events around every launch of a stage, resolved at the next sync.
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    int64_t launches[NSTAGES] = {};
+    double ms[NSTAGES] = {};
+    double bytes[NSTAGES] = {};
+
+    hipEvent_t get() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t mark(hipStream_t s) {
+        hipEvent_t e = get();
+        hipEventRecord(e, s);
+        return e;
+    }
+    void add(int stage, hipEvent_t a, hipEvent_t b, double by) { pending.push_back({stage, a, b, by}); }
+    // call only after the stream has been synchronised
+    void flush() {
+        std::vector<hipEvent_t> done;
+        for (const Pending& p : pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+                ms[p.stage] += t;
+                launches[p.stage] += 1;
+                bytes[p.stage] += p.bytes;
+            }
+            done.push_back(p.a);
+            done.push_back(p.b);
+        }
+        pending.clear();
+        std::sort(done.begin(), done.end());
+        done.erase(std::unique(done.begin(), done.end()), done.end());
+        for (hipEvent_t e : done) pool.push_back(e);
+    }
+    void reset() {
+        for (int i = 0; i < NSTAGES; ++i) { launches[i] = 0; ms[i] = 0.0; bytes[i] = 0.0; }
+    }
+    ~Profiler() {
+        for (const Pending& p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 struct cube_ctx {
+    Profiler prof;
     Geom g{};
     cube_box_desc desc{};
     hipStream_t stream = nullptr;
@@ -184,8 +251,19 @@ cube_status sync(cube_ctx* c) {
 // coarse potential into ctx->coarse (real part)
 void coarse_potential(cube_ctx* c) {
     const Geom& g = c->g;
+    Profiler& P = c->prof;
+    const double nc3 = (double)g.ncells;
+    hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_coarse_deposit(g, c->offsets, c->A, c->coarse, nullptr, c->stream);
+    hipEvent_t e1 = P.on ? P.mark(c->stream) : nullptr;
     fft3d_convolve(c->coarse, g.Nc, 1, c->tw_coarse, c->coarse_green, 1, c->stream);
+    if (P.on) {
+        hipEvent_t e2 = P.mark(c->stream);
+        // deposit: complex mesh write + offsets read + 3 position bytes per particle
+        P.add(ST_COARSE_DEP, e0, e1, 12.0 * nc3 + 3.0 * (double)g.n);
+        // five read+write sweeps of the complex mesh
+        P.add(ST_COARSE_FFT, e1, e2, 80.0 * nc3);
+    }
 }
 
 // fine potentials of tiles [t0, t0 + nt) into ctx->fine_pairs
@@ -197,8 +275,25 @@ void fine_potential(cube_ctx* c, int t0, int nt) {
         const int64_t cube3 = (int64_t)g.F * g.F * g.F;
         hipMemsetAsync(c->fine_pairs + (int64_t)(pairs - 1) * 2 * cube3, 0, 2 * cube3 * sizeof(float), c->stream);
     }
+    Profiler& P = c->prof;
+    hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_pairs, nullptr, c->stream);
-    fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0, c->stream);
+    if (!P.on) {
+        fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0,
+                       c->stream);
+        return;
+    }
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) ev[i] = P.get();
+    fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0, c->stream,
+                   ev);
+    const double f3 = (double)g.F * g.F * g.F, fc3 = (double)g.Fc * g.Fc * g.Fc;
+    const double per_tile = (double)g.n / g.ntiles;
+    const double src = per_tile * f3 / ((double)g.T * g.T * g.T);    // tile plus buffer
+    // deposit: FP32 mesh write + offsets read + 3 position bytes per source
+    P.add(ST_FINE_DEP, e0, ev[0], nt * (4.0 * f3 + 4.0 * fc3 + 3.0 * src));
+    // every FFT sweep reads and writes the complex pair meshes once
+    for (int i = 0; i < 5; ++i) P.add(ST_FFT_XF + i, ev[i], ev[i + 1], 16.0 * pairs * f3);
 }
 
 GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
@@ -236,18 +331,33 @@ cube_status run_step(cube_ctx* c) {
     launch_step_prologue(c->sc, c->desc.v_headroom, s);
     launch_fill_i32(c->counts_new, 0, g.ncells, s);
     coarse_potential(c);
+    Profiler& P = c->prof;
     for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
         const int nt = std::min(c->batch, g.ntiles - t0);
         fine_potential(c, t0, nt);
         GatherArgs a = gather_args(c, GATHER_STEP, t0, nt);
+        hipEvent_t e0 = P.on ? P.mark(s) : nullptr;
         launch_gather(a, s);
+        if (P.on) {
+            const double np = (double)g.n * nt / g.ntiles;
+            const double t4 = (double)(g.T + 4) * (g.T + 4) * (g.T + 4);
+            const double c4 = (double)(g.Tc + 4) * (g.Tc + 4) * (g.Tc + 4);
+            // 6 B in, 7 B out (m', u', move code), one count update, potentials read once
+            P.add(ST_GATHER, e0, P.mark(s), 21.0 * np + 4.0 * nt * (t4 + c4));
+        }
     }
+    hipEvent_t es = P.on ? P.mark(s) : nullptr;
     exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s);
+    if (P.on) P.add(ST_SCAN, es, P.mark(s), 8.0 * (double)g.ncells);
     CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     cube_status st = sync(c);
     if (st != CUBE_OK) return st;
+    if (P.on) P.flush();
     if (c->sc_host->far_count == 0) {
+        hipEvent_t ec = P.on ? P.mark(s) : nullptr;
         launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, c->B, c->A, s);
+        // 6 B + move code read, 6 B written, old and new offsets read
+        if (P.on) P.add(ST_COMPACT, ec, P.mark(s), 13.0 * (double)g.n + 8.0 * (double)g.ncells);
     } else {
         // general path: stable sort of the new keys (temporary buffers)
         uint32_t *key = nullptr, *idx = nullptr, *kt = nullptr, *it = nullptr;
@@ -499,6 +609,7 @@ cube_status cube_pm_step(cube_ctx* c, int32_t nsteps) {
         if (st != CUBE_OK) return st;
     }
     st = sync(c);
+    if (st == CUBE_OK && c->prof.on) c->prof.flush();
     auto t1 = std::chrono::steady_clock::now();
     if (nsteps > 0) c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
     return st;
@@ -730,6 +841,37 @@ cube_status cube_fft3d(int32_t n, float* data, int32_t inverse, void* hip_stream
     if (e != hipSuccess) return fail(CUBE_DEVICE, hipGetErrorString(e));
     e = hipGetLastError();
     if (e != hipSuccess) return fail(CUBE_DEVICE, hipGetErrorString(e));
+    return CUBE_OK;
+}
+
+cube_status cube_profile_enable(cube_ctx* c, int32_t enable) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    c->prof.flush();
+    c->prof.reset();
+    c->prof.on = enable != 0;
+    return CUBE_OK;
+}
+
+cube_status cube_profile_read(cube_ctx* c, cube_stage_stat* out, int32_t max, int32_t* n) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (!out || !n || max < 0) return fail(CUBE_INVALID, "bad profile buffer");
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    c->prof.flush();
+    int k = 0;
+    for (int i = 0; i < NSTAGES && k < max; ++i) {
+        std::memset(&out[k], 0, sizeof(cube_stage_stat));
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", kStageNames[i]);
+        out[k].launches = c->prof.launches[i];
+        out[k].total_ms = c->prof.ms[i];
+        out[k].bytes = c->prof.bytes[i];
+        ++k;
+    }
+    *n = k;
     return CUBE_OK;
 }
 

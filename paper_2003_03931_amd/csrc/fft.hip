@@ -370,13 +370,19 @@ void fft3d(float2* data, int n, int batch, bool inverse, const float2* tw, hipSt
 }
 
 void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void* green_octant, int table_kind,
-                    hipStream_t s) {
+                    hipStream_t s, hipEvent_t* ev) {
     PassFn f = pass_for(n);
+    if (ev) hipEventRecord(ev[0], s);
     f(data, batch, 0, 0, tw, nullptr, s);
+    if (ev) hipEventRecord(ev[1], s);
     f(data, batch, 1, 0, tw, nullptr, s);
+    if (ev) hipEventRecord(ev[2], s);
     f(data, batch, 2, table_kind == 0 ? 2 : 3, tw, green_octant, s);
+    if (ev) hipEventRecord(ev[3], s);
     f(data, batch, 1, 1, tw, nullptr, s);
+    if (ev) hipEventRecord(ev[4], s);
     f(data, batch, 0, 1, tw, nullptr, s);
+    if (ev) hipEventRecord(ev[5], s);
 }
 
 }  // namespace cube

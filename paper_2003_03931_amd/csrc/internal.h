@@ -101,8 +101,9 @@ void fft_make_twiddles(int n, float2* dev_table, hipStream_t s);
 void fft3d(float2* data, int n, int batch, bool inverse, const float2* tw, hipStream_t s);
 // Forward 3-D, multiply by a real octant Green's table, inverse 3-D.
 // table_kind: 0 = float octant (n/2+1)^3, 1 = double octant.
+// ev (optional, 6 events): recorded before the first pass and after each pass.
 void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void* green_octant,
-                    int table_kind, hipStream_t s);
+                    int table_kind, hipStream_t s, hipEvent_t* ev = nullptr);
 
 // ---- green.hip ----------------------------------------------------------
 // FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).
