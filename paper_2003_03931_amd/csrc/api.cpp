@@ -52,13 +52,12 @@ int ilog2(int v) {
 }
 
 enum Stage {
-    ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_XF, ST_FFT_YF, ST_FFT_ZC, ST_FFT_YI, ST_FFT_XI,
+    ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_R2C, ST_FFT_ZG, ST_FFT_C2R,
     ST_GATHER, ST_SCAN, ST_COMPACT, NSTAGES
 };
 const char* const kStageNames[NSTAGES] = {
-    "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_fft_x_fwd", "fine_fft_y_fwd",
-    "fine_fft_z_green_inv", "fine_fft_y_inv", "fine_fft_x_inv", "gather_kick_drift", "scan_counts",
-    "compact"};
+    "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_r2c_xy", "fine_z_green",
+    "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact"};
 
 // HIP events around every launch of a stage, resolved at the next sync.
 struct Profiler {
@@ -141,7 +140,8 @@ struct cube_ctx {
     float2* coarse = nullptr;
     double* coarse_green = nullptr;
     float2* tw_coarse = nullptr;
-    float* fine_pairs = nullptr;
+    float* fine_real = nullptr;       // batch x F^3 real meshes (density, then potential)
+    float2* fine_spec = nullptr;      // batch x F^2 (F/2+1) half spectra
     float* fine_green = nullptr;
     float2* tw_fine = nullptr;
     void* scan_ws = nullptr;
@@ -152,6 +152,7 @@ struct cube_ctx {
 
     int64_t step = 0;
     double last_step_ms = 0.0;
+    int32_t max_count = 0;            // largest cell count of the current state
 
     ~cube_ctx() {
         if (sc_host) hipHostFree(sc_host);
@@ -214,10 +215,15 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     g.ncells = (int64_t)g.Nc * g.Nc * g.Nc;
     g.n = (int64_t)g.ns * g.ns * g.ns;
     g.ntiles = g.nt * g.nt * g.nt;
+    g.tc_shift = is_pow2(g.Tc) ? ilog2(g.Tc) : -1;
+    g.nt_shift = is_pow2(g.nt) ? ilog2(g.nt) : -1;
     if (g.n >= (int64_t)1 << 31) return fail(CUBE_INVALID, "more than 2^31 - 1 particles");
     if (g.Nc % 4 || g.Nc < 10) return fail(CUBE_INVALID, "coarse mesh side must be a multiple of 4 and >= 12");
-    if (!fft_supported(g.Nc) || !fft_supported(g.F))
+    if (!fft_supported(g.Nc) || !fft_tiles_supported(g.F))
         return fail(CUBE_UNSUPPORTED, "mesh side not supported by the FFT radix plans");
+    if (!compact_supported(g)) return fail(CUBE_UNSUPPORTED, "coarse mesh too small for the compaction bricks");
+    if (!gather_supported(g))
+        return fail(CUBE_UNSUPPORTED, "tile side must be a multiple of 32 fine cells and r in {4, 8, 16}");
     if (!(d->dt > 0.0f) || !(d->v_headroom >= 1.0f)) return fail(CUBE_INVALID, "need dt > 0 and v_headroom >= 1");
     if (d->precision != CUBE_FP32) return fail(CUBE_UNSUPPORTED, "only the FP32 precision is built");
     *out = g;
@@ -266,34 +272,30 @@ void coarse_potential(cube_ctx* c) {
     }
 }
 
-// fine potentials of tiles [t0, t0 + nt) into ctx->fine_pairs
+// fine potentials of tiles [t0, t0 + nt) into ctx->fine_real
 void fine_potential(cube_ctx* c, int t0, int nt) {
     const Geom& g = c->g;
-    const int pairs = (nt + 1) / 2;
-    if (nt & 1) {
-        // the last pair carries one tile: its other lane must be finite (zero)
-        const int64_t cube3 = (int64_t)g.F * g.F * g.F;
-        hipMemsetAsync(c->fine_pairs + (int64_t)(pairs - 1) * 2 * cube3, 0, 2 * cube3 * sizeof(float), c->stream);
-    }
     Profiler& P = c->prof;
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
-    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_pairs, nullptr, c->stream);
+    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_count),
+                        c->stream);
     if (!P.on) {
-        fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0,
-                       c->stream);
+        fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, c->stream);
         return;
     }
-    hipEvent_t ev[6];
-    for (int i = 0; i < 6; ++i) ev[i] = P.get();
-    fft3d_convolve(reinterpret_cast<float2*>(c->fine_pairs), g.F, pairs, c->tw_fine, c->fine_green, 0, c->stream,
-                   ev);
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i) ev[i] = P.get();
+    fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, c->stream, ev);
     const double f3 = (double)g.F * g.F * g.F, fc3 = (double)g.Fc * g.Fc * g.Fc;
+    const double h3 = (double)g.F * g.F * (g.F / 2 + 1);
     const double per_tile = (double)g.n / g.ntiles;
     const double src = per_tile * f3 / ((double)g.T * g.T * g.T);    // tile plus buffer
     // deposit: FP32 mesh write + offsets read + 3 position bytes per source
     P.add(ST_FINE_DEP, e0, ev[0], nt * (4.0 * f3 + 4.0 * fc3 + 3.0 * src));
-    // every FFT sweep reads and writes the complex pair meshes once
-    for (int i = 0; i < 5; ++i) P.add(ST_FFT_XF + i, ev[i], ev[i + 1], 16.0 * pairs * f3);
+    // xy planes: real mesh in, half spectrum out (and back); z: half spectrum in and out
+    P.add(ST_FFT_R2C, ev[0], ev[1], nt * (4.0 * f3 + 8.0 * h3));
+    P.add(ST_FFT_ZG, ev[1], ev[2], nt * 16.0 * h3);
+    P.add(ST_FFT_C2R, ev[2], ev[3], nt * (8.0 * h3 + 4.0 * f3));
 }
 
 GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
@@ -305,7 +307,7 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     a.dir = c->dir;
     a.far_key = c->far_key;
     a.counts_new = c->counts_new;
-    a.fine_pairs = c->fine_pairs;
+    a.fine_real = c->fine_real;
     a.coarse = c->coarse;
     a.sc = c->sc;
     a.dt = c->desc.dt;
@@ -347,13 +349,15 @@ cube_status run_step(cube_ctx* c) {
         }
     }
     hipEvent_t es = P.on ? P.mark(s) : nullptr;
-    exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s);
+    launch_fill_i32(&c->sc->max_count, 0, 1, s);
+    exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &c->sc->max_count);
     if (P.on) P.add(ST_SCAN, es, P.mark(s), 8.0 * (double)g.ncells);
     CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     cube_status st = sync(c);
     if (st != CUBE_OK) return st;
     if (P.on) P.flush();
-    if (c->sc_host->far_count == 0) {
+    // the fast compaction's 16-bit per-code counts bound the source cells' counts
+    if (c->sc_host->far_count == 0 && c->max_count <= 65535) {
         hipEvent_t ec = P.on ? P.mark(s) : nullptr;
         launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, c->B, c->A, s);
         // 6 B + move code read, 6 B written, old and new offsets read
@@ -384,6 +388,7 @@ cube_status run_step(cube_ctx* c) {
         if (st != CUBE_OK) return st;
     }
     launch_step_epilogue(c->sc, s);
+    c->max_count = c->sc_host->max_count;
     std::swap(c->counts, c->counts_new);
     std::swap(c->offsets, c->offsets_new);
     c->step += 1;
@@ -446,7 +451,8 @@ cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** ou
     CUBE_TRY(c->alloc_n(&c->coarse_green, Mc * Mc * Mc));
     CUBE_TRY(c->alloc_n(&c->tw_coarse, g.Nc));
     const int64_t fcube = (int64_t)g.F * g.F * g.F;
-    CUBE_TRY(c->alloc_n(&c->fine_pairs, (int64_t)((c->batch + 1) / 2) * 2 * fcube));
+    CUBE_TRY(c->alloc_n(&c->fine_real, (int64_t)c->batch * fcube));
+    CUBE_TRY(c->alloc_n(&c->fine_spec, (int64_t)c->batch * g.F * g.F * (g.F / 2 + 1)));
     CUBE_TRY(c->alloc_n(&c->fine_green, Mf * Mf * Mf));
     CUBE_TRY(c->alloc_n(&c->tw_fine, g.F));
     CUBE_TRY(c->alloc_n(&c->reduced, 64));
@@ -556,16 +562,18 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     stable_sort_pairs(key, idx, kt, it, n, bits, ws, s);
     launch_fill_i32(c->counts, 0, g.ncells + 16, s);
     launch_count_keys(key, n, c->counts, s);
-    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s);
     StepScalars init{};
     init.s = s0;
     init.s_next = s0;
     *c->sc_host = init;
     hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s);
+    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
     launch_scatter_compressed(g, idx, qp, dvel, s0, c->A, c->counts, c->sc, n, s);
+    hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s);
     st = sync(c);
     release();
     if (st != CUBE_OK) return st;
+    c->max_count = c->sc_host->max_count;
     c->has_state = true;
     c->step = 0;
     return CUBE_OK;
@@ -680,13 +688,14 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
         if (v->ids) CUBE_HIP(hipMemcpyAsync(c->A.ids, v->ids, g.n * sizeof(uint32_t), kind, s));
         else CUBE_HIP(hipMemsetAsync(c->A.ids, 0, g.n * sizeof(uint32_t), s));
     }
-    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s);
     StepScalars init{};
     init.s = v->s_v;
     init.s_next = v->s_v;
     init.max_u = v->max_u;
     *c->sc_host = init;
     CUBE_HIP(hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s));
+    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     int32_t total = -1;
     CUBE_HIP(hipMemcpyAsync(&total, c->offsets + g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     st = sync(c);
@@ -699,6 +708,7 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
         sync(c);
         return fail(CUBE_INVALID, "counts do not sum to n_particles");
     }
+    c->max_count = c->sc_host->max_count;
     c->has_state = true;
     c->step = v->step;
     return CUBE_OK;
@@ -711,7 +721,7 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
     const Geom& g = c->g;
     hipStream_t s = c->stream;
     const int chunks = (int)(g.ncells / g.Tc);
-    const int64_t gather_blocks = (int64_t)g.Tc * g.Tc * c->batch;
+    const int64_t gather_blocks = (int64_t)gather_blocks_per_tile(g) * c->batch;
     st = ensure_partial(c, std::max<int64_t>(4 * (int64_t)chunks, gather_blocks));
     if (st != CUBE_OK) return st;
     std::memset(out, 0, sizeof(*out));
@@ -745,7 +755,7 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
         GatherArgs a = gather_args(c, GATHER_POTENTIAL, t0, nt);
         a.partial = c->partial;
         launch_gather(a, s);
-        const int64_t np = (int64_t)g.Tc * g.Tc * nt;
+        const int64_t np = (int64_t)gather_blocks_per_tile(g) * nt;
         part.resize(np);
         CUBE_HIP(hipMemcpyAsync(part.data(), c->partial, np * sizeof(double), hipMemcpyDeviceToHost, s));
         st = sync(c);
@@ -814,14 +824,11 @@ cube_status cube_debug_mesh(cube_ctx* c, int32_t what, int32_t tile, float* out)
     } else if (what == 2 || what == 3) {
         if (tile < 0 || tile >= g.ntiles) return fail(CUBE_INVALID, "tile out of range");
         const int64_t fcube = (int64_t)g.F * g.F * g.F;
-        if (what == 2) {
-            CUBE_HIP(hipMemsetAsync(c->fine_pairs, 0, 2 * fcube * sizeof(float), s));
-            launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_pairs, nullptr, s);
-        } else {
-            fine_potential(c, tile, 1);
-        }
-        CUBE_HIP(hipMemcpy2DAsync(out, sizeof(float), c->fine_pairs, 2 * sizeof(float), sizeof(float), fcube,
-                                  hipMemcpyDeviceToDevice, s));
+        if (what == 2)
+            launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_real, fine_deposit_needs_wide(g, c->max_count),
+                                s);
+        else fine_potential(c, tile, 1);
+        CUBE_HIP(hipMemcpyAsync(out, c->fine_real, fcube * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
         return fail(CUBE_INVALID, "unknown mesh");
     }

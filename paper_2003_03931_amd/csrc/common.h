@@ -111,3 +111,28 @@ __device__ inline int find_cell(const int* offs, int len, int p) {
 }
 
 }  // namespace cube
+
+namespace cube {
+
+// Copy `total` elements from global to LDS with U independent loads in flight
+// per thread: lds[lidx(e)] = glob[gidx(e)] for e in [0, total).  Issuing the
+// loads of a batch before any LDS store keeps the memory pipe full instead of
+// paying one full latency per element.
+template <int NT, int U, class T, class FG, class FL>
+__device__ __forceinline__ void stage_to_lds(int total, const T* __restrict__ glob, T* lds, FG gidx, FL lidx) {
+    for (int base = 0; base < total; base += NT * U) {
+        T tmp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            if (e < total) tmp[u] = glob[gidx(e)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            if (e < total) lds[lidx(e)] = tmp[u];
+        }
+    }
+}
+
+}  // namespace cube

@@ -3,109 +3,251 @@
 // counting sort of the old order by new canonical cell.
 //
 // Fast path (every particle moved at most one coarse cell per axis): one
-// workgroup owns a 4^3 block of destination cells.  Its particles can only
-// come from the 6^3 halo of source cells around it, so it histograms the move
-// codes of those sources (27 directions), orders each destination's 27 source
-// cells by canonical index, and places every incoming particle at
-//   new_offset[dest] + (particles from earlier sources) + (rank among the
-//   earlier same-direction particles of its own source cell).
-// Deterministic, no global atomics.  Needs N_c to be a multiple of 4 and >= 6.
+// workgroup owns a brick of destination cells made of BY x BZ segments of BX
+// cells along x inside one tile, so every segment's output is one contiguous
+// run of the new arrays.  Its particles can only come from the source window
+// (BX+2) x (BY+2) x (BZ+2).  Per source cell, one thread walks the cell's
+// particles in order twice: first to histogram their 27 move codes, then --
+// once each destination has ordered its 27 source cells by canonical index and
+// formed prefix counts -- to give every incoming particle its slot
+//   new_offset[dest] + (arrivals from earlier source cells)
+//                    + (earlier same-code particles of its own source cell).
+// Slots are mapped in LDS and the planes copied run by run (coalesced); a
+// brick with more arrivals than the map holds scatters directly instead.
+// Per-code counts are 16-bit: the caller takes this path only when no cell
+// holds more than 65535 particles.  Deterministic, no global atomics.
 //
 // General path: the new keys are sorted stably with the LSD radix sort and the
 // planes are permuted.
+#include <algorithm>
+
 #include "common.h"
 
 namespace cube {
 
 namespace {
 
-constexpr int kCB = 4;                         // destination block side
-constexpr int kHalo = kCB + 2;                 // source window side
-constexpr int kNH = kHalo * kHalo * kHalo;     // 216 source cells
-constexpr int kND = kCB * kCB * kCB;           // 64 destination cells
+constexpr int kCThreads = 256;
+constexpr int kMaxBX = 16;
+constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
+constexpr int kMaxDst = kMaxBX * 2 * 2;
+constexpr int kSlots = 1024;
+constexpr int kDirCap = 4096;                      // staged move codes of the source window
 
-__global__ __launch_bounds__(256) void k_compact_fast(Geom g, const int32_t* __restrict__ off_old,
-                                                       const int32_t* __restrict__ off_new,
-                                                       const uint8_t* __restrict__ dir, Planes src, Planes dst) {
-    __shared__ int h_canon[kNH], h_start[kNH], h_pref[kNH + 1];
-    __shared__ int hist[kNH][27];
-    __shared__ int pre[kND][27];
-    __shared__ int d_off[kND];
-    __shared__ int s_scan[256 / kWave + 1];
+struct CompactShape {
+    int BX, BY, BZ;
+};
 
-    const int nb = g.Nc / kCB;
+__global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape sh, const int32_t* __restrict__ off_old,
+                                                            const int32_t* __restrict__ off_new,
+                                                            const uint8_t* __restrict__ dir, Planes src, Planes dst) {
+    __shared__ int s_start[kMaxSrc], s_canon[kMaxSrc], s_cnt[kMaxSrc];
+    __shared__ uint16_t s_hist[kMaxSrc][27];
+    __shared__ int s_pre[kMaxDst][27];
+    __shared__ int s_doff[kMaxDst + 1];
+    __shared__ int s_run[kMaxDst + 1];      // per destination row segment: slot base
+    __shared__ int s_slot[kSlots];
+    __shared__ int s_pref[kMaxSrc + 1];
+    __shared__ int s_scan[kCThreads / kWave + 1];
+    __shared__ uint8_t s_dir[kDirCap];
+
+    const int BX = sh.BX, BY = sh.BY, BZ = sh.BZ;
+    const int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    const int nsrc = SX * SY * SZ, ndst = BX * BY * BZ, nrow = BY * BZ;
+    const int nbx = g.Nc / BX, nby = g.Nc / BY;
     const int b = blockIdx.x;
-    const int B0[3] = {(b % nb) * kCB, ((b / nb) % nb) * kCB, (b / (nb * nb)) * kCB};
+    const int B0[3] = {(b % nbx) * BX, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * BZ};
 
-    int cnt = 0;
-    if (threadIdx.x < kNH) {
-        const int h = threadIdx.x;
-        const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
+    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
         const int64_t c = canon(g, wrapi(B0[0] + hx - 1, g.Nc), wrapi(B0[1] + hy - 1, g.Nc),
                                 wrapi(B0[2] + hz - 1, g.Nc));
-        h_canon[h] = (int)c;
+        s_canon[h] = (int)c;
         const int st = off_old[c];
-        cnt = off_old[c + 1] - st;
-        h_start[h] = st;
+        s_start[h] = st;
+        s_cnt[h] = off_old[c + 1] - st;
 #pragma unroll
-        for (int d = 0; d < 27; ++d) hist[h][d] = 0;
+        for (int d = 0; d < 27; ++d) s_hist[h][d] = 0;
     }
-    if (threadIdx.x < kND) {
-        const int e = threadIdx.x;
-        const int ex = e % kCB, ey = (e / kCB) % kCB, ez = e / (kCB * kCB);
-        d_off[e] = off_new[canon(g, B0[0] + ex, B0[1] + ey, B0[2] + ez)];
-    }
-    int total;
-    const int pref = block_exclusive_scan(cnt, s_scan, &total);
-    if (threadIdx.x < kNH) h_pref[threadIdx.x] = pref;
-    if (threadIdx.x == 0) h_pref[kNH] = total;
-    __syncthreads();
-
-    // 27-direction histogram of every source cell
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int s = find_cell(h_pref, kNH, e);
-        const int p = h_start[s] + (e - h_pref[s]);
-        const int d = dir[p];
-        if (d < 27) atomicAdd(&hist[s][d], 1);
-    }
-    __syncthreads();
-
-    // pre[dest][d]: particles arriving from sources that precede source(dest, d)
-    for (int e = threadIdx.x; e < kND * 27; e += blockDim.x) {
-        const int dest = e / 27, d = e % 27;
-        const int ex = dest % kCB + 1, ey = (dest / kCB) % kCB + 1, ez = dest / (kCB * kCB) + 1;
-        const int hs = (ex - (d % 3 - 1)) + kHalo * ((ey - ((d / 3) % 3 - 1)) + kHalo * (ez - (d / 9 - 1)));
-        const int my = h_canon[hs];
-        int acc = 0;
-        for (int d2 = 0; d2 < 27; ++d2) {
-            const int hs2 =
-                (ex - (d2 % 3 - 1)) + kHalo * ((ey - ((d2 / 3) % 3 - 1)) + kHalo * (ez - (d2 / 9 - 1)));
-            if (h_canon[hs2] < my) acc += hist[hs2][d2];
+    for (int e = threadIdx.x; e <= ndst; e += kCThreads) {
+        if (e < ndst) {
+            const int ex = e % BX, ey = (e / BX) % BY, ez = e / (BX * BY);
+            s_doff[e] = off_new[canon(g, B0[0] + ex, B0[1] + ey, B0[2] + ez)];
         }
-        pre[dest][d] = acc;
+    }
+    if ((int)threadIdx.x < nrow) {
+        // arrivals of each of the BY*BZ row segments (each contiguous in the new order)
+        const int r = threadIdx.x, ey = r % BY, ez = r / BY;
+        const int64_t first = canon(g, B0[0], B0[1] + ey, B0[2] + ez);
+        s_run[r + 1] = off_new[first + BX] - off_new[first];
     }
     __syncthreads();
-
-    // place every particle whose destination lies in this block
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int s = find_cell(h_pref, kNH, e);
-        const int p = h_start[s] + (e - h_pref[s]);
-        const int d = dir[p];
-        if (d >= 27) continue;
-        const int sx = s % kHalo, sy = (s / kHalo) % kHalo, sz = s / (kHalo * kHalo);
-        const int ex = sx + (d % 3 - 1) - 1, ey = sy + ((d / 3) % 3 - 1) - 1, ez = sz + (d / 9 - 1) - 1;
-        if (ex < 0 || ex >= kCB || ey < 0 || ey >= kCB || ez < 0 || ez >= kCB) continue;
-        const int dest = ex + kCB * (ey + kCB * ez);
-        int rank = 0;
-        for (int q = h_start[s]; q < p; ++q) rank += (dir[q] == d);
-        const int64_t o = (int64_t)d_off[dest] + pre[dest][d] + rank;
-        if (o < 0 || o >= g.n) continue;          // inconsistent counts: never write out of range
+    if (threadIdx.x == 0) {
+        s_run[0] = 0;
+        for (int r = 1; r <= nrow; ++r) s_run[r] += s_run[r - 1];
+    }
+    __syncthreads();
+    // prefix over the source cells (two cells per thread at most)
+    {
+        constexpr int kPer = (kMaxSrc + kCThreads - 1) / kCThreads;
+        int c[kPer], run = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            dst.m[a][o] = src.m[a][p];
-            dst.u[a][o] = src.u[a][p];
+        for (int q = 0; q < kPer; ++q) {
+            const int h = threadIdx.x * kPer + q;
+            c[q] = h < nsrc ? s_cnt[h] : 0;
+            run += c[q];
         }
-        if (dst.ids) dst.ids[o] = src.ids[p];
+        int tot;
+        int base = block_exclusive_scan(run, s_scan, &tot);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int h = threadIdx.x * kPer + q;
+            if (h < nsrc) s_pref[h] = base;
+            base += c[q];
+        }
+        if (threadIdx.x == 0) s_pref[nsrc] = tot;
+    }
+    __syncthreads();
+    // stage the window's move codes in LDS when they fit
+    const int nwin = s_pref[nsrc];
+    const bool staged = nwin <= kDirCap;
+    if (staged)
+        stage_to_lds<kCThreads, 8>(
+            nwin, dir, s_dir,
+            [&](int e) {
+                const int h = find_cell(s_pref, nsrc, e);
+                return s_start[h] + (e - s_pref[h]);
+            },
+            [](int e) { return e; });
+    __syncthreads();
+    auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
+
+    // walk 1: 27-code histogram of every source cell
+    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+        const int n = s_cnt[h];
+        for (int q = 0; q < n; ++q) {
+            const int d = code(h, q);
+            if (d < 27) s_hist[h][d] = (uint16_t)(s_hist[h][d] + 1);
+        }
+    }
+    __syncthreads();
+
+    // arrivals from earlier source cells, per destination and code
+    for (int dcell = threadIdx.x; dcell < ndst; dcell += kCThreads) {
+        const int ex = dcell % BX + 1, ey = (dcell / BX) % BY + 1, ez = dcell / (BX * BY) + 1;
+        int srcs[27];
+        bool lexi = true;        // are the 27 sources ordered like their codes (descending)?
+        int prev = 0x7fffffff;
+        for (int d = 0; d < 27; ++d) {
+            const int hs = (ex - (d % 3 - 1)) + SX * ((ey - ((d / 3) % 3 - 1)) + SY * (ez - (d / 9 - 1)));
+            srcs[d] = hs;
+        }
+        for (int d = 0; d < 27; ++d) {
+            const int c = s_canon[srcs[d]];
+            lexi = lexi && (c < prev);
+            prev = c;
+        }
+        if (lexi) {
+            // canonical order = descending code: suffix sums
+            int acc = 0;
+            for (int d = 26; d >= 0; --d) {
+                s_pre[dcell][d] = acc;
+                acc += s_hist[srcs[d]][d];
+            }
+        } else {
+            // sources span tiles or wrap: order by canonical index in registers
+            int key[27], cnt[27];
+#pragma unroll
+            for (int d = 0; d < 27; ++d) {
+                key[d] = s_canon[srcs[d]];
+                cnt[d] = s_hist[srcs[d]][d];
+            }
+#pragma unroll
+            for (int d = 0; d < 27; ++d) {
+                int acc = 0;
+#pragma unroll
+                for (int d2 = 0; d2 < 27; ++d2) acc += (key[d2] < key[d]) ? cnt[d2] : 0;
+                s_pre[dcell][d] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    // reuse the histogram as running per-code counters
+    for (int h = threadIdx.x; h < nsrc; h += kCThreads)
+#pragma unroll
+        for (int d = 0; d < 27; ++d) s_hist[h][d] = 0;
+    __syncthreads();
+
+    const bool use_slots = s_run[nrow] <= kSlots;
+    // walk 2: slot of every particle that lands in this brick
+    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+        const int st = s_start[h], n = s_cnt[h];
+        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+        for (int q = 0; q < n; ++q) {
+            const int p = st + q;
+            const int d = code(h, q);
+            if (d >= 27) continue;
+            const int rank = s_hist[h][d];
+            s_hist[h][d] = (uint16_t)(rank + 1);
+            const int ex = hx + (d % 3 - 1) - 1, ey = hy + ((d / 3) % 3 - 1) - 1, ez = hz + (d / 9 - 1) - 1;
+            if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) continue;
+            const int dcell = ex + BX * (ey + BY * ez);
+            const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
+            if (use_slots) {
+                const int row = ey + BY * ez;
+                const int first = s_doff[BX * row];
+                const int slot = s_run[row] + (o - first);
+                if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
+            } else if (o >= 0 && o < g.n) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    dst.m[a][o] = src.m[a][p];
+                    dst.u[a][o] = src.u[a][p];
+                }
+                if (dst.ids) dst.ids[o] = src.ids[p];
+            }
+        }
+    }
+    if (!use_slots) return;
+    __syncthreads();
+    // copy run by run: consecutive slots are consecutive outputs
+    const int total = s_run[nrow];
+    constexpr int U = 4;
+    for (int base = 0; base < total; base += kCThreads * U) {
+        uint8_t mv[U][3];
+        int8_t uv[U][3];
+        uint32_t idv[U];
+        int ov[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kCThreads + threadIdx.x;
+            ov[u] = -1;
+            if (i < total) {
+                const int row = find_cell(s_run, nrow, i);
+                const int o = s_doff[BX * row] + (i - s_run[row]);
+                const int p = s_slot[i];
+                if (o >= 0 && o < g.n && p >= 0 && p < g.n) {
+                    ov[u] = o;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        mv[u][a] = src.m[a][p];
+                        uv[u][a] = src.u[a][p];
+                    }
+                    if (dst.ids) idv[u] = src.ids[p];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = ov[u];
+            if (o < 0) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dst.m[a][o] = mv[u][a];
+                dst.u[a][o] = uv[u][a];
+            }
+            if (dst.ids) dst.ids[o] = idv[u];
+        }
     }
 }
 
@@ -146,13 +288,29 @@ __global__ void k_permute(const uint32_t* __restrict__ perm, Planes src, Planes 
     if (dst.ids) dst.ids[j] = src.ids[p];
 }
 
+CompactShape compact_shape(const Geom& g) {
+    CompactShape sh;
+    const int H = g.r / g.f;                       // particles per coarse cell ~ H^3
+    sh.BY = sh.BZ = (H <= 2) ? 2 : 1;
+    int bx = std::min(g.Tc, kMaxBX);
+    while (bx + 2 > g.Nc || g.Tc % bx) bx /= 2;    // the window must not wrap onto itself
+    sh.BX = bx;
+    return sh;
+}
+
 }  // namespace
+
+bool compact_supported(const Geom& g) {
+    const CompactShape sh = compact_shape(g);
+    return sh.BX >= 1 && g.Nc % sh.BX == 0 && g.Nc % sh.BY == 0 && sh.BY + 2 <= g.Nc;
+}
 
 void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new, const uint8_t* dir,
                          Planes src, Planes dst, hipStream_t s) {
-    const int nb = g.Nc / kCB;
-    hipLaunchKernelGGL(k_compact_fast, dim3(nb * nb * nb), dim3(256), 0, s, g, offsets_old, offsets_new, dir, src,
-                       dst);
+    const CompactShape sh = compact_shape(g);
+    const int64_t nb = (int64_t)(g.Nc / sh.BX) * (g.Nc / sh.BY) * (g.Nc / sh.BZ);
+    hipLaunchKernelGGL(k_compact_fast, dim3((unsigned)nb), dim3(kCThreads), 0, s, g, sh, offsets_old, offsets_new,
+                       dir, src, dst);
 }
 
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir, const uint32_t* far_key,

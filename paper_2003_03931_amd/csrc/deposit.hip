@@ -12,6 +12,9 @@
 // and D = 512 / (target cells per coarse cell), so every CIC weight is an
 // integer multiple of 1/D per axis and of 1/D^3 in 3-D.  The FP32 output is
 // round(acc / D^3 / cell_volume - 1), the single rounding of the exact value.
+// A target cell gathers particles of at most 8 coarse cells, each weight at
+// most D^3, so 32-bit accumulators are exact whenever 8 D^3 max_count < 2^32
+// (the caller checks the state's largest cell count); otherwise 64-bit.
 #include "common.h"
 
 namespace cube {
@@ -23,11 +26,11 @@ enum DepositMode { DEP_COARSE = 0, DEP_FINE_TILED = 1, DEP_FINE_PERIODIC = 2, DE
 constexpr int kDepThreads = 256;
 constexpr int kMaxSrc = 1000;   // (BW / cpc + 2)^3 for the largest source window
 
-template <int BW, int MODE>
+template <int BW, int MODE, class ACC>
 __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* __restrict__ offsets, Planes p,
                                                           float* __restrict__ out, int M, int cpc, int log2D,
                                                           double scale, int tile0) {
-    __shared__ unsigned long long acc[BW * BW * BW];
+    __shared__ ACC acc[BW * BW * BW];
     __shared__ int s_start[kMaxSrc];
     __shared__ int s_pref[kMaxSrc + 1];
     __shared__ int s_scan[kDepThreads / kWave + 1];
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         box0[2] = tz * g.Tc - g.hc;
     }
 
-    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) acc[i] = 0;
 
     // per-thread run of up to 4 source cells: counts, then a block scan
     constexpr int kPer = (kMaxSrc + kDepThreads - 1) / kDepThreads;
@@ -98,36 +101,52 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
 
     const int D = 1 << log2D;
     const int halfD = D >> 1;
-    for (int e = threadIdx.x; e < total; e += kDepThreads) {
-        const int s = find_cell(s_pref, nsrc, e);
-        const int pidx = s_start[s] + (e - s_pref[s]);
-        const int rel[3] = {s % nsa[0] - 1, (s / nsa[0]) % nsa[1] - 1, s / (nsa[0] * nsa[1]) - 1};
-        int i0[3];
-        unsigned w1[3];
+    constexpr int U = 4;                       // particles per thread with loads in flight
+    for (int base = 0; base < total; base += kDepThreads * U) {
+        int mm[U][3], src_of[U];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int P = 2 * (rel[k] * 256 + (int)p.m[k][pidx]) + 1;   // units of 1/D target cells
-            const int Pm = P - halfD;
-            i0[k] = Pm >> log2D;                                          // floor division
-            w1[k] = (unsigned)(Pm & (D - 1));
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kDepThreads + threadIdx.x;
+            src_of[u] = -1;
+            if (e < total) {
+                const int s = find_cell(s_pref, nsrc, e);
+                const int pidx = s_start[s] + (e - s_pref[s]);
+                src_of[u] = s;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) mm[u][k] = p.m[k][pidx];
+            }
         }
 #pragma unroll
-        for (int oz = 0; oz < 2; ++oz) {
-            const int iz = i0[2] + oz;
-            if (iz < 0 || iz >= bw[2]) continue;
-            const unsigned wz = oz ? w1[2] : (unsigned)D - w1[2];
+        for (int u = 0; u < U; ++u) {
+            const int s = src_of[u];
+            if (s < 0) continue;
+            const int rel[3] = {s % nsa[0] - 1, (s / nsa[0]) % nsa[1] - 1, s / (nsa[0] * nsa[1]) - 1};
+            int i0[3];
+            unsigned w1[3];
 #pragma unroll
-            for (int oy = 0; oy < 2; ++oy) {
-                const int iy = i0[1] + oy;
-                if (iy < 0 || iy >= bw[1]) continue;
-                const unsigned wyz = (oy ? w1[1] : (unsigned)D - w1[1]) * wz;
+            for (int k = 0; k < 3; ++k) {
+                const int P = 2 * (rel[k] * 256 + mm[u][k]) + 1;   // units of 1/D target cells
+                const int Pm = P - halfD;
+                i0[k] = Pm >> log2D;                                // floor division
+                w1[k] = (unsigned)(Pm & (D - 1));
+            }
 #pragma unroll
-                for (int ox = 0; ox < 2; ++ox) {
-                    const int ix = i0[0] + ox;
-                    if (ix < 0 || ix >= bw[0]) continue;
-                    const unsigned long long w =
-                        (unsigned long long)(ox ? w1[0] : (unsigned)D - w1[0]) * (unsigned long long)wyz;
-                    if (w) atomicAdd(&acc[(iz * BW + iy) * BW + ix], w);
+            for (int oz = 0; oz < 2; ++oz) {
+                const int iz = i0[2] + oz;
+                if (iz < 0 || iz >= bw[2]) continue;
+                const unsigned wz = oz ? w1[2] : (unsigned)D - w1[2];
+#pragma unroll
+                for (int oy = 0; oy < 2; ++oy) {
+                    const int iy = i0[1] + oy;
+                    if (iy < 0 || iy >= bw[1]) continue;
+                    const unsigned wyz = (oy ? w1[1] : (unsigned)D - w1[1]) * wz;
+#pragma unroll
+                    for (int ox = 0; ox < 2; ++ox) {
+                        const int ix = i0[0] + ox;
+                        if (ix < 0 || ix >= bw[0]) continue;
+                        const ACC w = (ACC)(ox ? w1[0] : (unsigned)D - w1[0]) * (ACC)wyz;
+                        if (w) atomicAdd(&acc[(iz * BW + iy) * BW + ix], w);
+                    }
                 }
             }
         }
@@ -141,9 +160,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         const float v = (float)((double)acc[i] * scale - 1.0);
         const int64_t cell = (int64_t)(T0[0] + ix) + (int64_t)M * ((T0[1] + iy) + (int64_t)M * (T0[2] + iz));
         if (MODE == DEP_FINE_TILED || MODE == DEP_FINE_PERIODIC) {
-            const int k = blockIdx.y;          // tile in batch: pair k/2, lane k%2
-            float* mesh = out + (int64_t)(k >> 1) * 2 * (int64_t)M * M * M;
-            mesh[2 * cell + (k & 1)] = v;
+            out[(int64_t)blockIdx.y * M * M * M + cell] = v;     // real mesh of tile k
         } else {
             out[2 * cell] = v;
             out[2 * cell + 1] = 0.0f;
@@ -165,23 +182,34 @@ void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, floa
     const int nb = (g.Nc + BW - 1) / BW;
     // acc in units of 2^-27 particle; density = mass / H^3 with H = r / f
     const double scale = std::ldexp(1.0, -27) * ((double)g.f * g.f * g.f) / ((double)g.r * g.r * g.r);
-    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s, g, offsets, p,
+    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE, unsigned long long>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s,
+                       g, offsets, p,
                        reinterpret_cast<float*>(mesh), g.Nc, 1, 9, scale, 0);
 }
 
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
-                         float* pair_mesh, int32_t* /*overflow*/, hipStream_t s) {
+                         float* mesh, bool wide, hipStream_t s) {
     constexpr int BW = 16;
     const int nb = (g.F + BW - 1) / BW;
     const int log2D = g.log2D;
     // acc in units of D^-3 fine-cell masses; density = mass / h^3 = mass * f^3
     const double scale = std::ldexp(1.0, -3 * log2D) * ((double)g.f * g.f * g.f);
-    if (g.periodic)
-        hipLaunchKernelGGL((k_deposit<BW, DEP_FINE_PERIODIC>), dim3(nb * nb * nb, ntiles), dim3(kDepThreads), 0,
-                           s, g, offsets, p, pair_mesh, g.F, g.r, log2D, scale, tile0);
-    else
-        hipLaunchKernelGGL((k_deposit<BW, DEP_FINE_TILED>), dim3(nb * nb * nb, ntiles), dim3(kDepThreads), 0, s,
-                           g, offsets, p, pair_mesh, g.F, g.r, log2D, scale, tile0);
+    const dim3 grid(nb * nb * nb, ntiles), block(kDepThreads);
+#define CUBE_DEP(MODE, T) \
+    hipLaunchKernelGGL((k_deposit<BW, MODE, T>), grid, block, 0, s, g, offsets, p, mesh, g.F, g.r, log2D, scale, tile0)
+    if (g.periodic) {
+        if (wide) CUBE_DEP(DEP_FINE_PERIODIC, unsigned long long);
+        else CUBE_DEP(DEP_FINE_PERIODIC, unsigned int);
+    } else {
+        if (wide) CUBE_DEP(DEP_FINE_TILED, unsigned long long);
+        else CUBE_DEP(DEP_FINE_TILED, unsigned int);
+    }
+#undef CUBE_DEP
+}
+
+bool fine_deposit_needs_wide(const Geom& g, int max_count) {
+    // 8 coarse cells x D^3 per particle must stay below 2^32
+    return (double)max_count * 8.0 * std::ldexp(1.0, 3 * g.log2D) >= 4294967296.0;
 }
 
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, hipStream_t s) {
@@ -190,7 +218,8 @@ void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2
     const int nb = (g.ns + BW - 1) / BW;
     const int log2D = ilog2(512 / H);
     const double scale = std::ldexp(1.0, -3 * log2D);
-    hipLaunchKernelGGL((k_deposit<BW, DEP_DIAG>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s, g, offsets, p,
+    hipLaunchKernelGGL((k_deposit<BW, DEP_DIAG, unsigned long long>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s,
+                       g, offsets, p,
                        reinterpret_cast<float*>(mesh), g.ns, H, log2D, scale, 0);
 }
 

@@ -145,24 +145,33 @@ struct Dft<8, INV> {
     }
 };
 
-// ---- one Stockham pass over W pencils in LDS -----------------------------
-// Pencil w occupies lds[w*LDN .. w*LDN+N).  NS = product of the radices of
+// ---- one Stockham pass over P pencils in LDS -----------------------------
+// Layout L: P pencils, element i of pencil w at lds[w*SP + i*SE]; with WFAST
+// consecutive threads take consecutive pencils (strided pencils), otherwise
+// consecutive butterflies of one pencil (contiguous pencils), so that lanes
+// touch consecutive LDS words either way.  NS = product of the radices of
 // the passes already done.
-template <int N, int W, bool INV, int NS, int R>
+template <int P_, int SE_, int SP_, bool WFAST_, int NT_>
+struct Lay {
+    static constexpr int P = P_, SE = SE_, SP = SP_, NT = NT_;
+    static constexpr bool WFAST = WFAST_;
+};
+
+template <int N, class L, bool INV, int NS, int R>
 __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw) {
-    constexpr int LDN = N + 1;
     constexpr int NB = N / R;
-    constexpr int TOTAL = NB * W;
-    constexpr int IT = (TOTAL + kFftThreads - 1) / kFftThreads;
+    constexpr int TOTAL = NB * L::P;
+    constexpr int IT = (TOTAL + L::NT - 1) / L::NT;
     float2 v[IT][R];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int b = threadIdx.x + it * kFftThreads;
-        if (TOTAL % kFftThreads == 0 || b < TOTAL) {
-            const int j = b % NB, w = b / NB;
-            const float2* col = lds + w * LDN;
+        const int b = threadIdx.x + it * L::NT;
+        if (TOTAL % L::NT == 0 || b < TOTAL) {
+            const int j = L::WFAST ? b / L::P : b % NB;
+            const int w = L::WFAST ? b % L::P : b / NB;
+            const float2* col = lds + w * L::SP;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = col[j + r * NB];
+            for (int r = 0; r < R; ++r) v[it][r] = col[(j + r * NB) * L::SE];
             if (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
@@ -177,25 +186,26 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int b = threadIdx.x + it * kFftThreads;
-        if (TOTAL % kFftThreads == 0 || b < TOTAL) {
-            const int j = b % NB, w = b / NB;
+        const int b = threadIdx.x + it * L::NT;
+        if (TOTAL % L::NT == 0 || b < TOTAL) {
+            const int j = L::WFAST ? b / L::P : b % NB;
+            const int w = L::WFAST ? b % L::P : b / NB;
             const int k = j % NS;
-            float2* col = lds + w * LDN + (j / NS) * NS * R + k;
+            float2* col = lds + w * L::SP + ((j / NS) * NS * R + k) * L::SE;
 #pragma unroll
-            for (int r = 0; r < R; ++r) col[r * NS] = v[it][r];
+            for (int r = 0; r < R; ++r) col[r * NS * L::SE] = v[it][r];
         }
     }
     __syncthreads();
 }
 
-template <int N, int W, bool INV, int NS>
+template <int N, class L, bool INV, int NS>
 __device__ __forceinline__ void run_passes(float2*, const float2*) {}
 
-template <int N, int W, bool INV, int NS, int R, int... Rest>
+template <int N, class L, bool INV, int NS, int R, int... Rest>
 __device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw) {
-    stockham_pass<N, W, INV, NS, R>(lds, tw);
-    run_passes<N, W, INV, NS * R, Rest...>(lds, tw);
+    stockham_pass<N, L, INV, NS, R>(lds, tw);
+    run_passes<N, L, INV, NS * R, Rest...>(lds, tw);
 }
 
 // Radix plan per supported size.
@@ -204,9 +214,9 @@ struct Plan;
 #define CUBE_FFT_PLAN(NN, ...)                                                   \
     template <>                                                                  \
     struct Plan<NN> {                                                            \
-        template <int W, bool INV>                                               \
+        template <class L, bool INV>                                             \
         __device__ static void run(float2* lds, const float2* __restrict__ tw) { \
-            run_passes<NN, W, INV, 1, __VA_ARGS__>(lds, tw);                     \
+            run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw);                     \
         }                                                                        \
     };
 CUBE_FFT_PLAN(16, 4, 4)
@@ -263,16 +273,22 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
         }
     }
     float2* g = cube_base + base;
-    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
-        int i, w;
-        if (KIND == 0) { i = e % N; w = e / N; } else { w = e % W; i = e / W; }
-        lds[w * LDN + i] = g[i * stride_i + w * stride_w];
-    }
+    stage_to_lds<kFftThreads, 8>(
+        W * N, g, lds,
+        [&](int e) {
+            const int i = KIND == 0 ? e % N : e / W, w = KIND == 0 ? e / N : e % W;
+            return (int64_t)i * stride_i + (int64_t)w * stride_w;
+        },
+        [&](int e) {
+            const int i = KIND == 0 ? e % N : e / W, w = KIND == 0 ? e / N : e % W;
+            return w * LDN + i;
+        });
     __syncthreads();
+    using L = Lay<W, 1, LDN, false, kFftThreads>;
     if (MODE == 1) {
-        Plan<N>::template run<W, true>(lds, tw);
+        Plan<N>::template run<L, true>(lds, tw);
     } else {
-        Plan<N>::template run<W, false>(lds, tw);
+        Plan<N>::template run<L, false>(lds, tw);
     }
     if (MODE >= 2) {
         // multiply by G(kx, ky, kz): this block holds kz = i, ky = yz, kx = x0 + w
@@ -292,12 +308,197 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
             lds[w * LDN + i] = v;
         }
         __syncthreads();
-        Plan<N>::template run<W, true>(lds, tw);
+        Plan<N>::template run<L, true>(lds, tw);
     }
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
         int i, w;
         if (KIND == 0) { i = e % N; w = e / N; } else { w = e % W; i = e / W; }
         g[i * stride_i + w * stride_w] = lds[w * LDN + i];
+    }
+}
+
+// ---- real tile meshes: R2C / C2R through xy planes ---------------------
+// A tile's real mesh [z][y][x] (N^3 floats) maps to a half spectrum
+// [kz][ky][kx], kx in [0, N/2] (N^2 (N/2+1) complex).  One workgroup owns a
+// whole z-plane in LDS: rows 2j and 2j+1 are transformed together as one
+// complex row and separated with the Hermitian symmetry, then the N/2+1
+// columns are transformed along y.  The inverse runs the same steps backwards.
+constexpr int kPlaneThreads = 512;
+
+template <int N>
+__global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __restrict__ real_tiles,
+                                                             float2* __restrict__ spec_tiles,
+                                                             const float2* __restrict__ tw) {
+    constexpr int NH = N / 2 + 1;
+    constexpr int HALF = N / 2;
+    __shared__ float2 lds[N * NH];
+    const int z = blockIdx.x;
+    const float* src = real_tiles + (int64_t)blockIdx.y * N * N * N + (int64_t)z * N * N;
+    // rows 2j (real part) and 2j+1 (imaginary part) -> complex row j
+    {
+        constexpr int TOT = HALF * N;
+        constexpr int U = 16;
+        for (int base = 0; base < TOT; base += kPlaneThreads * U) {
+            float re[U], im[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * kPlaneThreads + threadIdx.x;
+                if (e < TOT) {
+                    const int j = e / N, x = e % N;
+                    re[u] = src[(2 * j) * N + x];
+                    im[u] = src[(2 * j + 1) * N + x];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * kPlaneThreads + threadIdx.x;
+                if (e < TOT) lds[e] = make_float2(re[u], im[u]);
+            }
+        }
+    }
+    __syncthreads();
+    Plan<N>::template run<Lay<HALF, 1, N, false, kPlaneThreads>, false>(lds, tw);
+    // separate the two real rows' spectra: A = (Z(k) + conj Z(N-k)) / 2, B = (Z(k) - conj Z(N-k)) / 2i
+    constexpr int SEP = HALF * NH;
+    constexpr int IT = (SEP + kPlaneThreads - 1) / kPlaneThreads;
+    float2 va[IT], vb[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kPlaneThreads;
+        if (e < SEP) {
+            const int j = e / NH, k = e % NH;
+            const float2 z1 = lds[j * N + k];
+            const float2 z2 = lds[j * N + (k == 0 ? 0 : N - k)];
+            va[it] = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+            vb[it] = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kPlaneThreads;
+        if (e < SEP) {
+            const int j = e / NH, k = e % NH;
+            lds[(2 * j) * NH + k] = va[it];
+            lds[(2 * j + 1) * NH + k] = vb[it];
+        }
+    }
+    __syncthreads();
+    Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, false>(lds, tw);
+    float2* dst = spec_tiles + (int64_t)blockIdx.y * N * N * NH + (int64_t)z * N * NH;
+    for (int e = threadIdx.x; e < N * NH; e += kPlaneThreads) dst[e] = lds[e];
+}
+
+template <int N>
+__global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __restrict__ spec_tiles,
+                                                             float* __restrict__ real_tiles,
+                                                             const float2* __restrict__ tw) {
+    constexpr int NH = N / 2 + 1;
+    constexpr int HALF = N / 2;
+    __shared__ float2 lds[N * NH];
+    const int z = blockIdx.x;
+    const float2* src = spec_tiles + (int64_t)blockIdx.y * N * N * NH + (int64_t)z * N * NH;
+    stage_to_lds<kPlaneThreads, 16>(N * NH, src, lds, [](int e) { return e; }, [](int e) { return e; });
+    __syncthreads();
+    Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, true>(lds, tw);
+    // rebuild complex rows Z = A + iB over the full k range (Hermitian extension)
+    constexpr int ROWS = HALF * N;
+    constexpr int IT = (ROWS + kPlaneThreads - 1) / kPlaneThreads;
+    float2 vz[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kPlaneThreads;
+        if (e < ROWS) {
+            const int j = e / N, k = e % N;
+            float2 a, b;
+            if (k <= HALF) {
+                a = lds[(2 * j) * NH + k];
+                b = lds[(2 * j + 1) * NH + k];
+            } else {
+                const float2 ac = lds[(2 * j) * NH + (N - k)];
+                const float2 bc = lds[(2 * j + 1) * NH + (N - k)];
+                a = make_float2(ac.x, -ac.y);
+                b = make_float2(bc.x, -bc.y);
+            }
+            vz[it] = make_float2(a.x - b.y, a.y + b.x);      // a + i b
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kPlaneThreads;
+        if (e < ROWS) lds[e] = vz[it];                      // row j at j*N + k
+    }
+    __syncthreads();
+    Plan<N>::template run<Lay<HALF, 1, N, false, kPlaneThreads>, true>(lds, tw);
+    float* dst = real_tiles + (int64_t)blockIdx.y * N * N * N + (int64_t)z * N * N;
+    for (int e = threadIdx.x; e < HALF * N; e += kPlaneThreads) {
+        const int j = e / N, x = e % N;
+        const float2 v = lds[j * N + x];
+        dst[(2 * j) * N + x] = v.x;
+        dst[(2 * j + 1) * N + x] = v.y;
+    }
+}
+
+// z pencils of the half spectrum: forward, times G (float octant), inverse.
+template <int N>
+__global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__ spec_tiles,
+                                                            const float2* __restrict__ tw,
+                                                            const float* __restrict__ green) {
+    constexpr int NH = N / 2 + 1;
+    constexpr int W = 16;
+    constexpr int LDN = N + 1;
+    constexpr int PLANE = N * NH;
+    __shared__ float2 lds[W * LDN];
+    const int c0 = blockIdx.x * W;                 // flattened (ky, kx) of the first pencil
+    float2* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
+    stage_to_lds<kFftThreads, 10>(
+        W * N, g, lds, [](int e) { return (int64_t)(e / W) * PLANE + (e % W); },
+        [](int e) { return (e % W) * LDN + e / W; });
+    __syncthreads();
+    using L = Lay<W, 1, LDN, false, kFftThreads>;
+    Plan<N>::template run<L, false>(lds, tw);
+    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+        const int w = e % W, i = e / W;
+        const int c = c0 + w;
+        const int ky = c / NH, kx = c - ky * NH;
+        const float gv = green[((int64_t)fold(i, N) * NH + fold(ky, N)) * NH + kx];
+        const float2 v = lds[w * LDN + i];
+        lds[w * LDN + i] = make_float2(v.x * gv, v.y * gv);
+    }
+    __syncthreads();
+    Plan<N>::template run<L, true>(lds, tw);
+    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+        const int w = e % W, i = e / W;
+        g[(int64_t)i * PLANE + w] = lds[w * LDN + i];
+    }
+}
+
+template <int N>
+void launch_tiles(float* real_tiles, float2* spec_tiles, int ntiles, const float2* tw, const float* green,
+                  hipStream_t s, hipEvent_t* ev) {
+    constexpr int NH = N / 2 + 1;
+    if (ev) hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(k_r2c_plane<N>, dim3(N, ntiles), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw);
+    if (ev) hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL(k_zconv_half<N>, dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw, green);
+    if (ev) hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL(k_c2r_plane<N>, dim3(N, ntiles), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw);
+    if (ev) hipEventRecord(ev[3], s);
+}
+
+using TilesFn = void (*)(float*, float2*, int, const float2*, const float*, hipStream_t, hipEvent_t*);
+
+TilesFn tiles_for(int n) {
+    switch (n) {
+        case 32: return launch_tiles<32>;
+        case 48: return launch_tiles<48>;
+        case 64: return launch_tiles<64>;
+        case 96: return launch_tiles<96>;
+        case 128: return launch_tiles<128>;
+        case 160: return launch_tiles<160>;
+        case 192: return launch_tiles<192>;
+        default: return nullptr;
     }
 }
 
@@ -349,6 +550,13 @@ PassFn pass_for(int n) {
 }  // namespace
 
 bool fft_supported(int n) { return pass_for(n) != nullptr; }
+
+bool fft_tiles_supported(int n) { return tiles_for(n) != nullptr; }
+
+void fft_tiles_convolve(float* real_tiles, float2* spec_tiles, int n, int ntiles, const float2* tw,
+                        const float* green_octant, hipStream_t s, hipEvent_t* ev) {
+    tiles_for(n)(real_tiles, spec_tiles, ntiles, tw, green_octant, s, ev);
+}
 
 void fft_make_twiddles(int n, float2* dev_table, hipStream_t s) {
     std::vector<float2> h(n);

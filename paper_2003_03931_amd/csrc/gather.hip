@@ -2,51 +2,49 @@
 // long-range coarse-mesh part plus the short-range part of the particle's own
 // tile; Sec. III-A: positions and velocities are re-encoded after the update).
 //
-// One workgroup per chunk (an x-row of coarse cells of one tile), whose
-// particles are contiguous.  For each particle:
-//   * decode (Eq. (2)) into fine-box and coarse coordinates, exactly;
-//   * a = CIC-gather of -grad phi_f (tile box) + CIC-gather of -grad phi_c,
-//     the gradients taken by 2-point central differences on the fly from the
-//     potentials (no force mesh is stored);
+// One workgroup per brick of 32 x 16 x 8 fine cells of one tile.  It stages
+// the tile's fine potential over the brick plus a 2-cell halo and the coarse
+// potential over the brick's coarse cells plus a 2-cell halo in LDS, then
+// walks the brick's particles (its coarse cells' contiguous ranges):
+//   * decode (Eq. (2)) into fine and coarse coordinates, exactly;
+//   * a = CIC-gather of -grad phi_f + CIC-gather of -grad phi_c, gradients by
+//     2-point central differences taken on the fly from the LDS potentials;
 //   * kick in FP64:  u' = clamp(rint((u s + a dt) / s'), -127, 127);
 //   * drift in cell-local quanta, exactly in FP64:
 //       X = m + 1/2 + ((u' s') (256/H)) dt,  q = floor(X),
 //       carry = floor(q / 256), m' = q mod 256, cell' = cell + carry (periodic);
-//   * write (m', u') at the same index of the second particle buffer, a move
-//     code for the compaction and one count for the new cell.
+//   * write (m', u') at the same index of the second particle buffer and a
+//     move code for the compaction; new-cell counts go to an LDS histogram
+//     over the brick's cells plus one cell, flushed once per brick.
 #include "common.h"
 
 namespace cube {
 
 namespace {
 
-struct FinePhi {
-    const float* p;   // pair-packed complex mesh: value at 2*idx
-    int F;
-    bool wrap;
-    __device__ float at(int x, int y, int z) const {
-        if (wrap) { x = wrapi(x, F); y = wrapi(y, F); z = wrapi(z, F); }
-        return p[2 * (((int64_t)z * F + y) * F + x)];
-    }
-};
+constexpr int kBX = 32, kBY = 16, kBZ = 8;              // brick, fine cells
+constexpr int kLX = kBX + 4, kLY = kBY + 4, kLZ = kBZ + 4;
+constexpr int kFineLds = kLX * kLY * kLZ;                // 8640 floats
+constexpr int kMinR = 4;                                 // coarse cells of >= 4 fine cells
+constexpr int kMaxCoarseLds = (kBX / kMinR + 4) * (kBY / kMinR + 4) * (kBZ / kMinR + 4);
+constexpr int kMaxRows = (kBY / kMinR) * (kBZ / kMinR);
+constexpr int kMaxRowLen = kBX / kMinR;
+constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
+constexpr int kGatherThreads = 256;
 
-struct CoarsePhi {
+struct LdsGrid {
     const float* p;
-    int N;
-    __device__ float at(int x, int y, int z) const {
-        x = wrapi(x, N); y = wrapi(y, N); z = wrapi(z, N);
-        return p[2 * (((int64_t)z * N + y) * N + x)];
-    }
+    int sx, sxy;      // strides
+    __device__ float at(int x, int y, int z) const { return p[(z * sxy) + y * sx + x]; }
 };
 
-// CIC gather of -grad(phi) with 2-point differences; i0/t per axis, inv2h = 1/(2 cell).
-template <class Phi>
-__device__ __forceinline__ void gather_force(const Phi& phi, const int i0[3], const float t[3], float inv2h,
+// CIC gather of -grad(phi): i0/t per axis in LDS-grid coordinates.
+__device__ __forceinline__ void gather_force(const LdsGrid& phi, const int i0[3], const float t[3], float inv2h,
                                              float out[3]) {
     const float w[3][2] = {{1.0f - t[0], t[0]}, {1.0f - t[1], t[1]}, {1.0f - t[2], t[2]}};
     float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
-    for (int oz = 0; oz < 2; ++oz) {
+    for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
         for (int oy = 0; oy < 2; ++oy) {
             const int y = i0[1] + oy, z = i0[2] + oz;
@@ -54,9 +52,8 @@ __device__ __forceinline__ void gather_force(const Phi& phi, const int i0[3], co
             const float x1 = phi.at(i0[0] + 1, y, z), x2 = phi.at(i0[0] + 2, y, z);
             ax += w[1][oy] * w[2][oz] * (w[0][0] * (xm - x1) + w[0][1] * (x0 - x2));
         }
-    }
 #pragma unroll
-    for (int oz = 0; oz < 2; ++oz) {
+    for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
         for (int ox = 0; ox < 2; ++ox) {
             const int x = i0[0] + ox, z = i0[2] + oz;
@@ -64,9 +61,8 @@ __device__ __forceinline__ void gather_force(const Phi& phi, const int i0[3], co
             const float y1 = phi.at(x, i0[1] + 1, z), y2 = phi.at(x, i0[1] + 2, z);
             ay += w[0][ox] * w[2][oz] * (w[1][0] * (ym - y1) + w[1][1] * (y0 - y2));
         }
-    }
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy) {
+    for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
         for (int ox = 0; ox < 2; ++ox) {
             const int x = i0[0] + ox, y = i0[1] + oy;
@@ -74,14 +70,12 @@ __device__ __forceinline__ void gather_force(const Phi& phi, const int i0[3], co
             const float z1 = phi.at(x, y, i0[2] + 1), z2 = phi.at(x, y, i0[2] + 2);
             az += w[0][ox] * w[1][oy] * (w[2][0] * (zm - z1) + w[2][1] * (z0 - z2));
         }
-    }
     out[0] = ax * inv2h;
     out[1] = ay * inv2h;
     out[2] = az * inv2h;
 }
 
-template <class Phi>
-__device__ __forceinline__ float gather_value(const Phi& phi, const int i0[3], const float t[3]) {
+__device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3], const float t[3]) {
     float acc = 0.f;
 #pragma unroll
     for (int oz = 0; oz < 2; ++oz)
@@ -95,48 +89,142 @@ __device__ __forceinline__ float gather_value(const Phi& phi, const int i0[3], c
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
-    extern __shared__ int offs[];
-    __shared__ double s_red[256 / kWave];
+__global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
+    __shared__ float s_fine[kFineLds];
+    __shared__ float s_coarse[kMaxCoarseLds];
+    __shared__ int s_rowoff[kMaxRows][kMaxRowLen + 1];
+    __shared__ int s_rowpref[kMaxRows + 1];
+    __shared__ int s_hist[kMaxHist];
+    __shared__ int s_scan[kGatherThreads / kWave + 1];
+    __shared__ double s_red[kGatherThreads / kWave];
+
     const Geom& g = A.g;
-    const int k = blockIdx.y;                        // tile within the batch
+    const int r = g.r;
+    const int BXc = kBX / r, BYc = kBY / r, BZc = kBZ / r;
+    const int nrows = BYc * BZc;
+    const int k = blockIdx.y;                              // tile within the batch
     const int tile = A.tile0 + k;
-    const int64_t q = (int64_t)tile * g.Tc * g.Tc + blockIdx.x;
-    const Chunk ch = chunk_of(g, q);
-    for (int j = threadIdx.x; j <= g.Tc; j += blockDim.x) offs[j] = A.offsets[ch.c0 + j];
+    const int nbx = g.T / kBX, nby = g.T / kBY;
+    const int b = blockIdx.x;
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int tx = tile % g.nt, ty = (tile / g.nt) % g.nt, tz = tile / (g.nt * g.nt);
+    // brick origin: tile-local fine and coarse coordinates, global coarse
+    const int lf[3] = {bx * kBX, by * kBY, bz * kBZ};
+    const int lc[3] = {lf[0] / r, lf[1] / r, lf[2] / r};
+    const int gc[3] = {tx * g.Tc + lc[0], ty * g.Tc + lc[1], tz * g.Tc + lc[2]};
+
+    // fine potential of the brick plus 2 cells: tile-box coords b + lf - 2 ...
+    const float* fmesh = A.fine_real + (int64_t)k * g.F * g.F * g.F;   // tile k of the batch
+    const int F = g.F, ox = g.b + lf[0] - 2, oy = g.b + lf[1] - 2, oz = g.b + lf[2] - 2;
+    const bool per = g.periodic != 0;
+    stage_to_lds<kGatherThreads, 16>(
+        kFineLds, fmesh, s_fine,
+        [=](int e) {
+            int fx = ox + e % kLX, fy = oy + (e / kLX) % kLY, fz = oz + e / (kLX * kLY);
+            if (per) {
+                fx = fx < 0 ? fx + F : (fx >= F ? fx - F : fx);
+                fy = fy < 0 ? fy + F : (fy >= F ? fy - F : fy);
+                fz = fz < 0 ? fz + F : (fz >= F ? fz - F : fz);
+            }
+            return ((int64_t)fz * F + fy) * F + fx;
+        },
+        [](int e) { return e; });
+    // coarse potential of the brick's coarse cells plus 2 (periodic)
+    const int CX = BXc + 4, CY = BYc + 4, CZ = BZc + 4;
+    const float* cmesh = reinterpret_cast<const float*>(A.coarse);
+    const int Nc = g.Nc, cx0 = gc[0] - 2, cy0 = gc[1] - 2, cz0 = gc[2] - 2;
+    stage_to_lds<kGatherThreads, 4>(
+        CX * CY * CZ, cmesh, s_coarse,
+        [=](int e) {
+            int cx = cx0 + e % CX, cy = cy0 + (e / CX) % CY, cz = cz0 + e / (CX * CY);
+            cx = cx < 0 ? cx + Nc : (cx >= Nc ? cx - Nc : cx);
+            cy = cy < 0 ? cy + Nc : (cy >= Nc ? cy - Nc : cy);
+            cz = cz < 0 ? cz + Nc : (cz >= Nc ? cz - Nc : cz);
+            return 2 * (((int64_t)cz * Nc + cy) * Nc + cx);
+        },
+        [](int e) { return e; });
+    // particle ranges: rows of BXc contiguous cells
+    for (int e = threadIdx.x; e < nrows * (BXc + 1); e += kGatherThreads) {
+        const int row = e / (BXc + 1), j = e % (BXc + 1);
+        const int ry = row % BYc, rz = row / BYc;
+        const int64_t c0 = canon(g, gc[0], gc[1] + ry, gc[2] + rz);
+        s_rowoff[row][j] = A.offsets[c0 + j];
+    }
+    const int HX = BXc + 2, HY = BYc + 2, HZ = BZc + 2;
+    if (MODE == GATHER_STEP)
+        for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) s_hist[e] = 0;
+    __syncthreads();
+    {
+        const int row = threadIdx.x;
+        const int cnt = row < nrows ? s_rowoff[row][BXc] - s_rowoff[row][0] : 0;
+        int total;
+        const int pref = block_exclusive_scan(cnt, s_scan, &total);
+        if (row < nrows) s_rowpref[row] = pref;
+        if (row == 0) s_rowpref[nrows] = total;
+    }
     __syncthreads();
 
-    const FinePhi fphi{A.fine_pairs + (int64_t)(k >> 1) * 2 * (int64_t)g.F * g.F * g.F + (k & 1), g.F,
-                       g.periodic != 0};
-    const CoarsePhi cphi{reinterpret_cast<const float*>(A.coarse), g.Nc};
+    const LdsGrid fphi{s_fine, kLX, kLX * kLY};
+    const LdsGrid cphi{s_coarse, CX, CX * CY};
     const int D = 1 << g.log2D, halfD = D >> 1;
     const float invD = 1.0f / (float)D;
     const float inv2h = (float)g.f * 0.5f;                   // 1 / (2h)
-    const float inv2H = (float)g.f / (2.0f * (float)g.r);    // 1 / (2H)
-
-    double s = 0.0, s_next = 0.0;
-    if (MODE == GATHER_STEP) { s = A.sc->s; s_next = A.sc->s_next; }
-    const double q256H = 256.0 * g.f / g.r;                  // 256 / H
+    const float inv2H = (float)g.f / (2.0f * (float)r);      // 1 / (2H)
+    double s = 0.0, s_next = 0.0, inv_s_next = 0.0;
+    if (MODE == GATHER_STEP) {
+        s = A.sc->s;
+        s_next = A.sc->s_next;
+        inv_s_next = 1.0 / s_next;                           // exact: s' is a power of two
+    }
+    const double q256H = 256.0 * g.f / r;                    // 256 / H
     const double dt = (double)A.dt;
 
     int umax = 0, sat = 0, cmax = 0, nfar = 0;
     double esum = 0.0;
-    for (int p = offs[0] + threadIdx.x; p < offs[g.Tc]; p += blockDim.x) {
-        const int j = find_cell(offs, g.Tc, p);
-        const int cell[3] = {ch.cx0 + j, ch.cy, ch.cz};
-        const int cbox[3] = {j + g.hc, ch.ly + g.hc, ch.lz + g.hc};   // tile-box coarse coords
-        int m[3];
+    const int total = s_rowpref[nrows];
+    // software pipeline: the next particle's bytes are in flight while the
+    // current one is computed
+    auto locate = [&](int e, int& p, int& lx, int& ly, int& lz) {
+        const int row = find_cell(s_rowpref, nrows, e);
+        p = s_rowoff[row][0] + (e - s_rowpref[row]);
+        lx = find_cell(s_rowoff[row], BXc, p);
+        ly = row % BYc;
+        lz = row / BYc;
+    };
+    int np_ = 0, nlx = 0, nly = 0, nlz = 0, nm[3] = {0, 0, 0}, nu[3] = {0, 0, 0};
+    if ((int)threadIdx.x < total) {
+        locate(threadIdx.x, np_, nlx, nly, nlz);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) m[a] = A.in.m[a][p];
+        for (int a = 0; a < 3; ++a) {
+            nm[a] = A.in.m[a][np_];
+            if (MODE == GATHER_STEP) nu[a] = A.in.u[a][np_];
+        }
+    }
+    for (int e = threadIdx.x; e < total; e += kGatherThreads) {
+        const int p = np_;
+        const int lcell[3] = {nlx, nly, nlz};                // cell within the brick
+        int m[3], uo[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { m[a] = nm[a]; uo[a] = nu[a]; }
+        if (e + kGatherThreads < total) {
+            locate(e + kGatherThreads, np_, nlx, nly, nlz);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nm[a] = A.in.m[a][np_];
+                if (MODE == GATHER_STEP) nu[a] = A.in.u[a][np_];
+            }
+        }
         int fi[3], ci[3];
         float ft[3], ct[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int Pf = 2 * (cbox[a] * 256 + m[a]) + 1 - halfD;
-            fi[a] = Pf >> g.log2D;
+            // fine: brick-relative position in 1/D cells, LDS origin at -2
+            const int Pf = 2 * (lcell[a] * 256 + m[a]) + 1 - halfD;
+            fi[a] = (Pf >> g.log2D) + 2;
             ft[a] = (float)(Pf & (D - 1)) * invD;
-            const int Pc = 2 * (cell[a] * 256 + m[a]) + 1 - 256;
-            ci[a] = Pc >> 9;
+            // coarse: brick-relative in 1/512 coarse cells, LDS origin at -2
+            const int Pc = 2 * (lcell[a] * 256 + m[a]) + 1 - 256;
+            ci[a] = (Pc >> 9) + 2;
             ct[a] = (float)(Pc & 511) * (1.0f / 512.0f);
         }
         if (MODE == GATHER_POTENTIAL) {
@@ -152,53 +240,81 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
             for (int a = 0; a < 3; ++a) A.acc[3 * (int64_t)p + a] = acc[a];
             continue;
         }
-        // kick (FP64) and requantise
-        int un[3], carry[3], mn[3];
+        // kick (FP64) and requantise; drift in cell-local quanta (exact FP64)
+        int un[3], carry[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double v = (double)A.in.u[a][p] * s + (double)acc[a] * dt;
-            double w = rint(v / s_next);
+            const double v = (double)uo[a] * s + (double)acc[a] * dt;
+            double w = rint(v * inv_s_next);
             sat += fabs(w) > 127.0;
             w = fmin(fmax(w, -127.0), 127.0);
             un[a] = (int)w;
             umax = max(umax, abs(un[a]));
-            // drift in cell-local quanta, exact in FP64
             const double X = ((double)m[a] + 0.5) + (((double)un[a] * s_next) * q256H) * dt;
             const int qq = (int)floor(X);
             carry[a] = qq >> 8;                  // floor division by 256
-            mn[a] = qq & 255;
+            A.out.m[a][p] = (uint8_t)(qq & 255);
+            A.out.u[a][p] = (int8_t)un[a];
             cmax = max(cmax, abs(carry[a]));
         }
-        int nc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            nc[a] = wrapi(cell[a] + carry[a], g.Nc);
-            A.out.m[a][p] = (uint8_t)mn[a];
-            A.out.u[a][p] = (int8_t)un[a];
-        }
         if (A.out.ids) A.out.ids[p] = A.in.ids[p];
-        const int64_t cn = canon(g, nc[0], nc[1], nc[2]);
-        atomicAdd(&A.counts_new[cn], 1);
         const bool near = abs(carry[0]) <= 1 && abs(carry[1]) <= 1 && abs(carry[2]) <= 1;
         if (near) {
             A.dir[p] = (uint8_t)((carry[0] + 1) + 3 * (carry[1] + 1) + 9 * (carry[2] + 1));
+            const int hx = lcell[0] + carry[0] + 1, hy = lcell[1] + carry[1] + 1, hz = lcell[2] + carry[2] + 1;
+            atomicAdd(&s_hist[(hz * HY + hy) * HX + hx], 1);
         } else {
+            const int64_t cn = canon(g, wrapi(gc[0] + lcell[0] + carry[0], g.Nc),
+                                     wrapi(gc[1] + lcell[1] + carry[1], g.Nc),
+                                     wrapi(gc[2] + lcell[2] + carry[2], g.Nc));
             A.dir[p] = 255;
             A.far_key[p] = (uint32_t)cn;
+            atomicAdd(&A.counts_new[cn], 1);
             ++nfar;
         }
     }
 
     if (MODE == GATHER_STEP) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) {
+            const int c = s_hist[e];
+            if (c) {
+                const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+                int cx = gc[0] + hx - 1, cy = gc[1] + hy - 1, cz = gc[2] + hz - 1;
+                cx = cx < 0 ? cx + g.Nc : (cx >= g.Nc ? cx - g.Nc : cx);
+                cy = cy < 0 ? cy + g.Nc : (cy >= g.Nc ? cy - g.Nc : cy);
+                cz = cz < 0 ? cz + g.Nc : (cz >= g.Nc ? cz - g.Nc : cz);
+                const int64_t cn = canon(g, cx, cy, cz);
+                atomicAdd(&A.counts_new[cn], c);
+            }
+        }
+        // block reduction, then one atomic per block into one of 64 slots
+        __shared__ int s_r[4][kGatherThreads / kWave];
         umax = wave_max(umax);
         cmax = wave_max(cmax);
         sat = wave_sum(sat);
         nfar = wave_sum(nfar);
         if ((threadIdx.x & (kWave - 1)) == 0) {
-            if (umax) atomicMax(&A.sc->max_u_next, umax);
-            if (cmax) atomicMax(&A.sc->max_carry, cmax);
-            if (sat) atomicAdd((unsigned long long*)&A.sc->saturations, (unsigned long long)sat);
-            if (nfar) atomicAdd(&A.sc->far_count, nfar);
+            const int w = threadIdx.x / kWave;
+            s_r[0][w] = umax;
+            s_r[1][w] = cmax;
+            s_r[2][w] = sat;
+            s_r[3][w] = nfar;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int bu = 0, bc = 0, bs = 0, bf = 0;
+            for (int w = 0; w < kGatherThreads / kWave; ++w) {
+                bu = max(bu, s_r[0][w]);
+                bc = max(bc, s_r[1][w]);
+                bs += s_r[2][w];
+                bf += s_r[3][w];
+            }
+            const int slot = (blockIdx.x + blockIdx.y * 7) & 63;
+            if (bu) atomicMax(&A.sc->umax_slot[slot], bu);
+            if (bc) atomicMax(&A.sc->cmax_slot[slot], bc);
+            if (bs) atomicAdd((unsigned long long*)&A.sc->saturations, (unsigned long long)bs);
+            if (bf) atomicAdd(&A.sc->far_count, bf);
         }
     } else if (MODE == GATHER_POTENTIAL) {
         esum = wave_sum_d(esum);
@@ -206,7 +322,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
-            for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += s_red[w];
+            for (int w = 0; w < kGatherThreads / kWave; ++w) t += s_red[w];
             A.partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
         }
     }
@@ -214,15 +330,20 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
 
 }  // namespace
 
+int gather_blocks_per_tile(const Geom& g) { return (g.T / kBX) * (g.T / kBY) * (g.T / kBZ); }
+
+bool gather_supported(const Geom& g) {
+    return g.T % kBX == 0 && g.T % kBY == 0 && g.r >= kMinR && kBZ % g.r == 0;
+}
+
 void launch_gather(const GatherArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)(a.g.Tc * a.g.Tc), a.ntiles);
-    const size_t shm = (a.g.Tc + 1) * sizeof(int);
+    const dim3 grid((unsigned)gather_blocks_per_tile(a.g), a.ntiles);
     if (a.mode == GATHER_STEP)
-        hipLaunchKernelGGL(k_gather<GATHER_STEP>, grid, dim3(256), shm, s, a);
+        hipLaunchKernelGGL(k_gather<GATHER_STEP>, grid, dim3(kGatherThreads), 0, s, a);
     else if (a.mode == GATHER_FORCE)
-        hipLaunchKernelGGL(k_gather<GATHER_FORCE>, grid, dim3(256), shm, s, a);
+        hipLaunchKernelGGL(k_gather<GATHER_FORCE>, grid, dim3(kGatherThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_gather<GATHER_POTENTIAL>, grid, dim3(256), shm, s, a);
+        hipLaunchKernelGGL(k_gather<GATHER_POTENTIAL>, grid, dim3(kGatherThreads), 0, s, a);
 }
 
 }  // namespace cube

@@ -28,10 +28,17 @@ struct Geom {
     int64_t ncells;   // Nc^3
     int64_t n;        // ns^3 particles
     int ntiles;       // nt^3
+    int tc_shift;     // log2(Tc) when Tc is a power of two, else -1
+    int nt_shift;     // log2(nt) when nt is a power of two, else -1
 };
 
 // Canonical cell index: tile-major (tile index x fastest), x fastest inside.
 __host__ __device__ inline int64_t canon(const Geom& g, int cx, int cy, int cz) {
+    if (g.tc_shift >= 0 && g.nt_shift >= 0) {
+        const int s = g.tc_shift, m = g.Tc - 1, ns = g.nt_shift;
+        const int64_t tile = (cx >> s) + ((int64_t)((cy >> s) + ((cz >> s) << ns)) << ns);
+        return (tile << (3 * s)) + (cx & m) + ((int64_t)((cy & m) + ((cz & m) << s)) << s);
+    }
     int tx = cx / g.Tc, ty = cy / g.Tc, tz = cz / g.Tc;
     int lx = cx - tx * g.Tc, ly = cy - ty * g.Tc, lz = cz - tz * g.Tc;
     int64_t tile = tx + (int64_t)g.nt * (ty + (int64_t)g.nt * tz);
@@ -53,7 +60,11 @@ struct StepScalars {
     int32_t max_carry;   // max |carry| of the step
     int64_t saturations; // clamped velocity components (cumulative)
     int32_t overflow;    // an exact accumulator would overflow
-    int32_t pad;
+    int32_t max_count;   // largest cell count of the newest counts (set by the scan)
+    // per-block maxima land in 64 slots (spreads atomic contention); the
+    // epilogue folds them into max_u / max_carry
+    int32_t umax_slot[64];
+    int32_t cmax_slot[64];
 };
 
 // Particle planes: m[3] uint8 then u[3] int8, each of capacity n.
@@ -64,9 +75,11 @@ struct Planes {
 };
 
 // ---- scan.hip -----------------------------------------------------------
-// out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.
+// out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  If max_out
+// is given, atomicMax(max_out, max(in)) as well.
 size_t scan_workspace_bytes(int64_t n);
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
+                        int32_t* max_out = nullptr);
 
 // ---- sort.hip -----------------------------------------------------------
 // Stable LSD sort of (key, value) pairs by the low `bits` key bits.
@@ -88,8 +101,11 @@ void launch_count_keys(const uint32_t* key, int64_t n, int32_t* counts, hipStrea
 // ---- deposit.hip --------------------------------------------------------
 void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
                            int32_t* overflow, hipStream_t s);
+// real density meshes of tiles [tile0, tile0 + ntiles) into mesh + k F^3;
+// wide selects 64-bit accumulators (needed when fine_deposit_needs_wide)
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
-                         float* pair_mesh, int32_t* overflow, hipStream_t s);
+                         float* mesh, bool wide, hipStream_t s);
+bool fine_deposit_needs_wide(const Geom& g, int max_count);
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
                          hipStream_t s);
 
@@ -104,6 +120,14 @@ void fft3d(float2* data, int n, int batch, bool inverse, const float2* tw, hipSt
 // ev (optional, 6 events): recorded before the first pass and after each pass.
 void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void* green_octant,
                     int table_kind, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// Real tile meshes (ntiles cubes of n^3 floats, [z][y][x]) -> convolution with
+// a real even octant table through half spectra (n^2 (n/2+1) complex per
+// tile, workspace) -> potentials in place.  ev (optional, 4 events) is
+// recorded before the first and after each of the three sweeps.
+bool fft_tiles_supported(int n);
+void fft_tiles_convolve(float* real_tiles, float2* spec_tiles, int n, int ntiles, const float2* tw,
+                        const float* green_octant, hipStream_t s, hipEvent_t* ev = nullptr);
 
 // ---- green.hip ----------------------------------------------------------
 // FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).
@@ -121,7 +145,7 @@ struct GatherArgs {
     uint8_t* dir;           // GATHER_STEP: move code 0..26, 255 = far mover
     uint32_t* far_key;      // GATHER_STEP: new canonical cell of far movers
     int32_t* counts_new;    // GATHER_STEP: histogram of new cells
-    const float* fine_pairs;   // fine potential of the batch (pair-packed)
+    const float* fine_real;    // fine potentials of the batch: ntiles real F^3 meshes
     const float2* coarse;      // coarse potential (real part)
     StepScalars* sc;
     float* acc;             // GATHER_FORCE: [n][3]
@@ -132,8 +156,11 @@ struct GatherArgs {
     int mode;
 };
 void launch_gather(const GatherArgs& a, hipStream_t s);
+int gather_blocks_per_tile(const Geom& g);
+bool gather_supported(const Geom& g);
 
 // ---- compact.hip --------------------------------------------------------
+bool compact_supported(const Geom& g);
 void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
                          const uint8_t* dir, Planes src, Planes dst, hipStream_t s);
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir,

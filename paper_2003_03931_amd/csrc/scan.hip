@@ -15,24 +15,33 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ in,
-                                                             int64_t n, int32_t* __restrict__ sums) {
+                                                             int64_t n, int32_t* __restrict__ sums,
+                                                             int32_t* __restrict__ max_out) {
     __shared__ int lds[kScanThreads / kWave + 1];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int acc = 0;
+    int acc = 0, mx = 0;
     if (base + kScanItems <= n) {
         const int4* p = reinterpret_cast<const int4*>(in + base);
 #pragma unroll
         for (int i = 0; i < kScanItems / 4; ++i) {
             int4 q = p[i];
             acc += q.x + q.y + q.z + q.w;
+            mx = max(max(mx, max(q.x, q.y)), max(q.z, q.w));
         }
     } else {
         for (int i = 0; i < kScanItems; ++i)
-            if (base + i < n) acc += in[base + i];
+            if (base + i < n) {
+                acc += in[base + i];
+                mx = max(mx, in[base + i]);
+            }
     }
     int total;
     block_exclusive_scan(acc, lds, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
+    if (max_out) {
+        mx = wave_max(mx);
+        if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_out, mx);
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in,
@@ -81,15 +90,16 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __res
 
 // Single-block scan for short inputs (n <= kScanTile): out[0..n].
 __global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __restrict__ in, int64_t n,
-                                                              int32_t* __restrict__ out) {
+                                                              int32_t* __restrict__ out, int32_t* __restrict__ max_out) {
     __shared__ int lds[kScanThreads / kWave + 1];
     const int64_t base = (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
-    int acc = 0;
+    int acc = 0, mx = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         v[i] = (base + i < n) ? in[base + i] : 0;
         acc += v[i];
+        mx = max(mx, v[i]);
     }
     int total;
     int run = block_exclusive_scan(acc, lds, &total);
@@ -98,6 +108,10 @@ __global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __re
         run += v[i];
     }
     if (threadIdx.x == 0) out[n] = total;
+    if (max_out) {
+        mx = wave_max(mx);
+        if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_out, mx);
+    }
 }
 
 inline int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
@@ -115,9 +129,9 @@ size_t scan_workspace_bytes(int64_t n) {
     return bytes + 256;
 }
 
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s, int32_t* max_out) {
     if (n <= kScanTile) {
-        hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kScanThreads), 0, s, in, n, out);
+        hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kScanThreads), 0, s, in, n, out, max_out);
         return;
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -125,7 +139,7 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hi
     int32_t* sums = static_cast<int32_t*>(ws);
     int32_t* sums_scan = sums + round16(nb);
     void* rest = sums_scan + round16(nb + 1);
-    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums, max_out);
     exclusive_scan_i32(sums, sums_scan, nb, rest, s);
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums_scan, out);
 }

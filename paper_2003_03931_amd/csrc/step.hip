@@ -26,12 +26,22 @@ __global__ void k_prologue(StepScalars* sc, float hv) {
     sc->max_u_next = 0;
     sc->far_count = 0;
     sc->max_carry = 0;
+    for (int i = 0; i < 64; ++i) {
+        sc->umax_slot[i] = 0;
+        sc->cmax_slot[i] = 0;
+    }
 }
 
 __global__ void k_epilogue(StepScalars* sc) {
     if (threadIdx.x != 0) return;
+    int um = sc->max_u_next, cm = sc->max_carry;
+    for (int i = 0; i < 64; ++i) {
+        um = max(um, sc->umax_slot[i]);
+        cm = max(cm, sc->cmax_slot[i]);
+    }
     sc->s = sc->s_next;
-    sc->max_u = sc->max_u_next;
+    sc->max_u = um;
+    sc->max_carry = cm;
 }
 
 __global__ void k_fill(int32_t* p, int32_t v, int64_t n) {

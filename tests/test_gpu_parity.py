@@ -172,3 +172,61 @@ def test_steps_match_oracle(name, nsteps):
     assert np.mean(d == 0) >= 0.99
     # canonical order: every stored particle is inside its counted cell
     assert np.all(np.diff(np.repeat(np.arange(st["counts"].size), st["counts"])) >= 0)
+
+
+def test_general_compaction_path_far_movers():
+    """Velocities large enough that particles cross several coarse cells in
+    one step: the library must take its sorted general compaction path and
+    still match the oracle."""
+    from oracle import codec, pm, step
+    box, ref = oracle_state("c1")
+    fast = codec.State(box, ref.counts.copy(), ref.m.copy(), ref.u.copy(), 1.0, ref.M, ref.ids.copy())
+    o, info = step.step(pm.Solver(box), fast, return_info=True)
+    assert info["max_carry"] >= 2
+    with gpu_box("c1") as g:
+        load_state(g, fast)
+        g.step(1)
+        st = g.get_state()
+        diag = g.diagnostics()
+    assert diag["max_carry"] == info["max_carry"]
+    assert st["counts"].sum() == ref.n
+    d = _compare_by_id(box, st, o)
+    assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
+
+
+def _dense_state(n_dense, seed=77):
+    """t4 box with n_dense particles packed into one coarse cell (the rest
+    uniform): exercises the wide (64-bit) fine deposit and, above 65535 per
+    cell, the sorted compaction."""
+    import oracle
+    from oracle import codec
+    spec = config("t4")
+    box = oracle.Box.from_spec(spec).validate()
+    rng = np.random.default_rng(seed)
+    n = spec.n_side ** 3
+    pos = rng.uniform(0, spec.n_side, size=(n, 3))
+    pos[:n_dense] = 10.0 + rng.uniform(0, box.H, size=(n_dense, 3))   # one coarse cell
+    vel = rng.normal(0, 0.3, size=(n, 3))
+    return box, codec.compress(box, pos.astype(np.float32), vel.astype(np.float32), with_ids=True)
+
+
+@pytest.mark.parametrize("n_dense", [300, 70000])
+def test_dense_cell_paths(n_dense):
+    from oracle import cic, pm, step
+    box, ref = _dense_state(n_dense)
+    assert ref.counts.max() >= n_dense
+    Q = ref.quanta()
+    off = ref.offsets()
+    tile = int(np.argmax(np.add.reduceat(ref.counts, np.arange(0, box.n_cells, box.Tc ** 3))))
+    idx, origin = pm.tile_sources(box, ref.counts, off, tile)
+    rho = cic.deposit(pm.tile_box_coords(box, Q[idx], origin), box.F, periodic=False) / box.h ** 3 - 1.0
+    o = step.step(pm.Solver(box), ref)
+    with gpu_box("t4") as g:
+        load_state(g, ref)
+        got = g.debug_mesh(2, tile).cpu().numpy()
+        g.step(1)
+        st = g.get_state()
+    assert np.array_equal(got, rho.transpose(2, 1, 0).astype(np.float32))
+    assert st["counts"].sum() == ref.n
+    d = _compare_by_id(box, st, o)
+    assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
