@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--tiles-per-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="bytes of a plain device copy to run first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -81,7 +83,17 @@ def main():
     import torch
     from cube_inputs import config, zeldovich_ics
     from paper_2003_03931_amd import CubeBox
+    from paper_2003_03931_amd.profiling import lookup_traffic
 
+    if args.calibrate_copy:
+        # one elementwise kernel that reads and writes exactly this many bytes
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.calibrate_copy} bytes done")
     spec = config(args.config)
     n = spec.n_side ** 3
     log(f"initial conditions {spec.n_side}^3 ...")
@@ -148,7 +160,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": lookup_traffic(dom["name"], spec.name),
             "avg_launch_ms": avg_ms,
             "bytes_per_launch": bytes_per_launch,
         },

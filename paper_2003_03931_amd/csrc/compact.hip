@@ -108,29 +108,27 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (threadIdx.x == 0) s_pref[nsrc] = tot;
     }
     __syncthreads();
-    // stage the window's move codes in LDS when they fit
+    // walk 1: each source cell's thread loads its move codes (8 in flight),
+    // stages them in LDS when the window fits, and histograms them
     const int nwin = s_pref[nsrc];
     const bool staged = nwin <= kDirCap;
-    if (staged)
-        stage_to_lds<kCThreads, 8>(
-            nwin, dir, s_dir,
-            [&](int e) {
-                const int h = find_cell(s_pref, nsrc, e);
-                return s_start[h] + (e - s_pref[h]);
-            },
-            [](int e) { return e; });
-    __syncthreads();
-    auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
-
-    // walk 1: 27-code histogram of every source cell
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-        const int n = s_cnt[h];
-        for (int q = 0; q < n; ++q) {
-            const int d = code(h, q);
-            if (d < 27) s_hist[h][d] = (uint16_t)(s_hist[h][d] + 1);
+        const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
+        for (int q0 = 0; q0 < n; q0 += 8) {
+            int cq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cq[u] = (q0 + u < n) ? (int)dir[st + q0 + u] : 255;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (q0 + u >= n) break;
+                const int d = cq[u];
+                if (staged) s_dir[base + q0 + u] = (uint8_t)d;
+                if (d < 27) s_hist[h][d] = (uint16_t)(s_hist[h][d] + 1);
+            }
         }
     }
     __syncthreads();
+    auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
 
     // arrivals from earlier source cells, per destination and code
     for (int dcell = threadIdx.x; dcell < ndst; dcell += kCThreads) {
