@@ -136,3 +136,21 @@ __device__ __forceinline__ void stage_to_lds(int total, const T* __restrict__ gl
 }
 
 }  // namespace cube
+
+namespace cube {
+
+constexpr int kXcds = 8;
+
+// Workgroups are handed to the 8 XCDs round-robin (linear id mod 8).  This
+// maps the linear id to a logical block so that each XCD receives one
+// contiguous range of logical blocks: neighbouring blocks, which share
+// particle ranges, offsets and halos, then share one L2.
+__device__ __forceinline__ int64_t xcd_logical_block() {
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    const int64_t bid = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    const int64_t per = nb / kXcds, rem = nb % kXcds;
+    const int64_t x = bid % kXcds, k = bid / kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+}  // namespace cube

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     const int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
     const int nsrc = SX * SY * SZ, ndst = BX * BY * BZ, nrow = BY * BZ;
     const int nbx = g.Nc / BX, nby = g.Nc / BY;
-    const int b = blockIdx.x;
+    const int b = (int)xcd_logical_block();
     const int B0[3] = {(b % nbx) * BX, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * BZ};
 
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {

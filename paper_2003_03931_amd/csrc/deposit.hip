@@ -36,7 +36,9 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
     __shared__ int s_scan[kDepThreads / kWave + 1];
 
     const int nbx = (M + BW - 1) / BW;
-    const int b = blockIdx.x;
+    const int64_t lb = xcd_logical_block();
+    const int b = (int)(lb % gridDim.x);        // block within the mesh
+    const int ky = (int)(lb / gridDim.x);       // tile within the batch
     const int T0[3] = {(b % nbx) * BW, ((b / nbx) % nbx) * BW, (b / (nbx * nbx)) * BW};
     const int bw[3] = {min(BW, M - T0[0]), min(BW, M - T0[1]), min(BW, M - T0[2])};
     int nsa[3];
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
 
     int tile = 0, box0[3] = {0, 0, 0};
     if (MODE == DEP_FINE_TILED) {
-        tile = tile0 + blockIdx.y;
+        tile = tile0 + ky;
         const int tx = tile % g.nt, ty = (tile / g.nt) % g.nt, tz = tile / (g.nt * g.nt);
         box0[0] = tx * g.Tc - g.hc;
         box0[1] = ty * g.Tc - g.hc;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         const float v = (float)((double)acc[i] * scale - 1.0);
         const int64_t cell = (int64_t)(T0[0] + ix) + (int64_t)M * ((T0[1] + iy) + (int64_t)M * (T0[2] + iz));
         if (MODE == DEP_FINE_TILED || MODE == DEP_FINE_PERIODIC) {
-            out[(int64_t)blockIdx.y * M * M * M + cell] = v;     // real mesh of tile k
+            out[(int64_t)ky * M * M * M + cell] = v;     // real mesh of tile k
         } else {
             out[2 * cell] = v;
             out[2 * cell + 1] = 0.0f;

@@ -13,6 +13,7 @@
 //
 // Conventions: forward uses exp(-2 pi i jk/N) like numpy; inverse is
 // unnormalised (the 1/N^3 is folded into the Green's tables).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -158,14 +159,14 @@ struct Lay {
 };
 
 template <int N, class L, bool INV, int NS, int R>
-__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw, int tid) {
     constexpr int NB = N / R;
     constexpr int TOTAL = NB * L::P;
     constexpr int IT = (TOTAL + L::NT - 1) / L::NT;
     float2 v[IT][R];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int b = threadIdx.x + it * L::NT;
+        const int b = tid + it * L::NT;
         if (TOTAL % L::NT == 0 || b < TOTAL) {
             const int j = L::WFAST ? b / L::P : b % NB;
             const int w = L::WFAST ? b % L::P : b / NB;
@@ -186,7 +187,7 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int b = threadIdx.x + it * L::NT;
+        const int b = tid + it * L::NT;
         if (TOTAL % L::NT == 0 || b < TOTAL) {
             const int j = L::WFAST ? b / L::P : b % NB;
             const int w = L::WFAST ? b % L::P : b / NB;
@@ -200,12 +201,12 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
 }
 
 template <int N, class L, bool INV, int NS>
-__device__ __forceinline__ void run_passes(float2*, const float2*) {}
+__device__ __forceinline__ void run_passes(float2*, const float2*, int) {}
 
 template <int N, class L, bool INV, int NS, int R, int... Rest>
-__device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw) {
-    stockham_pass<N, L, INV, NS, R>(lds, tw);
-    run_passes<N, L, INV, NS * R, Rest...>(lds, tw);
+__device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw, int tid) {
+    stockham_pass<N, L, INV, NS, R>(lds, tw, tid);
+    run_passes<N, L, INV, NS * R, Rest...>(lds, tw, tid);
 }
 
 // Radix plan per supported size.
@@ -215,8 +216,9 @@ struct Plan;
     template <>                                                                  \
     struct Plan<NN> {                                                            \
         template <class L, bool INV>                                             \
-        __device__ static void run(float2* lds, const float2* __restrict__ tw) { \
-            run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw);                     \
+        __device__ static void run(float2* lds, const float2* __restrict__ tw,   \
+                                   int tid = threadIdx.x) {                      \
+            run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw, tid);                \
         }                                                                        \
     };
 CUBE_FFT_PLAN(16, 4, 4)
@@ -325,133 +327,184 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
 // columns are transformed along y.  The inverse runs the same steps backwards.
 constexpr int kPlaneThreads = 512;
 
+// Persistent: each workgroup walks planes blockIdx.x, +gridDim.x, ...; the
+// next plane's global loads are issued into registers before the current
+// plane's LDS passes, so memory and LDS work overlap even at one workgroup
+// per CU.  Twiddles live in LDS so no global load sits inside the passes.
+// Complex row j (real rows 2j, 2j+1) sits at lds[j*(N+2) + x], which is also
+// where the separated half-spectrum rows 2j and 2j+1 (stride N/2+1) go, so
+// the Hermitian separation is done row by row in place, one wave per row:
+// a wave's LDS reads all complete before its writes.
 template <int N>
 __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __restrict__ real_tiles,
                                                              float2* __restrict__ spec_tiles,
-                                                             const float2* __restrict__ tw) {
+                                                             const float2* __restrict__ tw_g, int nplanes) {
     constexpr int NH = N / 2 + 1;
     constexpr int HALF = N / 2;
-    __shared__ float2 lds[N * NH];
-    const int z = blockIdx.x;
-    const float* src = real_tiles + (int64_t)blockIdx.y * N * N * N + (int64_t)z * N * N;
-    // rows 2j (real part) and 2j+1 (imaginary part) -> complex row j
-    {
-        constexpr int TOT = HALF * N;
-        constexpr int U = 16;
-        for (int base = 0; base < TOT; base += kPlaneThreads * U) {
-            float re[U], im[U];
+    constexpr int RS = N + 2;                    // complex row stride = 2 NH
+    constexpr int TOT = HALF * N;
+    constexpr int PER = (TOT + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int KIT = (NH + kWave - 1) / kWave;
+    constexpr int NW = kPlaneThreads / kWave;
+    __shared__ float2 lds[HALF * RS];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += kPlaneThreads) tw[i] = tw_g[i];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    float re[PER], im[PER];
+    auto prefetch = [&](int pl) {
+        const float* src = real_tiles + (int64_t)(pl / N) * N * N * N + (int64_t)(pl % N) * N * N;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = base + u * kPlaneThreads + threadIdx.x;
-                if (e < TOT) {
-                    const int j = e / N, x = e % N;
-                    re[u] = src[(2 * j) * N + x];
-                    im[u] = src[(2 * j + 1) * N + x];
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) {
+                const int j = e / N, x = e % N;
+                re[u] = src[(2 * j) * N + x];
+                im[u] = src[(2 * j + 1) * N + x];
+            }
+        }
+    };
+    int plane = blockIdx.x;
+    if (plane < nplanes) prefetch(plane);
+    for (; plane < nplanes; plane += gridDim.x) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) lds[(e / N) * RS + e % N] = make_float2(re[u], im[u]);
+        }
+        __syncthreads();
+        if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
+        // a fresh, opaque thread index per plane keeps the passes' LDS
+        // address arithmetic from being hoisted out of the plane loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        Plan<N>::template run<Lay<HALF, 1, RS, false, kPlaneThreads>, false>(lds, tw, tid);
+        // A(k) = (Z(k) + conj Z(N-k)) / 2, B(k) = (Z(k) - conj Z(N-k)) / 2i, k = 0..N/2
+        for (int j = wv; j < HALF; j += NW) {
+            float2* row = lds + j * RS;
+            float2 va[KIT], vb[KIT];
+#pragma unroll
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < NH) {
+                    const float2 z1 = row[k];
+                    const float2 z2 = row[k == 0 ? 0 : N - k];
+                    va[t] = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+                    vb[t] = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
                 }
             }
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = base + u * kPlaneThreads + threadIdx.x;
-                if (e < TOT) lds[e] = make_float2(re[u], im[u]);
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < NH) {
+                    row[k] = va[t];
+                    row[NH + k] = vb[t];
+                }
             }
         }
+        __syncthreads();
+        Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, false>(lds, tw, tid);
+        float2* dst = spec_tiles + (int64_t)(plane / N) * N * N * NH + (int64_t)(plane % N) * N * NH;
+        for (int e = threadIdx.x; e < N * NH; e += kPlaneThreads) dst[e] = lds[e];
     }
-    __syncthreads();
-    Plan<N>::template run<Lay<HALF, 1, N, false, kPlaneThreads>, false>(lds, tw);
-    // separate the two real rows' spectra: A = (Z(k) + conj Z(N-k)) / 2, B = (Z(k) - conj Z(N-k)) / 2i
-    constexpr int SEP = HALF * NH;
-    constexpr int IT = (SEP + kPlaneThreads - 1) / kPlaneThreads;
-    float2 va[IT], vb[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kPlaneThreads;
-        if (e < SEP) {
-            const int j = e / NH, k = e % NH;
-            const float2 z1 = lds[j * N + k];
-            const float2 z2 = lds[j * N + (k == 0 ? 0 : N - k)];
-            va[it] = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
-            vb[it] = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kPlaneThreads;
-        if (e < SEP) {
-            const int j = e / NH, k = e % NH;
-            lds[(2 * j) * NH + k] = va[it];
-            lds[(2 * j + 1) * NH + k] = vb[it];
-        }
-    }
-    __syncthreads();
-    Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, false>(lds, tw);
-    float2* dst = spec_tiles + (int64_t)blockIdx.y * N * N * NH + (int64_t)z * N * NH;
-    for (int e = threadIdx.x; e < N * NH; e += kPlaneThreads) dst[e] = lds[e];
 }
 
 template <int N>
 __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __restrict__ spec_tiles,
                                                              float* __restrict__ real_tiles,
-                                                             const float2* __restrict__ tw) {
+                                                             const float2* __restrict__ tw_g, int nplanes) {
     constexpr int NH = N / 2 + 1;
     constexpr int HALF = N / 2;
-    __shared__ float2 lds[N * NH];
-    const int z = blockIdx.x;
-    const float2* src = spec_tiles + (int64_t)blockIdx.y * N * N * NH + (int64_t)z * N * NH;
-    stage_to_lds<kPlaneThreads, 16>(N * NH, src, lds, [](int e) { return e; }, [](int e) { return e; });
-    __syncthreads();
-    Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, true>(lds, tw);
-    // rebuild complex rows Z = A + iB over the full k range (Hermitian extension)
-    constexpr int ROWS = HALF * N;
-    constexpr int IT = (ROWS + kPlaneThreads - 1) / kPlaneThreads;
-    float2 vz[IT];
+    constexpr int RS = N + 2;
+    constexpr int TOT = N * NH;
+    constexpr int PER = (TOT + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int KIT = (N + kWave - 1) / kWave;
+    constexpr int NW = kPlaneThreads / kWave;
+    __shared__ float2 lds[HALF * RS];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += kPlaneThreads) tw[i] = tw_g[i];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    float2 pv[PER];
+    auto prefetch = [&](int pl) {
+        const float2* src = spec_tiles + (int64_t)(pl / N) * N * N * NH + (int64_t)(pl % N) * N * NH;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kPlaneThreads;
-        if (e < ROWS) {
-            const int j = e / N, k = e % N;
-            float2 a, b;
-            if (k <= HALF) {
-                a = lds[(2 * j) * NH + k];
-                b = lds[(2 * j + 1) * NH + k];
-            } else {
-                const float2 ac = lds[(2 * j) * NH + (N - k)];
-                const float2 bc = lds[(2 * j + 1) * NH + (N - k)];
-                a = make_float2(ac.x, -ac.y);
-                b = make_float2(bc.x, -bc.y);
-            }
-            vz[it] = make_float2(a.x - b.y, a.y + b.x);      // a + i b
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) pv[u] = src[e];
         }
-    }
-    __syncthreads();
+    };
+    int plane = blockIdx.x;
+    if (plane < nplanes) prefetch(plane);
+    for (; plane < nplanes; plane += gridDim.x) {
+        __syncthreads();
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kPlaneThreads;
-        if (e < ROWS) lds[e] = vz[it];                      // row j at j*N + k
-    }
-    __syncthreads();
-    Plan<N>::template run<Lay<HALF, 1, N, false, kPlaneThreads>, true>(lds, tw);
-    float* dst = real_tiles + (int64_t)blockIdx.y * N * N * N + (int64_t)z * N * N;
-    for (int e = threadIdx.x; e < HALF * N; e += kPlaneThreads) {
-        const int j = e / N, x = e % N;
-        const float2 v = lds[j * N + x];
-        dst[(2 * j) * N + x] = v.x;
-        dst[(2 * j + 1) * N + x] = v.y;
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = pv[u];
+        }
+        __syncthreads();
+        if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
+        // a fresh, opaque thread index per plane keeps the passes' LDS
+        // address arithmetic from being hoisted out of the plane loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, true>(lds, tw, tid);
+        // complex row Z(k) = A(k) + i B(k) over k = 0..N-1 (Hermitian extension of A, B)
+        for (int j = wv; j < HALF; j += NW) {
+            float2* row = lds + j * RS;
+            float2 vz[KIT];
+#pragma unroll
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < N) {
+                    const int kk = k <= HALF ? k : N - k;
+                    const float sg = k <= HALF ? 1.0f : -1.0f;
+                    const float2 a = row[kk], b = row[NH + kk];
+                    vz[t] = make_float2(a.x - sg * b.y, sg * a.y + b.x);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < N) row[k] = vz[t];
+            }
+        }
+        __syncthreads();
+        Plan<N>::template run<Lay<HALF, 1, RS, false, kPlaneThreads>, true>(lds, tw, tid);
+        float* dst = real_tiles + (int64_t)(plane / N) * N * N * N + (int64_t)(plane % N) * N * N;
+        for (int e = threadIdx.x; e < HALF * N; e += kPlaneThreads) {
+            const int j = e / N, x = e % N;
+            const float2 v = lds[j * RS + x];
+            dst[(2 * j) * N + x] = v.x;
+            dst[(2 * j + 1) * N + x] = v.y;
+        }
     }
 }
 
 // z pencils of the half spectrum: forward, times G (float octant), inverse.
+// Twiddles and the block's Green's values are staged in LDS with the data.
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__ spec_tiles,
-                                                            const float2* __restrict__ tw,
+                                                            const float2* __restrict__ tw_g,
                                                             const float* __restrict__ green) {
     constexpr int NH = N / 2 + 1;
     constexpr int W = 16;
     constexpr int LDN = N + 1;
     constexpr int PLANE = N * NH;
     __shared__ float2 lds[W * LDN];
+    __shared__ float2 tw[N];
+    __shared__ float gl[W * NH];                   // G(kz folded, this block's (ky, kx))
     const int c0 = blockIdx.x * W;                 // flattened (ky, kx) of the first pencil
     float2* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
+    for (int i = threadIdx.x; i < N; i += kFftThreads) tw[i] = tw_g[i];
+    for (int e = threadIdx.x; e < W * NH; e += kFftThreads) {
+        const int w = e % W, fz = e / W;
+        const int c = c0 + w;
+        const int ky = c / NH, kx = c - ky * NH;
+        gl[e] = green[((int64_t)fz * NH + fold(ky, N)) * NH + kx];
+    }
     stage_to_lds<kFftThreads, 10>(
         W * N, g, lds, [](int e) { return (int64_t)(e / W) * PLANE + (e % W); },
         [](int e) { return (e % W) * LDN + e / W; });
@@ -460,9 +513,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__
     Plan<N>::template run<L, false>(lds, tw);
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
         const int w = e % W, i = e / W;
-        const int c = c0 + w;
-        const int ky = c / NH, kx = c - ky * NH;
-        const float gv = green[((int64_t)fold(i, N) * NH + fold(ky, N)) * NH + kx];
+        const float gv = gl[fold(i, N) * W + w];
         const float2 v = lds[w * LDN + i];
         lds[w * LDN + i] = make_float2(v.x * gv, v.y * gv);
     }
@@ -474,16 +525,29 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__
     }
 }
 
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 template <int N>
 void launch_tiles(float* real_tiles, float2* spec_tiles, int ntiles, const float2* tw, const float* green,
                   hipStream_t s, hipEvent_t* ev) {
     constexpr int NH = N / 2 + 1;
     if (ev) hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_r2c_plane<N>, dim3(N, ntiles), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw);
+    const int nplanes = N * ntiles;
+    const int blocks = std::min(nplanes, device_cus());
+    hipLaunchKernelGGL(k_r2c_plane<N>, dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw, nplanes);
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_zconv_half<N>, dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw, green);
     if (ev) hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_c2r_plane<N>, dim3(N, ntiles), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw);
+    hipLaunchKernelGGL(k_c2r_plane<N>, dim3(blocks), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw, nplanes);
     if (ev) hipEventRecord(ev[3], s);
 }
 

@@ -102,10 +102,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const int r = g.r;
     const int BXc = kBX / r, BYc = kBY / r, BZc = kBZ / r;
     const int nrows = BYc * BZc;
-    const int k = blockIdx.y;                              // tile within the batch
+    const int64_t lb = xcd_logical_block();
+    const int k = (int)(lb / gridDim.x);                   // tile within the batch
     const int tile = A.tile0 + k;
     const int nbx = g.T / kBX, nby = g.T / kBY;
-    const int b = blockIdx.x;
+    const int b = (int)(lb % gridDim.x);
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int tx = tile % g.nt, ty = (tile / g.nt) % g.nt, tz = tile / (g.nt * g.nt);
     // brick origin: tile-local fine and coarse coordinates, global coarse
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int w = 0; w < kGatherThreads / kWave; ++w) t += s_red[w];
-            A.partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
+            A.partial[(int64_t)k * gridDim.x + b] = t;
         }
     }
 }
