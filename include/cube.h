@@ -29,6 +29,7 @@
 #ifndef CUBE_H
 #define CUBE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -40,13 +41,31 @@ typedef enum {
     CUBE_INVALID = 1,      /* bad descriptor, geometry or argument; ctx unchanged     */
     CUBE_OOM = 2,          /* device allocation failed; ctx unchanged                 */
     CUBE_DEVICE = 3,       /* HIP runtime error; ctx is poisoned (only destroy valid) */
-    CUBE_NOT_READY = 4,    /* reserved for asynchronous queries                       */
-    CUBE_OVERFLOW = 5,     /* an exact accumulator would overflow                     */
+    CUBE_NOT_READY = 4,    /* cube_poll: the request is queued or running             */
+    CUBE_OVERFLOW = 5,     /* a CUBE_MIXED_FP16 spectrum value left the FP16 range    */
     CUBE_UNSUPPORTED = 6   /* mesh side not factorable by the FFT radices             */
 } cube_status;
 
+/*
+ * Precision of the fine-mesh work.  Deposits are exact fixed point in every
+ * mode, and every FFT pass, Green's multiply, gradient, interpolation and kick
+ * computes in FP32.  The modes differ only in how the half spectra of the tile
+ * meshes are stored in HBM between the three FFT sweeps (the largest traffic
+ * of the step):
+ *   CUBE_FP32        FP32 complex (8 bytes per value).
+ *   CUBE_MIXED_BF16  BF16 real and imaginary parts (4 bytes), rounded to
+ *                    nearest even; about 2^-9 relative error per stored value.
+ *   CUBE_MIXED_FP16  FP16 parts scaled by a power of two (4 bytes); about
+ *                    2^-12 relative error per value.  Batches whose densities
+ *                    could leave the FP16 range are run with FP32 storage;
+ *                    a potential spectrum value beyond it makes cube_pm_step
+ *                    return CUBE_OVERFLOW with the state left as before the
+ *                    step.
+ */
 typedef enum {
-    CUBE_FP32 = 0          /* FP32 meshes and force (the only precision built)        */
+    CUBE_FP32 = 0,
+    CUBE_MIXED_BF16 = 1,
+    CUBE_MIXED_FP16 = 2
 } cube_precision;
 
 /*
@@ -129,13 +148,38 @@ typedef struct {
 /* Thread-local description of the last failure (empty if none). */
 const char* cube_last_error(void);
 
+/*
+ * Device memory callbacks.  The library obtains every device buffer it uses
+ * (state, meshes, tables, workspace, and the temporaries of single calls)
+ * through them.  alloc returns at least `bytes` bytes of device memory usable
+ * in stream order on hip_stream, or NULL on failure (the call then returns
+ * CUBE_OOM); free receives the pointer with the same `bytes`.  Temporaries are
+ * freed right after the stream work that used them was enqueued, so a
+ * stream-ordered allocator may hand them out again on the same stream.
+ * `user` is passed back unchanged.  The callbacks must outlive the context.
+ */
+typedef struct {
+    void* (*alloc)(void* user, size_t bytes, void* hip_stream);
+    void (*free)(void* user, void* ptr, size_t bytes, void* hip_stream);
+    void* user;
+} cube_allocator;
+
 /* Create a context for one box: validates the geometry, allocates the state,
- * the meshes and the workspace with hipMalloc on the current device, builds
- * the FFT twiddles (FP64-derived) and the Green's tables (FP64).  hip_stream
- * is a hipStream_t (NULL = the default stream).  The state starts empty (all
- * counts zero) until cube_compress or cube_set_state.  Errors: CUBE_INVALID,
- * CUBE_UNSUPPORTED, CUBE_OOM, CUBE_DEVICE. */
-cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** out);
+ * the meshes and the workspace on the current device (through `alloc`, or
+ * hipMalloc when it is NULL), builds the FFT twiddles (FP64-derived) and the
+ * Green's tables (FP64).  hip_stream is a hipStream_t (NULL = the default
+ * stream).  The state starts empty (all counts zero) until cube_compress or
+ * cube_set_state.  Errors: CUBE_INVALID, CUBE_UNSUPPORTED, CUBE_OOM,
+ * CUBE_DEVICE. */
+cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, void* hip_stream,
+                      cube_ctx** out);
+
+/* Device bytes of a context for this descriptor, without allocating:
+ * *persistent is held from cube_init to cube_destroy, *transient is the
+ * largest set of temporaries one call adds on top (compress from host
+ * buffers, the general compaction path, the power spectrum).  Errors as
+ * cube_init's validation. */
+cube_status cube_footprint(const cube_box_desc* desc, int64_t* persistent, int64_t* transient);
 
 /* Free everything owned by the context (NULL is ignored). */
 void cube_destroy(cube_ctx* ctx);
@@ -156,12 +200,14 @@ cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
 
 /* Advance the state by nsteps kick-drift steps.  Enqueued on the context
  * stream; returns after the last step's completion flag is read back (one
- * small device-to-host copy per step).  CUBE_OVERFLOW if an exact fixed-point
- * accumulator would overflow (the state is then the one before that step). */
+ * small device-to-host copy per step).  CUBE_OVERFLOW if a CUBE_MIXED_FP16
+ * spectrum value left the FP16 range: the state is then the one before that
+ * step (only the cumulative saturation counter may include the aborted step). */
 cube_status cube_pm_step(cube_ctx* ctx, int32_t nsteps);
 
 /* Acceleration of every particle at the current state, no update.
- * acc[i*3+k], canonical order, float32.  Synchronises. */
+ * acc[i*3+k], canonical order, float32.  Synchronises.  CUBE_OVERFLOW as for
+ * cube_pm_step (the output is then not valid). */
 cube_status cube_forces(cube_ctx* ctx, float* acc, int32_t on_device);
 
 /* Copy the state out to / in from caller buffers (see cube_state_view).
@@ -210,6 +256,80 @@ cube_status cube_profile_enable(cube_ctx* ctx, int32_t enable);
 
 /* Copy up to max stage records into out; *n receives the number written. */
 cube_status cube_profile_read(cube_ctx* ctx, cube_stage_stat* out, int32_t max, int32_t* n);
+
+/*
+ * Serving: independent boxes submitted one by one, each run to completion
+ * (compress, n_steps steps, optional diagnostics and state copy-out) on one
+ * GPU.  Admission is first-in first-out against an HBM budget: the request at
+ * the head of the queue starts when a slot is free and its footprint
+ * (persistent + transient bytes from cube_footprint) fits in what running
+ * boxes leave of the budget.  Each slot is one host thread with its own HIP
+ * stream and context, so up to max_slots boxes run concurrently.
+ *   hbm_budget_bytes  device bytes the running boxes may hold together.
+ *   max_slots         boxes in flight at once (>= 1).
+ *   precision         cube_precision forced on every request, or -1 to keep
+ *                     each request's own.
+ *   device            HIP device of every context.
+ * The server is internally synchronised: any thread may submit and poll.
+ */
+typedef struct {
+    int64_t hbm_budget_bytes;
+    int32_t max_slots;
+    int32_t precision;
+    int32_t device;
+    int32_t reserved;
+} cube_server_desc;
+
+/*
+ * One box.  pos/vel are host arrays [n][3] (as for cube_compress) and
+ * out_state, if not NULL, receives the final state (host buffers, as for
+ * cube_get_state).  The caller keeps all of them alive and unchanged until
+ * cube_poll reports the request done.  want_diag nonzero: fill the result's
+ * diagnostics (costs about one force evaluation).
+ */
+typedef struct {
+    cube_box_desc desc;
+    int32_t n_steps;
+    int32_t want_diag;
+    const float* pos;
+    const float* vel;
+    int64_t n;
+    cube_state_view* out_state;
+} cube_request;
+
+/* Outcome of a request; times are milliseconds on the server's steady clock
+ * (0 = cube_server_create). */
+typedef struct {
+    int32_t status;            /* cube_status of the run                        */
+    int32_t reserved;
+    int64_t steps_done;
+    int64_t footprint_bytes;   /* bytes admitted against the budget            */
+    double submit_ms;
+    double start_ms;           /* admitted and started                          */
+    double done_ms;
+    cube_diag diag;            /* when want_diag                                */
+    char message[160];         /* cube_last_error text of a failed run          */
+} cube_result;
+
+typedef struct cube_server cube_server;
+
+/* Start the slot threads.  Errors: CUBE_INVALID (bad descriptor). */
+cube_status cube_server_create(const cube_server_desc* desc, cube_server** out);
+
+/* Queue a request; *ticket identifies it.  CUBE_INVALID if the descriptor
+ * is invalid, the arrays are missing or n != n_side^3, or the footprint
+ * exceeds the whole budget (it could never be admitted); CUBE_UNSUPPORTED as
+ * for cube_init. */
+cube_status cube_submit(cube_server* srv, const cube_request* req, uint64_t* ticket);
+
+/* CUBE_NOT_READY while the request waits or runs; CUBE_OK once it is done,
+ * with *out filled (the ticket is then released: polling it again is
+ * CUBE_INVALID); CUBE_INVALID for an unknown ticket. */
+cube_status cube_poll(cube_server* srv, uint64_t ticket, cube_result* out);
+
+/* Wait for the running boxes, drop the queued ones, stop the threads.  NULL
+ * is ignored. */
+void cube_server_destroy(cube_server* srv);
 
 #ifdef __cplusplus
 }

@@ -155,6 +155,49 @@ def _fine_all(box, Q, counts, offsets, Gf, want_phi, workers):
     return acc, pot
 
 
+# ------------------------------------------- sampled evaluation of large boxes
+# The same steps as above, decoding only the particles that a few tiles need,
+# for boxes whose full decode would not fit a test's time (R4, R5, R11).
+def quanta_of_cells(box: Box, counts, offsets, m, cells):
+    """Storage indices and global quanta of the particles of `cells`
+    (canonical indices), decoded from counts, offsets and the m planes."""
+    cells = np.asarray(cells, dtype=np.int64)
+    cnt = np.asarray(counts[cells], dtype=np.int64)
+    idx = _expand_ranges(np.asarray(offsets[cells], dtype=np.int64), cnt)
+    cx, cy, cz = box.cell_of_canon(np.repeat(cells, cnt))
+    Q = np.empty((idx.size, 3), dtype=np.int64)
+    Q[:, 0] = 256 * cx + m[0][idx]
+    Q[:, 1] = 256 * cy + m[1][idx]
+    Q[:, 2] = 256 * cz + m[2][idx]
+    return idx, Q
+
+
+def tile_force_sampled(box: Box, counts, offsets, m, t, Gf):
+    """Fine-mesh acceleration of the particles of tile t: (indices, quanta,
+    acceleration), with only the tile's sources decoded."""
+    tx, ty, tz = box.tile_coords(t)
+    Nc, Tc, hc = box.n_coarse, box.Tc, box.halo_c
+    span = box.F // box.coarse_ratio
+    origin = np.array([tx * Tc - hc, ty * Tc - hc, tz * Tc - hc]) % Nc
+    rng = np.arange(span)
+    cz, cy, cx = np.meshgrid((origin[2] + rng) % Nc, (origin[1] + rng) % Nc,
+                             (origin[0] + rng) % Nc, indexing="ij")
+    _, Qs = quanta_of_cells(box, counts, offsets, m, box.canon(cx.ravel(), cy.ravel(), cz.ravel()))
+    periodic = box.tiles_per_dim == 1
+    rho = cic.deposit(tile_box_coords(box, Qs, origin), box.F, periodic=periodic) / box.h ** 3 - 1.0
+    phi = solve(rho, Gf)
+    tgt, Qt = quanta_of_cells(box, counts, offsets, m, np.arange(t * Tc ** 3, (t + 1) * Tc ** 3))
+    acc = cic.gather(fd_gradient(phi, box.h), tile_box_coords(box, Qt, origin), periodic=periodic).T
+    return tgt, Qt, acc
+
+
+def coarse_force_at(box: Box, rho_c, Gc, Q):
+    """Coarse-mesh acceleration at global quanta Q for a given coarse density
+    rho_c (mass per cell volume minus 1)."""
+    g = fd_gradient(solve(rho_c, Gc), box.H)
+    return cic.gather(g, (np.asarray(Q, dtype=np.float64) + 0.5) / 256.0, periodic=True).T
+
+
 # --------------------------------------------------------------------- public
 class Solver:
     """Holds the Green's tables of one geometry."""

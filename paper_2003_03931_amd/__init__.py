@@ -5,6 +5,8 @@ this package only marshals arguments to it.
 """
 
 from ._lib import CubeError, load, LIB_PATH, SIGNATURES
-from .box import CubeBox, fft3d, desc_from
+from .box import CubeBox, fft3d, desc_from, footprint, CUBE_FP32, CUBE_MIXED_BF16, CUBE_MIXED_FP16
+from .server import CubeServer
 
-__all__ = ["CubeBox", "CubeError", "fft3d", "load", "desc_from", "LIB_PATH", "SIGNATURES"]
+__all__ = ["CubeBox", "CubeServer", "CubeError", "fft3d", "footprint", "load", "desc_from", "LIB_PATH",
+           "SIGNATURES", "CUBE_FP32", "CUBE_MIXED_BF16", "CUBE_MIXED_FP16"]

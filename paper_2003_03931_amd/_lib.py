@@ -77,10 +77,57 @@ class StageStat(ctypes.Structure):
     ]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("desc", BoxDesc),
+        ("n_steps", ctypes.c_int32),
+        ("want_diag", ctypes.c_int32),
+        ("pos", ctypes.c_void_p),
+        ("vel", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("out_state", ctypes.POINTER(StateView)),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("steps_done", ctypes.c_int64),
+        ("footprint_bytes", ctypes.c_int64),
+        ("submit_ms", ctypes.c_double),
+        ("start_ms", ctypes.c_double),
+        ("done_ms", ctypes.c_double),
+        ("diag", Diag),
+        ("message", ctypes.c_char * 160),
+    ]
+
+
 # exported symbol -> (restype, argtypes); mirrors include/cube.h
 SIGNATURES = {
     "cube_last_error": (ctypes.c_char_p, []),
-    "cube_init": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_init": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.POINTER(Allocator), ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_footprint": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
     "cube_destroy": (None, [ctypes.c_void_p]),
     "cube_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int32]),
@@ -98,6 +145,10 @@ SIGNATURES = {
     "cube_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cube_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StageStat), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "cube_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "cube_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "cube_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 _lib = None

@@ -9,16 +9,68 @@ import ctypes
 
 import numpy as np
 
-from ._lib import BoxDesc, Diag, StageStat, StateView, check, load
+from ._lib import ALLOC_FN, FREE_FN, Allocator, BoxDesc, Diag, StageStat, StateView, check, load
 
 CUBE_FP32 = 0
+CUBE_MIXED_BF16 = 1
+CUBE_MIXED_FP16 = 2
+PRECISIONS = {"fp32": CUBE_FP32, "bf16": CUBE_MIXED_BF16, "fp16": CUBE_MIXED_FP16}
 
 
-def desc_from(spec, with_ids=False, tiles_per_batch=0):
+def desc_from(spec, with_ids=False, tiles_per_batch=0, precision=CUBE_FP32):
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
     return BoxDesc(int(spec.n_side), int(spec.tiles_per_dim), int(spec.fine_per_spacing),
                    int(spec.coarse_ratio), int(spec.buffer_fine), int(spec.r_cut_fine),
-                   float(spec.dt), float(spec.v_headroom), CUBE_FP32, 1 if with_ids else 0,
+                   float(spec.dt), float(spec.v_headroom), int(precision), 1 if with_ids else 0,
                    int(tiles_per_batch), 0)
+
+
+def footprint(spec, tiles_per_batch=0, precision=CUBE_FP32, with_ids=False):
+    """(persistent, transient) device bytes of a box, from cube_footprint."""
+    lib = load()
+    d = desc_from(spec, with_ids, tiles_per_batch, precision)
+    p, t = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.cube_footprint(ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)))
+    return p.value, t.value
+
+
+class TorchAllocator:
+    """cube_allocator callbacks backed by torch's caching allocator on one
+    device; counts live bytes so that callers can check the library's
+    footprint."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.peak = 0
+        self.calls = 0
+
+        def _alloc(user, nbytes, stream):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:
+                return None
+            self.live[ptr] = int(nbytes)
+            self.calls += 1
+            self.peak = max(self.peak, self.live_bytes())
+            return ptr
+
+        def _free(user, ptr, nbytes, stream):
+            try:
+                self.live.pop(int(ptr), None)
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+    def live_bytes(self):
+        return sum(self.live.values())
 
 
 class CubeBox:
@@ -26,17 +78,22 @@ class CubeBox:
     cube_box_desc (n_side, tiles_per_dim, fine_per_spacing, coarse_ratio,
     buffer_fine, r_cut_fine, dt, v_headroom)."""
 
-    def __init__(self, spec, with_ids=False, tiles_per_batch=0, device=0):
+    def __init__(self, spec, with_ids=False, tiles_per_batch=0, device=0, precision=CUBE_FP32,
+                 allocator="torch"):
+        """allocator: "torch" (device memory from torch's caching allocator,
+        the default) or "hip" (the library's own hipMalloc)."""
         import torch
         self.torch = torch
         self.lib = load()
         self.device = torch.device("cuda", device)
         torch.cuda.set_device(self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.desc = desc_from(spec, with_ids, tiles_per_batch)
+        self.desc = desc_from(spec, with_ids, tiles_per_batch, precision)
         self.with_ids = with_ids
+        self.allocator = TorchAllocator(self.device.index) if allocator == "torch" else None
         ctx = ctypes.c_void_p()
-        check(self.lib.cube_init(ctypes.byref(self.desc), ctypes.c_void_p(self.stream.cuda_stream),
+        al = ctypes.byref(self.allocator.struct) if self.allocator else None
+        check(self.lib.cube_init(ctypes.byref(self.desc), al, ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx)))
         self.ctx = ctx
         n = spec.n_side

@@ -36,6 +36,12 @@ cube_status fail(cube_status st, const std::string& msg) {
     return st;
 }
 
+}  // namespace
+
+void cube::set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
+namespace {
+
 #define CUBE_HIP(expr)                                                                         \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -118,6 +124,53 @@ struct Profiler {
 
 }  // namespace
 
+namespace {
+
+size_t round256(size_t bytes) { return std::max<size_t>((bytes + 255) / 256 * 256, 256); }
+
+// Device memory: the caller's callbacks, or hipMalloc / hipFree.  Sizes are
+// rounded up to 256 bytes, and the same rounded size is passed to free.
+struct DevMem {
+    cube_allocator al{};
+    bool custom = false;
+    hipStream_t stream = nullptr;
+    void* get(size_t bytes) {
+        bytes = round256(bytes);
+        if (custom) return al.alloc(al.user, bytes, stream);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, size_t bytes) {
+        if (!p) return;
+        if (custom) al.free(al.user, p, round256(bytes), stream);
+        else hipFree(p);
+    }
+};
+
+// Buffers that live for one call; released (stream-ordered) at scope exit.
+struct Temp {
+    DevMem& mem;
+    std::vector<std::pair<void*, size_t>> held;
+    explicit Temp(DevMem& m) : mem(m) {}
+    template <class T>
+    bool get(T** p, size_t bytes) {
+        void* q = mem.get(bytes);
+        *p = static_cast<T*>(q);
+        if (!q) return false;
+        held.push_back({q, bytes});
+        return true;
+    }
+    ~Temp() {
+        for (auto& e : held) mem.put(e.first, e.second);
+    }
+};
+
+}  // namespace
+
 struct cube_ctx {
     Profiler prof;
     Geom g{};
@@ -125,7 +178,8 @@ struct cube_ctx {
     hipStream_t stream = nullptr;
     bool poisoned = false;
     bool has_state = false;
-    std::vector<void*> allocs;
+    DevMem mem;
+    std::vector<std::pair<void*, size_t>> allocs;
 
     Planes A{}, B{};
     uint8_t* dir = nullptr;
@@ -141,12 +195,11 @@ struct cube_ctx {
     double* coarse_green = nullptr;
     float2* tw_coarse = nullptr;
     float* fine_real = nullptr;       // batch x F^3 real meshes (density, then potential)
-    float2* fine_spec = nullptr;      // batch x F^2 (F/2+1) half spectra
+    void* fine_spec = nullptr;        // batch x F^2 (F/2+1) half spectra (FP32 size: FP16 may fall back)
     float* fine_green = nullptr;
     float2* tw_fine = nullptr;
     void* scan_ws = nullptr;
     double* partial = nullptr;
-    int64_t partial_len = 0;
     double* reduced = nullptr;
     int batch = 1;
 
@@ -156,19 +209,13 @@ struct cube_ctx {
 
     ~cube_ctx() {
         if (sc_host) hipHostFree(sc_host);
-        for (void* p : allocs) hipFree(p);
+        for (auto& e : allocs) mem.put(e.first, e.second);
     }
 
     cube_status alloc(void** p, size_t bytes) {
-        bytes = (bytes + 255) / 256 * 256;
-        if (bytes == 0) bytes = 256;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CUBE_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                      hipGetErrorString(e));
-        }
-        allocs.push_back(*p);
+        *p = mem.get(bytes);
+        if (!*p) return fail(CUBE_OOM, "device allocation of " + std::to_string(round256(bytes)) + " bytes failed");
+        allocs.push_back({*p, bytes});
         return CUBE_OK;
     }
     template <class T>
@@ -225,9 +272,62 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (!gather_supported(g))
         return fail(CUBE_UNSUPPORTED, "tile side must be a multiple of 32 fine cells and r in {4, 8, 16}");
     if (!(d->dt > 0.0f) || !(d->v_headroom >= 1.0f)) return fail(CUBE_INVALID, "need dt > 0 and v_headroom >= 1");
-    if (d->precision != CUBE_FP32) return fail(CUBE_UNSUPPORTED, "only the FP32 precision is built");
+    if (d->precision != CUBE_FP32 && d->precision != CUBE_MIXED_BF16 && d->precision != CUBE_MIXED_FP16)
+        return fail(CUBE_INVALID, "unknown precision");
     *out = g;
     return CUBE_OK;
+}
+
+int batch_of(const Geom& g, const cube_box_desc& d) {
+    const int b = d.tiles_per_batch > 0 ? d.tiles_per_batch : 64;
+    return std::max(1, std::min(b, g.ntiles));
+}
+
+// per-block FP64 partial sums of the diagnostics (moments per chunk, potential per gather block)
+int64_t partial_len(const Geom& g, int batch) {
+    return std::max<int64_t>(4 * (g.ncells / g.Tc), (int64_t)gather_blocks_per_tile(g) * batch);
+}
+
+// Device bytes a context holds for its lifetime, and the largest set of
+// temporaries any call adds on top (compress from host buffers, the general
+// compaction path, the power spectrum, the Green's-table build).
+struct Footprint {
+    int64_t persistent;
+    int64_t transient;
+};
+
+Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
+    const int batch = batch_of(g, d);
+    const int64_t n = g.n, cells = g.ncells + 16;
+    const int64_t Mc = g.Nc / 2 + 1, Mf = g.F / 2 + 1, F3 = (int64_t)g.F * g.F * g.F;
+    int64_t p = 0;
+    auto add = [&](int64_t bytes) { p += (int64_t)round256((size_t)bytes); };
+    add(12 * n);
+    if (d.with_ids) {
+        add(4 * n);
+        add(4 * n);
+    }
+    add(n);
+    add(4 * n);
+    for (int i = 0; i < 4; ++i) add(4 * cells);
+    add(sizeof(StepScalars));
+    add((int64_t)scan_workspace_bytes(cells));
+    add(8 * g.ncells);
+    add(8 * Mc * Mc * Mc);
+    add(8 * (int64_t)g.Nc);
+    add(4 * batch * F3);
+    add(8 * (int64_t)batch * g.F * g.F * Mf);
+    add(4 * Mf * Mf * Mf);
+    add(8 * (int64_t)g.F);
+    add(8 * 64);
+    add(8 * partial_len(g, batch));
+    auto r = [](int64_t bytes) { return (int64_t)round256((size_t)bytes); };
+    const int64_t sortw = r((int64_t)sort_workspace_bytes(n));
+    const int64_t t_green = r((int64_t)fine_green_workspace_bytes(g));
+    const int64_t t_compress = 2 * r(12 * n) + 5 * r(4 * n) + r(256) + sortw;
+    const int64_t t_general = 4 * r(4 * n) + sortw;
+    const int64_t t_pk = r(8 * n) + r(8 * (int64_t)g.ns) + r(8 * 3 * (int64_t)g.ns * std::max(1, g.ns / 4 - 1));
+    return {p, std::max(std::max(t_green, t_compress), std::max(t_general, t_pk))};
 }
 
 cube_status check_ctx(cube_ctx* c) {
@@ -272,22 +372,41 @@ void coarse_potential(cube_ctx* c) {
     }
 }
 
+// Storage format of the tile half spectra for the current state: the mixed
+// FP16 mode falls back to FP32 while a fine-cell density could exceed the
+// FP16 range (a cell gathers at most 8 coarse cells of max_count particles,
+// density f^3 per particle; the plane transform's gain is divided out).
+int spec_format(const cube_ctx* c) {
+    switch (c->desc.precision) {
+        case CUBE_MIXED_BF16: return 1;
+        case CUBE_MIXED_FP16: {
+            const double f3 = (double)c->g.f * c->g.f * c->g.f;
+            return 8.0 * f3 * (double)c->max_count + 1.0 < 32768.0 ? 2 : 0;
+        }
+        default: return 0;
+    }
+}
+
 // fine potentials of tiles [t0, t0 + nt) into ctx->fine_real
 void fine_potential(cube_ctx* c, int t0, int nt) {
     const Geom& g = c->g;
     Profiler& P = c->prof;
+    const int fmt = spec_format(c);
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_count),
                         c->stream);
     if (!P.on) {
-        fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, c->stream);
+        fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
+                           c->stream);
         return;
     }
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) ev[i] = P.get();
-    fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, c->stream, ev);
+    fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
+                       c->stream, ev);
     const double f3 = (double)g.F * g.F * g.F, fc3 = (double)g.Fc * g.Fc * g.Fc;
-    const double h3 = (double)g.F * g.F * (g.F / 2 + 1);
+    // bytes per stored half-spectrum value: 8 (FP32) or 4 (16-bit pairs)
+    const double h3 = (double)g.F * g.F * (g.F / 2 + 1) * (fmt == 0 ? 1.0 : 0.5);
     const double per_tile = (double)g.n / g.ntiles;
     const double src = per_tile * f3 / ((double)g.T * g.T * g.T);    // tile plus buffer
     // deposit: FP32 mesh write + offsets read + 3 position bytes per source
@@ -315,16 +434,6 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     a.ntiles = nt;
     a.mode = mode;
     return a;
-}
-
-cube_status ensure_partial(cube_ctx* c, int64_t n) {
-    if (c->partial_len >= n) return CUBE_OK;
-    double* p = nullptr;
-    cube_status st = c->alloc_n(&p, n);
-    if (st != CUBE_OK) return st;
-    c->partial = p;
-    c->partial_len = n;
-    return CUBE_OK;
 }
 
 cube_status run_step(cube_ctx* c) {
@@ -356,6 +465,8 @@ cube_status run_step(cube_ctx* c) {
     cube_status st = sync(c);
     if (st != CUBE_OK) return st;
     if (P.on) P.flush();
+    if (c->sc_host->overflow)
+        return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range: use CUBE_MIXED_BF16 or CUBE_FP32");
     // the fast compaction's 16-bit per-code counts bound the source cells' counts
     if (c->sc_host->far_count == 0 && c->max_count <= 65535) {
         hipEvent_t ec = P.on ? P.mark(s) : nullptr;
@@ -366,25 +477,15 @@ cube_status run_step(cube_ctx* c) {
         // general path: stable sort of the new keys (temporary buffers)
         uint32_t *key = nullptr, *idx = nullptr, *kt = nullptr, *it = nullptr;
         void* ws = nullptr;
-        std::vector<void*> tmp;
-        auto grab = [&](void** p, size_t bytes) -> hipError_t {
-            hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
-            if (e == hipSuccess) tmp.push_back(*p);
-            return e;
-        };
+        Temp tmp(c->mem);
         const size_t nb = (size_t)g.n * sizeof(uint32_t);
-        if (grab((void**)&key, nb) != hipSuccess || grab((void**)&idx, nb) != hipSuccess ||
-            grab((void**)&kt, nb) != hipSuccess || grab((void**)&it, nb) != hipSuccess ||
-            grab(&ws, sort_workspace_bytes(g.n)) != hipSuccess) {
-            for (void* p : tmp) hipFree(p);
-            (void)hipGetLastError();
+        if (!tmp.get(&key, nb) || !tmp.get(&idx, nb) || !tmp.get(&kt, nb) || !tmp.get(&it, nb) ||
+            !tmp.get(&ws, sort_workspace_bytes(g.n)))
             return fail(CUBE_OOM, "general compaction: out of memory");
-        }
         launch_general_keys(g, c->offsets, c->dir, c->far_key, key, idx, s);
         stable_sort_pairs(key, idx, kt, it, g.n, ilog2((int)std::min<int64_t>(g.ncells, 1 << 30)) + 1, ws, s);
         launch_permute_planes(idx, c->B, c->A, g.n, s);
         st = sync(c);
-        for (void* p : tmp) hipFree(p);
         if (st != CUBE_OK) return st;
     }
     launch_step_epilogue(c->sc, s);
@@ -401,9 +502,21 @@ extern "C" {
 
 const char* cube_last_error(void) { return g_err.c_str(); }
 
-cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** out) {
+cube_status cube_footprint(const cube_box_desc* desc, int64_t* persistent, int64_t* transient) {
+    if (!persistent || !transient) return fail(CUBE_INVALID, "null output pointer");
+    Geom g;
+    cube_status st = validate(desc, &g);
+    if (st != CUBE_OK) return st;
+    const Footprint f = footprint_of(g, *desc);
+    *persistent = f.persistent;
+    *transient = f.transient;
+    return CUBE_OK;
+}
+
+cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, void* hip_stream, cube_ctx** out) {
     if (!out) return fail(CUBE_INVALID, "null output pointer");
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(CUBE_INVALID, "allocator needs alloc and free");
     Geom g;
     cube_status st = validate(desc, &g);
     if (st != CUBE_OK) return st;
@@ -412,10 +525,13 @@ cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** ou
     c->g = g;
     c->desc = *desc;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    c->mem.stream = c->stream;
+    if (alloc) {
+        c->mem.custom = true;
+        c->mem.al = *alloc;
+    }
     const int64_t n = g.n;
-    int batch = desc->tiles_per_batch > 0 ? desc->tiles_per_batch : 64;
-    batch = std::min(batch, g.ntiles);
-    c->batch = std::max(1, batch);
+    c->batch = batch_of(g, *desc);
 
 #define CUBE_TRY(x)              \
     do {                         \
@@ -452,10 +568,11 @@ cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** ou
     CUBE_TRY(c->alloc_n(&c->tw_coarse, g.Nc));
     const int64_t fcube = (int64_t)g.F * g.F * g.F;
     CUBE_TRY(c->alloc_n(&c->fine_real, (int64_t)c->batch * fcube));
-    CUBE_TRY(c->alloc_n(&c->fine_spec, (int64_t)c->batch * g.F * g.F * (g.F / 2 + 1)));
+    CUBE_TRY(c->alloc(&c->fine_spec, (size_t)c->batch * g.F * g.F * (g.F / 2 + 1) * sizeof(float2)));
     CUBE_TRY(c->alloc_n(&c->fine_green, Mf * Mf * Mf));
     CUBE_TRY(c->alloc_n(&c->tw_fine, g.F));
     CUBE_TRY(c->alloc_n(&c->reduced, 64));
+    CUBE_TRY(c->alloc_n(&c->partial, partial_len(g, c->batch)));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->sc_host), sizeof(StepScalars)) != hipSuccess) {
         c->sc_host = nullptr;
         delete c;
@@ -463,8 +580,13 @@ cube_status cube_init(const cube_box_desc* desc, void* hip_stream, cube_ctx** ou
     }
     std::memset(c->sc_host, 0, sizeof(StepScalars));
     c->sc_host->s = 1.0;
+    DevMem init_mem = c->mem;          // outlives c on the error paths below
+    Temp init_tmp(init_mem);
     void* gws = nullptr;
-    CUBE_TRY(c->alloc(&gws, fine_green_workspace_bytes(g)));
+    if (!init_tmp.get(&gws, fine_green_workspace_bytes(g))) {
+        delete c;
+        return fail(CUBE_OOM, "Green's table workspace");
+    }
 
     // empty state, tables, twiddles
     hipStream_t s = c->stream;
@@ -499,19 +621,7 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     const Geom& g = c->g;
     if (n != g.n || !pos || !vel) return fail(CUBE_INVALID, "compress needs n_side^3 particles");
     hipStream_t s = c->stream;
-    std::vector<void*> tmp;
-    auto grab = [&](void** p, size_t bytes) -> bool {
-        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        tmp.push_back(*p);
-        return true;
-    };
-    auto release = [&]() {
-        for (void* p : tmp) hipFree(p);
-        tmp.clear();
-    };
+    Temp tmp(c->mem);
     const float* dpos = pos;
     const float* dvel = vel;
     float *hp = nullptr, *hv = nullptr;
@@ -519,34 +629,25 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     void* ws = nullptr;
     const size_t fb = (size_t)n * 3 * sizeof(float), ub = (size_t)n * sizeof(uint32_t);
     if (!on_device) {
-        if (!grab((void**)&hp, fb) || !grab((void**)&hv, fb)) {
-            release();
-            return fail(CUBE_OOM, "compress: staging allocation failed");
-        }
+        if (!tmp.get(&hp, fb) || !tmp.get(&hv, fb)) return fail(CUBE_OOM, "compress: staging allocation failed");
         if (hipMemcpyAsync(hp, pos, fb, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(hv, vel, fb, hipMemcpyHostToDevice, s) != hipSuccess) {
-            release();
             c->poisoned = true;
             return fail(CUBE_DEVICE, "compress: upload failed");
         }
         dpos = hp;
         dvel = hv;
     }
-    if (!grab((void**)&key, ub) || !grab((void**)&idx, ub) || !grab((void**)&kt, ub) || !grab((void**)&it, ub) ||
-        !grab((void**)&qp, ub) || !grab((void**)&vmax, 256) || !grab(&ws, sort_workspace_bytes(n))) {
-        release();
+    if (!tmp.get(&key, ub) || !tmp.get(&idx, ub) || !tmp.get(&kt, ub) || !tmp.get(&it, ub) || !tmp.get(&qp, ub) ||
+        !tmp.get(&vmax, 256) || !tmp.get(&ws, sort_workspace_bytes(n)))
         return fail(CUBE_OOM, "compress: workspace allocation failed");
-    }
     launch_encode_keys(g, dpos, key, qp, idx, n, s);
     hipMemsetAsync(vmax, 0, sizeof(uint32_t), s);
     launch_absmax_f32(dvel, 3 * n, vmax, s);
     uint32_t vbits = 0;
     hipMemcpyAsync(&vbits, vmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     st = sync(c);
-    if (st != CUBE_OK) {
-        release();
-        return st;
-    }
+    if (st != CUBE_OK) return st;
     float vmaxf;
     std::memcpy(&vmaxf, &vbits, sizeof(float));
     double s0 = 1.0;
@@ -571,7 +672,6 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     launch_scatter_compressed(g, idx, qp, dvel, s0, c->A, c->counts, c->sc, n, s);
     hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s);
     st = sync(c);
-    release();
     if (st != CUBE_OK) return st;
     c->max_count = c->sc_host->max_count;
     c->has_state = true;
@@ -587,24 +687,14 @@ cube_status cube_decompress(cube_ctx* c, float* pos, float* vel, int64_t n, int3
     hipStream_t s = c->stream;
     float *dp = pos, *dv = vel;
     const size_t fb = (size_t)n * 3 * sizeof(float);
-    if (!on_device) {
-        if (hipMalloc(&dp, fb) != hipSuccess) return fail(CUBE_OOM, "decompress staging");
-        if (hipMalloc(&dv, fb) != hipSuccess) {
-            hipFree(dp);
-            return fail(CUBE_OOM, "decompress staging");
-        }
-    }
+    Temp tmp(c->mem);
+    if (!on_device && (!tmp.get(&dp, fb) || !tmp.get(&dv, fb))) return fail(CUBE_OOM, "decompress staging");
     launch_decode(g, c->offsets, c->A, c->sc, dp, dv, s);
     if (!on_device) {
         hipMemcpyAsync(pos, dp, fb, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(vel, dv, fb, hipMemcpyDeviceToHost, s);
     }
-    st = sync(c);
-    if (!on_device) {
-        hipFree(dp);
-        hipFree(dv);
-    }
-    return st;
+    return sync(c);
 }
 
 cube_status cube_pm_step(cube_ctx* c, int32_t nsteps) {
@@ -631,7 +721,9 @@ cube_status cube_forces(cube_ctx* c, float* acc, int32_t on_device) {
     hipStream_t s = c->stream;
     float* dacc = acc;
     const size_t bytes = (size_t)g.n * 3 * sizeof(float);
-    if (!on_device && hipMalloc(&dacc, bytes) != hipSuccess) return fail(CUBE_OOM, "forces staging");
+    Temp tmp(c->mem);
+    if (!on_device && !tmp.get(&dacc, bytes)) return fail(CUBE_OOM, "forces staging");
+    launch_fill_i32(&c->sc->overflow, 0, 1, s);
     coarse_potential(c);
     for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
         const int nt = std::min(c->batch, g.ntiles - t0);
@@ -641,8 +733,10 @@ cube_status cube_forces(cube_ctx* c, float* acc, int32_t on_device) {
         launch_gather(a, s);
     }
     if (!on_device) hipMemcpyAsync(acc, dacc, bytes, hipMemcpyDeviceToHost, s);
+    int32_t oflow = 0;
+    hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     st = sync(c);
-    if (!on_device) hipFree(dacc);
+    if (st == CUBE_OK && oflow) return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range");
     return st;
 }
 
@@ -721,9 +815,6 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
     const Geom& g = c->g;
     hipStream_t s = c->stream;
     const int chunks = (int)(g.ncells / g.Tc);
-    const int64_t gather_blocks = (int64_t)gather_blocks_per_tile(g) * c->batch;
-    st = ensure_partial(c, std::max<int64_t>(4 * (int64_t)chunks, gather_blocks));
-    if (st != CUBE_OK) return st;
     std::memset(out, 0, sizeof(*out));
     launch_moments(g, c->offsets, c->A, c->sc, c->partial, chunks, s);
     launch_reduce_partials(c->partial, chunks, 4, c->reduced, s);
@@ -746,6 +837,7 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
     out->step = c->step;
     out->last_step_ms = c->last_step_ms;
     // potential energy: 1/2 sum over particles of phi_f + phi_c at their positions
+    launch_fill_i32(&c->sc->overflow, 0, 1, s);
     coarse_potential(c);
     double wsum = 0.0;
     std::vector<double> part;
@@ -762,6 +854,11 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
         if (st != CUBE_OK) return st;
         for (double v : part) wsum += v;
     }
+    int32_t oflow = 0;
+    CUBE_HIP(hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    st = sync(c);
+    if (st != CUBE_OK) return st;
+    if (oflow) return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range");
     out->potential = 0.5 * wsum;
     return CUBE_OK;
 }
@@ -778,13 +875,10 @@ cube_status cube_power_spectrum(cube_ctx* c, int32_t nbins, double* k, double* p
     float2* tw = nullptr;
     double* part = nullptr;
     const int64_t cells = (int64_t)n * n * n;
-    if (hipMalloc(&mesh, cells * sizeof(float2)) != hipSuccess) return fail(CUBE_OOM, "P(k) mesh");
-    if (hipMalloc(&tw, n * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&part, (size_t)n * 3 * nbins * sizeof(double)) != hipSuccess) {
-        hipFree(mesh);
-        if (tw) hipFree(tw);
+    Temp tmp(c->mem);
+    if (!tmp.get(&mesh, cells * sizeof(float2)) || !tmp.get(&tw, n * sizeof(float2)) ||
+        !tmp.get(&part, (size_t)n * 3 * nbins * sizeof(double)))
         return fail(CUBE_OOM, "P(k) workspace");
-    }
     fft_make_twiddles(n, tw, s);
     launch_diag_deposit(g, c->offsets, c->A, mesh, s);
     fft3d(mesh, n, 1, false, tw, s);
@@ -792,9 +886,6 @@ cube_status cube_power_spectrum(cube_ctx* c, int32_t nbins, double* k, double* p
     std::vector<double> h((size_t)n * 3 * nbins);
     hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
     st = sync(c);
-    hipFree(mesh);
-    hipFree(tw);
-    hipFree(part);
     if (st != CUBE_OK) return st;
     for (int j = 0; j < nbins; ++j) {
         double ps = 0.0, ks = 0.0, cs = 0.0;

@@ -319,6 +319,58 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
     }
 }
 
+// ---- storage of the half spectra between the tile sweeps ----------------
+// FP32 complex, or one 32-bit word with two 16-bit values (real part in the
+// low half).  BF16 is rounded to nearest even from FP32 and needs no scaling;
+// FP16 values are stored times a power of two chosen by the host so that the
+// spectra of realistic densities and potentials stay inside its range, and
+// any value that would not fit raises the caller's flag.
+enum SpecFmt { SPEC_F32 = 0, SPEC_BF16 = 1, SPEC_F16 = 2 };
+
+template <int FMT>
+struct SpecStore;
+
+template <>
+struct SpecStore<SPEC_F32> {
+    using T = float2;
+    __device__ static float2 get(T v, float) { return v; }
+    __device__ static T put(float2 v, float, bool&) { return v; }
+};
+
+template <>
+struct SpecStore<SPEC_BF16> {
+    using T = uint32_t;
+    __device__ static float2 get(T v, float) {
+        return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+    }
+    __device__ static uint32_t bf16(float x) {
+        const uint32_t b = __float_as_uint(x);
+        return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+    }
+    __device__ static T put(float2 v, float, bool&) { return bf16(v.x) | (bf16(v.y) << 16); }
+};
+
+template <>
+struct SpecStore<SPEC_F16> {
+    using T = uint32_t;
+    __device__ static float h2f(uint32_t bits) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+    }
+    __device__ static uint32_t f2h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+    __device__ static float2 get(T v, float scale) {
+        return make_float2(h2f(v & 0xffffu) * scale, h2f(v >> 16) * scale);
+    }
+    __device__ static T put(float2 v, float scale, bool& bad) {
+        const float a = v.x * scale, b = v.y * scale;
+        bad = bad || !(fabsf(a) <= 65504.0f) || !(fabsf(b) <= 65504.0f);
+        return f2h(a) | (f2h(b) << 16);
+    }
+};
+
+__device__ __forceinline__ void raise_flag(bool bad, int32_t* flag) {
+    if (bad) *flag = 1;
+}
+
 // ---- real tile meshes: R2C / C2R through xy planes ---------------------
 // A tile's real mesh [z][y][x] (N^3 floats) maps to a half spectrum
 // [kz][ky][kx], kx in [0, N/2] (N^2 (N/2+1) complex).  One workgroup owns a
@@ -335,10 +387,12 @@ constexpr int kPlaneThreads = 512;
 // where the separated half-spectrum rows 2j and 2j+1 (stride N/2+1) go, so
 // the Hermitian separation is done row by row in place, one wave per row:
 // a wave's LDS reads all complete before its writes.
-template <int N>
+template <int N, int FMT>
 __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __restrict__ real_tiles,
-                                                             float2* __restrict__ spec_tiles,
-                                                             const float2* __restrict__ tw_g, int nplanes) {
+                                                             typename SpecStore<FMT>::T* __restrict__ spec_tiles,
+                                                             const float2* __restrict__ tw_g, int nplanes,
+                                                             float sc_out, int32_t* __restrict__ flag) {
+    using S = SpecStore<FMT>;
     constexpr int NH = N / 2 + 1;
     constexpr int HALF = N / 2;
     constexpr int RS = N + 2;                    // complex row stride = 2 NH
@@ -405,15 +459,19 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __rest
         }
         __syncthreads();
         Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, false>(lds, tw, tid);
-        float2* dst = spec_tiles + (int64_t)(plane / N) * N * N * NH + (int64_t)(plane % N) * N * NH;
-        for (int e = threadIdx.x; e < N * NH; e += kPlaneThreads) dst[e] = lds[e];
+        typename S::T* dst = spec_tiles + (int64_t)(plane / N) * N * N * NH + (int64_t)(plane % N) * N * NH;
+        bool bad = false;
+        for (int e = threadIdx.x; e < N * NH; e += kPlaneThreads) dst[e] = S::put(lds[e], sc_out, bad);
+        if (FMT == SPEC_F16) raise_flag(bad, flag);
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __restrict__ spec_tiles,
+template <int N, int FMT>
+__global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                              float* __restrict__ real_tiles,
-                                                             const float2* __restrict__ tw_g, int nplanes) {
+                                                             const float2* __restrict__ tw_g, int nplanes,
+                                                             float sc_in) {
+    using S = SpecStore<FMT>;
     constexpr int NH = N / 2 + 1;
     constexpr int HALF = N / 2;
     constexpr int RS = N + 2;
@@ -425,9 +483,9 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __res
     __shared__ float2 tw[N];
     for (int i = threadIdx.x; i < N; i += kPlaneThreads) tw[i] = tw_g[i];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    float2 pv[PER];
+    typename S::T pv[PER];
     auto prefetch = [&](int pl) {
-        const float2* src = spec_tiles + (int64_t)(pl / N) * N * N * NH + (int64_t)(pl % N) * N * NH;
+        const typename S::T* src = spec_tiles + (int64_t)(pl / N) * N * N * NH + (int64_t)(pl % N) * N * NH;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
@@ -441,7 +499,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __res
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
-            if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = pv[u];
+            if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = S::get(pv[u], sc_in);
         }
         __syncthreads();
         if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
@@ -485,19 +543,23 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const float2* __res
 
 // z pencils of the half spectrum: forward, times G (float octant), inverse.
 // Twiddles and the block's Green's values are staged in LDS with the data.
-template <int N>
-__global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__ spec_tiles,
+template <int N, int FMT>
+__global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                             const float2* __restrict__ tw_g,
-                                                            const float* __restrict__ green) {
+                                                            const float* __restrict__ green, float sc_in,
+                                                            float sc_out, int32_t* __restrict__ flag) {
+    using S = SpecStore<FMT>;
+    using T = typename S::T;
     constexpr int NH = N / 2 + 1;
     constexpr int W = 16;
     constexpr int LDN = N + 1;
     constexpr int PLANE = N * NH;
+    constexpr int U = 10;
     __shared__ float2 lds[W * LDN];
     __shared__ float2 tw[N];
     __shared__ float gl[W * NH];                   // G(kz folded, this block's (ky, kx))
     const int c0 = blockIdx.x * W;                 // flattened (ky, kx) of the first pencil
-    float2* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
+    T* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
     for (int i = threadIdx.x; i < N; i += kFftThreads) tw[i] = tw_g[i];
     for (int e = threadIdx.x; e < W * NH; e += kFftThreads) {
         const int w = e % W, fz = e / W;
@@ -505,9 +567,20 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__
         const int ky = c / NH, kx = c - ky * NH;
         gl[e] = green[((int64_t)fz * NH + fold(ky, N)) * NH + kx];
     }
-    stage_to_lds<kFftThreads, 10>(
-        W * N, g, lds, [](int e) { return (int64_t)(e / W) * PLANE + (e % W); },
-        [](int e) { return (e % W) * LDN + e / W; });
+    // element e: pencil w = e % W, kz = e / W (16 consecutive words per kz)
+    for (int base = 0; base < W * N; base += kFftThreads * U) {
+        T tmp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kFftThreads + (int)threadIdx.x;
+            if (e < W * N) tmp[u] = g[(int64_t)(e / W) * PLANE + (e % W)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kFftThreads + (int)threadIdx.x;
+            if (e < W * N) lds[(e % W) * LDN + e / W] = S::get(tmp[u], sc_in);
+        }
+    }
     __syncthreads();
     using L = Lay<W, 1, LDN, false, kFftThreads>;
     Plan<N>::template run<L, false>(lds, tw);
@@ -519,39 +592,66 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(float2* __restrict__
     }
     __syncthreads();
     Plan<N>::template run<L, true>(lds, tw);
+    bool bad = false;
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
         const int w = e % W, i = e / W;
-        g[(int64_t)i * PLANE + w] = lds[w * LDN + i];
+        g[(int64_t)i * PLANE + w] = S::put(lds[w * LDN + i], sc_out, bad);
     }
+    if (FMT == SPEC_F16) raise_flag(bad, flag);
 }
 
 int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
+    static const int cus = [] {
+        int dev = 0, v = 0;
         hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        return v;
+    }();
     return cus;
 }
 
-template <int N>
-void launch_tiles(float* real_tiles, float2* spec_tiles, int ntiles, const float2* tw, const float* green,
-                  hipStream_t s, hipEvent_t* ev) {
+template <int N, int FMT>
+void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* tw, const float* green,
+                      int32_t* flag, hipStream_t s, hipEvent_t* ev) {
     constexpr int NH = N / 2 + 1;
+    using T = typename SpecStore<FMT>::T;
+    T* spec_tiles = static_cast<T*>(spec);
+    // FP16 scales.  The xy-plane spectra of the density are sums of N^2
+    // cells: stored times 2^-e with 2^e >= N^2 they stay below max|rho - 1|
+    // (the host keeps that inside the FP16 range).  After the z pencils and
+    // the Green's multiply (which carries the 1/N^3 of the inverse
+    // transform) the values are the normalised 2-D coefficients of the
+    // potential, bounded by max|phi| and typically max|phi| / N: stored times
+    // 2^5 they keep clear of the subnormal range and overflow (the flag) only
+    // beyond |phi| ~ 2^11.
+    int e = 0;
+    while ((1 << e) < N * N) ++e;
+    const bool h = FMT == SPEC_F16;
+    const float rho_store = h ? std::ldexp(1.0f, -e) : 1.0f, rho_load = h ? std::ldexp(1.0f, e) : 1.0f;
+    const float phi_store = h ? 32.0f : 1.0f, phi_load = h ? 1.0f / 32.0f : 1.0f;
     if (ev) hipEventRecord(ev[0], s);
     const int nplanes = N * ntiles;
     const int blocks = std::min(nplanes, device_cus());
-    hipLaunchKernelGGL(k_r2c_plane<N>, dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw, nplanes);
+    hipLaunchKernelGGL((k_r2c_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw,
+                       nplanes, rho_store, flag);
     if (ev) hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL(k_zconv_half<N>, dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw, green);
+    hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw,
+                       green, rho_load, phi_store, flag);
     if (ev) hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_c2r_plane<N>, dim3(blocks), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw, nplanes);
+    hipLaunchKernelGGL((k_c2r_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw,
+                       nplanes, phi_load);
     if (ev) hipEventRecord(ev[3], s);
 }
 
-using TilesFn = void (*)(float*, float2*, int, const float2*, const float*, hipStream_t, hipEvent_t*);
+template <int N>
+void launch_tiles(float* real_tiles, void* spec, int ntiles, const float2* tw, const float* green, int fmt,
+                  int32_t* flag, hipStream_t s, hipEvent_t* ev) {
+    if (fmt == SPEC_BF16) launch_tiles_fmt<N, SPEC_BF16>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
+    else if (fmt == SPEC_F16) launch_tiles_fmt<N, SPEC_F16>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
+    else launch_tiles_fmt<N, SPEC_F32>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
+}
+
+using TilesFn = void (*)(float*, void*, int, const float2*, const float*, int, int32_t*, hipStream_t, hipEvent_t*);
 
 TilesFn tiles_for(int n) {
     switch (n) {
@@ -617,9 +717,10 @@ bool fft_supported(int n) { return pass_for(n) != nullptr; }
 
 bool fft_tiles_supported(int n) { return tiles_for(n) != nullptr; }
 
-void fft_tiles_convolve(float* real_tiles, float2* spec_tiles, int n, int ntiles, const float2* tw,
-                        const float* green_octant, hipStream_t s, hipEvent_t* ev) {
-    tiles_for(n)(real_tiles, spec_tiles, ntiles, tw, green_octant, s, ev);
+void fft_tiles_convolve(float* real_tiles, void* spec_tiles, int n, int ntiles, const float2* tw,
+                        const float* green_octant, int spec_format, int32_t* range_flag, hipStream_t s,
+                        hipEvent_t* ev) {
+    tiles_for(n)(real_tiles, spec_tiles, ntiles, tw, green_octant, spec_format, range_flag, s, ev);
 }
 
 void fft_make_twiddles(int n, float2* dev_table, hipStream_t s) {

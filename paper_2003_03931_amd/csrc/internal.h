@@ -8,6 +8,9 @@
 
 namespace cube {
 
+// Sets the calling thread's message returned by cube_last_error().
+void set_last_error(const char* msg);
+
 // Box geometry in the integer units the kernels use (Sec. II tiles + buffers,
 // Sec. III-A coarse-cell codec).  All sides are cell counts.
 struct Geom {
@@ -59,7 +62,7 @@ struct StepScalars {
     int32_t far_count;   // particles whose carry exceeds one cell
     int32_t max_carry;   // max |carry| of the step
     int64_t saturations; // clamped velocity components (cumulative)
-    int32_t overflow;    // an exact accumulator would overflow
+    int32_t overflow;    // a 16-bit spectrum value was out of range (cleared by the prologue)
     int32_t max_count;   // largest cell count of the newest counts (set by the scan)
     // per-block maxima land in 64 slots (spreads atomic contention); the
     // epilogue folds them into max_u / max_carry
@@ -123,11 +126,14 @@ void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void
 
 // Real tile meshes (ntiles cubes of n^3 floats, [z][y][x]) -> convolution with
 // a real even octant table through half spectra (n^2 (n/2+1) complex per
-// tile, workspace) -> potentials in place.  ev (optional, 4 events) is
+// tile, workspace) -> potentials in place.  spec_format: 0 FP32 complex,
+// 1 BF16 pairs, 2 scaled FP16 pairs (4 bytes per complex value); with FP16 an
+// out-of-range value sets *range_flag = 1.  ev (optional, 4 events) is
 // recorded before the first and after each of the three sweeps.
 bool fft_tiles_supported(int n);
-void fft_tiles_convolve(float* real_tiles, float2* spec_tiles, int n, int ntiles, const float2* tw,
-                        const float* green_octant, hipStream_t s, hipEvent_t* ev = nullptr);
+void fft_tiles_convolve(float* real_tiles, void* spec_tiles, int n, int ntiles, const float2* tw,
+                        const float* green_octant, int spec_format, int32_t* range_flag, hipStream_t s,
+                        hipEvent_t* ev = nullptr);
 
 // ---- green.hip ----------------------------------------------------------
 // FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).

@@ -26,6 +26,7 @@ __global__ void k_prologue(StepScalars* sc, float hv) {
     sc->max_u_next = 0;
     sc->far_count = 0;
     sc->max_carry = 0;
+    sc->overflow = 0;
     for (int i = 0; i < 64; ++i) {
         sc->umax_slot[i] = 0;
         sc->cmax_slot[i] = 0;

@@ -45,8 +45,61 @@ def test_invalid_descriptor_is_rejected_without_a_gpu():
     lib = load()
     ctx = ctypes.c_void_p()
     bad = BoxDesc(32, 1, 2, 3, 0, 12, 0.05, 2.0, 0, 0, 0, 0)      # r = 3 is not a power of two
-    assert lib.cube_init(ctypes.byref(bad), None, ctypes.byref(ctx)) == 1
+    assert lib.cube_init(ctypes.byref(bad), None, None, ctypes.byref(ctx)) == 1
     assert b"power" in lib.cube_last_error()
     bad2 = BoxDesc(64, 4, 2, 4, 8, 12, 0.05, 2.0, 0, 0, 0, 0)     # a > b - 3
-    assert lib.cube_init(ctypes.byref(bad2), None, ctypes.byref(ctx)) == 1
-    assert lib.cube_init(None, None, ctypes.byref(ctx)) == 1
+    assert lib.cube_init(ctypes.byref(bad2), None, None, ctypes.byref(ctx)) == 1
+    assert lib.cube_init(None, None, None, ctypes.byref(ctx)) == 1
+    bad3 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 7, 0, 0, 0)     # unknown precision
+    assert lib.cube_init(ctypes.byref(bad3), None, None, ctypes.byref(ctx)) == 1
+    assert b"precision" in lib.cube_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
+def test_footprint_is_host_only_and_grows_with_the_batch():
+    """cube_footprint validates and sizes without touching a device."""
+    from cube_inputs import config
+    from paper_2003_03931_amd import footprint
+    spec = config("t4")
+    p1, t1 = footprint(spec, tiles_per_batch=1)
+    p8, t8 = footprint(spec, tiles_per_batch=8)
+    F = 64 * 2 // 4 + 2 * 16
+    # each extra tile in flight holds one real mesh and one FP32 half spectrum
+    per_tile = 4 * F ** 3 + 8 * F * F * (F // 2 + 1)
+    assert p8 - p1 >= 7 * per_tile
+    n = spec.n_side ** 3
+    assert p1 >= 12 * n and t1 >= 24 * n          # planes; host staging of compress
+    from paper_2003_03931_amd._lib import BoxDesc, load
+    lib = load()
+    bad = BoxDesc(32, 1, 2, 3, 0, 12, 0.05, 2.0, 0, 0, 0, 0)
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.cube_footprint(ctypes.byref(bad), ctypes.byref(a), ctypes.byref(b)) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
+def test_server_rejects_bad_requests_without_a_gpu():
+    """Server creation and request validation are host-side; a box whose
+    footprint exceeds the whole budget is refused at submit."""
+    from cube_inputs import config
+    from paper_2003_03931_amd._lib import Request, ServerDesc, load
+    from paper_2003_03931_amd import desc_from
+    lib = load()
+    srv = ctypes.c_void_p()
+    assert lib.cube_server_create(ctypes.byref(ServerDesc(0, 1, -1, 0, 0)), ctypes.byref(srv)) == 1
+    assert lib.cube_server_create(ctypes.byref(ServerDesc(1 << 20, 0, -1, 0, 0)), ctypes.byref(srv)) == 1
+    assert lib.cube_server_create(ctypes.byref(ServerDesc(1 << 20, 1, -1, 0, 0)), ctypes.byref(srv)) == 0
+    try:
+        spec = config("c1")
+        import numpy as np
+        pos = np.zeros((spec.n_side ** 3, 3), np.float32)
+        req = Request(desc_from(spec), 1, 0, pos.ctypes.data, pos.ctypes.data, spec.n_side ** 3, None)
+        t = ctypes.c_uint64()
+        assert lib.cube_submit(srv, ctypes.byref(req), ctypes.byref(t)) == 1     # 1 MiB budget: never fits
+        assert b"budget" in lib.cube_last_error()
+        req.n = 5
+        assert lib.cube_submit(srv, ctypes.byref(req), ctypes.byref(t)) == 1
+        from paper_2003_03931_amd._lib import Result
+        r = Result()
+        assert lib.cube_poll(srv, ctypes.c_uint64(12345), ctypes.byref(r)) == 1
+    finally:
+        lib.cube_server_destroy(srv)

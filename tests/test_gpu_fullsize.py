@@ -1,0 +1,146 @@
+"""Parity at the full 1024^3 size, in the launch configuration the benchmark
+times (64 tiles per batch), on outputs the oracle can compute tile by tile.
+
+Input: the 2-per-axis lattice (8 particles per coarse cell) whose CIC density
+is exactly uniform on both meshes, with runs of cells whose particles are
+placed, counted and moving at random (cube_inputs.lattice_run_state).  By
+linearity the oracle's coarse density is the deposit of the run particles
+minus that of the lattice particles they replaced; the fine mesh of a sampled
+tile needs only that tile's sources.  Both sides start from the same bytes.
+"""
+
+import types
+
+import numpy as np
+import pytest
+
+from cube_inputs import config, lattice_run_state
+from cube_inputs.lattice import LATTICE_BYTES
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+S_V = 2.0 ** -6
+BATCH = 64
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from oracle import cic, green, pm
+    from paper_2003_03931_amd import CubeBox
+    spec = config("c3")
+    box = oracle.Box.from_spec(spec).validate()
+    Tc = box.Tc
+    ta = 5 + 16 * (5 + 16 * 5)          # tile (5, 5, 5): a 4-layer run in its middle
+    tb = 10 + 16 * (10 + 16 * 10)       # a run over the last layer of tile tb-1 and the first of tb
+    runs = [(ta * Tc ** 3 + 12 * Tc * Tc, 4 * Tc * Tc), (tb * Tc ** 3 - Tc * Tc, 2 * Tc * Tc)]
+    counts, m, u = lattice_run_state(box.n_cells, runs, seed=3001)
+    M = int(np.abs(u.astype(np.int64)).max())
+    off = np.zeros(box.n_cells + 1, np.int64)
+    np.cumsum(counts, out=off[1:])
+    print(f"state: n={counts.sum()} runs={runs} M={M}", flush=True)
+
+    # ---- GPU: forces, then one step
+    g = CubeBox(spec, tiles_per_batch=BATCH)
+    g.set_state(counts, m, u, S_V, M)
+    acc = g.forces()
+    tiles = [ta, ta + 1, tb - 1, tb, 0]
+    print("gpu forces done", flush=True)
+
+    # ---- oracle: coarse density of the runs relative to the lattice
+    lo, hi = LATTICE_BYTES
+    pat = np.array([[a, b, c] for c in (lo, hi) for b in (lo, hi) for a in (lo, hi)], np.int64)
+    dmass = np.zeros((box.n_coarse,) * 3)
+    for c0, L in runs:
+        cells = np.arange(c0, c0 + L)
+        _, Qp = pm.quanta_of_cells(box, counts, off, m, cells)
+        cx, cy, cz = box.cell_of_canon(np.repeat(cells, 8))
+        Ql = np.stack([256 * cx, 256 * cy, 256 * cz], 1) + np.tile(pat, (L, 1))
+        dmass += cic.deposit((Qp + 0.5) / 256.0, box.n_coarse)
+        dmass -= cic.deposit((Ql + 0.5) / 256.0, box.n_coarse)
+    rho_c = dmass / box.H ** 3
+    del dmass
+    Gf = green.fine_green(box)
+    per_tile = []
+    for t in tiles:
+        tgt, Qt, af = pm.tile_force_sampled(box, counts, off, m, t, Gf)
+        per_tile.append((t, tgt, Qt, af))
+    Qall = np.concatenate([p[2] for p in per_tile])
+    ac = pm.coarse_force_at(box, rho_c, green.coarse_green(box), Qall)
+    print("oracle forces done", flush=True)
+    ref, k = {}, 0
+    for t, tgt, Qt, af in per_tile:
+        ref[t] = (tgt, Qt, af + ac[k:k + tgt.size])
+        k += tgt.size
+    got = {}
+    for t, tgt, _, _ in per_tile:
+        got[t] = acc[torch.from_numpy(tgt).to(acc.device)].cpu().numpy()
+    del acc
+    torch.cuda.empty_cache()
+
+    g.step(1)
+    st = g.get_state()
+    g.close()
+    print("gpu step done", flush=True)
+    return types.SimpleNamespace(box=box, spec=spec, counts=counts, off=off, m=m, u=u, M=M, ref=ref, got=got,
+                                 tiles=tiles, ta=ta, tb=tb, state=st)
+
+
+def test_full_size_forces_on_sampled_tiles(full):
+    a = np.concatenate([full.got[t] for t in full.tiles])
+    b = np.concatenate([full.ref[t][2] for t in full.tiles])
+    err = rel_l2(a, b)
+    print(f"sampled-tile force relative L2 {err:.3e} over {a.shape[0]} particles")
+    assert err <= 1e-5
+    for t in (full.ta, full.tb - 1, full.tb):
+        assert rel_l2(full.got[t], full.ref[t][2]) <= 1e-5
+
+
+def test_full_size_step_on_sampled_tile(full):
+    """One step: velocity scale exact, mass conserved, and the particles that
+    land in the interior cells of the run tile arrive with the oracle's bytes,
+    in the oracle's stable order."""
+    from oracle import codec, step
+    box, st = full.box, full.state
+    assert st["counts"].sum() == box.n_side ** 3
+    assert st["s"] == codec.next_velocity_scale(box, S_V, full.M)
+
+    t = full.ta
+    tgt, Qt, a = full.ref[t]
+    old = types.SimpleNamespace(u=full.u[:, tgt], s=S_V, M=full.M, m=full.m[:, tgt], quanta=lambda: Qt)
+    u_new, s_new, _, _ = step.kick(box, old, a)
+    Q_new, carry = step.drift(box, old, u_new, s_new)
+    assert np.abs(carry).max() <= 1
+    cx, cy, cz = (Q_new // 256).T
+    Tc = box.Tc
+    tx, ty, tz = box.tile_coords(t)
+    lx, ly, lz = cx - tx * Tc, cy - ty * Tc, cz - tz * Tc
+    inner = (lx >= 1) & (lx <= Tc - 2) & (ly >= 1) & (ly <= Tc - 2) & (lz >= 1) & (lz <= Tc - 2)
+    dest = box.canon(cx, cy, cz)[inner]
+    order = np.lexsort((tgt[inner], dest))          # new order: by cell, then old order (stable)
+    dest = dest[order]
+    exp_m = (Q_new[inner] % 256)[order].T
+    exp_u = u_new[inner][order].T
+
+    r = np.arange(1, Tc - 1)
+    zz, yy, xx = np.meshgrid(r + tz * Tc, r + ty * Tc, r + tx * Tc, indexing="ij")
+    cells = np.sort(box.canon(xx.ravel(), yy.ravel(), zz.ravel()))
+    cnt_g = st["counts"][cells].astype(np.int64)
+    cnt_o = np.bincount(np.searchsorted(cells, dest), minlength=cells.size)
+    same_cells = cnt_g == cnt_o
+    assert np.mean(same_cells) >= 0.999
+    off_new = np.zeros(st["counts"].size + 1, np.int64)
+    np.cumsum(st["counts"], out=off_new[1:])
+    from oracle.pm import _expand_ranges
+    gi = _expand_ranges(off_new[cells[same_cells]], cnt_g[same_cells])
+    oi = _expand_ranges((np.cumsum(cnt_o) - cnt_o)[same_cells], cnt_o[same_cells])
+    dm = np.abs(st["m"][:, gi].astype(np.int64) - exp_m[:, oi]).max(axis=0)
+    du = np.abs(st["u"][:, gi].astype(np.int64) - exp_u[:, oi]).max(axis=0)
+    print(f"step: {gi.size} particles compared, exact {np.mean((dm == 0) & (du == 0)):.6f}")
+    assert np.mean((dm == 0) & (du == 0)) >= 0.999
+    assert dm.max() <= 1 and du.max() <= 1

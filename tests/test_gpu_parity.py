@@ -230,3 +230,39 @@ def test_dense_cell_paths(n_dense):
     assert st["counts"].sum() == ref.n
     d = _compare_by_id(box, st, o)
     assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
+
+
+# ---------------------------------------------------------- diagnostics
+@pytest.mark.parametrize("name,nsteps", [("t4", 0), ("c2s", 2)])
+def test_power_spectrum_matches_oracle(name, nsteps):
+    """P(k) of the same state: every shell with k < k_Ny/2 within 0.1%."""
+    from oracle import diag, pm, step
+    box, ref = oracle_state(name)
+    o = ref
+    for _ in range(nsteps):
+        o = step.step(pm.Solver(box), o, workers=1)
+    k_o, p_o, n_o = diag.power_spectrum(o)
+    with gpu_box(name) as g:
+        load_state(g, o)
+        k_g, p_g, n_g = g.power_spectrum()
+    assert np.array_equal(n_g, n_o)
+    assert np.allclose(k_g, k_o, rtol=1e-12)
+    assert np.max(np.abs(p_g / p_o - 1.0)) <= 1e-3
+
+
+@pytest.mark.parametrize("name", ["t4", "c2s"])
+def test_diagnostics_match_oracle(name):
+    """FP64 mass, momentum and kinetic energy of the decoded state, and the
+    potential energy (sum of FP32 potentials at the particles)."""
+    from oracle import diag, pm
+    box, ref = oracle_state(name)
+    mo = diag.moments(ref)
+    w = diag.potential_energy(pm.Solver(box), ref, workers=1)
+    with gpu_box(name) as g:
+        load_state(g, ref)
+        d = g.diagnostics()
+    assert d["mass"] == mo["mass"]
+    scale = np.sqrt(2.0 * mo["kinetic"])
+    assert np.max(np.abs(d["momentum"] - mo["momentum"])) <= 1e-12 * scale * np.sqrt(ref.n)
+    assert abs(d["kinetic"] / mo["kinetic"] - 1.0) <= 1e-13
+    assert abs(d["potential"] / w - 1.0) <= 1e-5
