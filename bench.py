@@ -8,10 +8,13 @@ displacement 2 spacings, 6 bytes per particle, FP32 meshes.  A step is one
 full cube_pm_step (deposits, both Poisson solves, gather, kick, drift,
 recount, compaction) with the state resident in HBM.
 
-Prints one JSON line: throughput in particle-steps/s, the dominant kernel's
-achieved bandwidth against the 8 TB/s HBM peak (HIP events on the library
-stream over the timed region), and the FP64 oracle timed on the host cores on
-a bounded sample of the same tile geometry.
+Prints one JSON line: throughput in particle-steps/s (FP32 spectra; the
+BF16 and FP16 spectrum stores on the same input beside it), the dominant
+kernel's achieved bandwidth against the 8 TB/s HBM peak (HIP events on the
+library stream over the timed region), the FP64 oracle timed on the host
+cores on a bounded sample of the same tile geometry, and a served stream of
+boxes (p50/p99 time to completion, aggregate particle-steps/s).  --batched N
+adds an ensemble of N boxes run concurrently against one at a time.
 """
 
 import argparse
@@ -57,6 +60,82 @@ def cpu_baseline(sample="c3cpu"):
                       f"8 particles per coarse cell): {n} particle-steps in {dt:.2f} s"}
 
 
+def served_spec(n_side, spectral_index, seed, name):
+    """Periodic box for the serving / batched workloads: f = 2, r = 4, tiles of
+    64^3 particles (48^3 for the 96^3 box, whose tile box is then 128^3), a
+    16-cell buffer and a 12-cell split radius; one periodic tile at 64^3."""
+    from cube_inputs import BoxSpec
+    from cube_inputs.configs import DT
+    if n_side == 64:
+        nt, b = 1, 0
+    elif n_side == 96:
+        nt, b = 2, 16
+    else:
+        nt, b = n_side // 64, 16
+    return BoxSpec(name, n_side, nt, 2, 4, b, 12, DT, 2.0, spectral_index, 0.5, seed, 1)
+
+
+def make_requests(kind, count, rng_seed):
+    """(spec, pos, vel, steps, arrival_s) per request.
+    serving: sides log-uniform over [64, 256] rounded to multiples of 64,
+    steps uniform in [5, 50], exponential inter-arrivals at 4 per second.
+    batched: sides from {64, 96, 128, 192, 256}, 16 steps, all at t = 0.
+    Both: P(k) ~ k^n with n uniform in [-2.5, -1], rms displacement 0.5."""
+    import numpy as np
+    from cube_inputs import zeldovich_ics
+    rng = np.random.default_rng(rng_seed)
+    out, t = [], 0.0
+    for i in range(count):
+        if kind == "serving":
+            side = int(np.clip(64 * round(np.exp(rng.uniform(np.log(64), np.log(256))) / 64), 64, 256))
+            steps = int(rng.integers(5, 51))
+            t += rng.exponential(1.0 / 4.0)
+        else:
+            side = int(rng.choice([64, 96, 128, 192, 256]))
+            steps = 16
+        n_index = float(rng.uniform(-2.5, -1.0))
+        spec = served_spec(side, n_index, rng_seed + 1 + i, f"{kind}{i}")
+        pos, vel = zeldovich_ics(side, n_index, 0.5, spec.seed, spec.dt)
+        out.append((spec, pos, vel, steps, t if kind == "serving" else 0.0))
+    return out
+
+
+def run_server(reqs, slots, budget, precision, realtime):
+    """Submit the requests (at their arrival times when realtime) to one
+    server; returns per-request results and the wall time."""
+    from paper_2003_03931_amd import CubeServer
+    with CubeServer(budget, max_slots=slots, precision=precision) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for spec, pos, vel, steps, at in reqs:
+            if realtime:
+                delay = at - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(spec, pos, vel, steps))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+    bad = [r["message"] for r in res if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"served request failed: {bad[0]}")
+    return res, wall
+
+
+def serving_report(reqs, res, wall, slots, budget, precision):
+    import numpy as np
+    ttc = np.array([r["done_ms"] - r["submit_ms"] for r in res])
+    wait = np.array([r["start_ms"] - r["submit_ms"] for r in res])
+    ps = sum(spec.n_side ** 3 * steps for spec, _, _, steps, _ in reqs)
+    span_s = (max(r["done_ms"] for r in res) - min(r["submit_ms"] for r in res)) * 1e-3
+    return {"requests": len(res), "slots": slots, "hbm_budget_gb": budget / 1e9, "precision": precision,
+            "p50_ms": float(np.percentile(ttc, 50)), "p99_ms": float(np.percentile(ttc, 99)),
+            "admission_wait_p50_ms": float(np.percentile(wait, 50)),
+            "admission_wait_p99_ms": float(np.percentile(wait, 99)),
+            "particle_steps_per_s": ps / span_s, "wall_s": wall,
+            "workload": "Poisson arrivals at 4/s; sides log-uniform in [64, 256] (multiples of 64); steps "
+                        "uniform in [5, 50]; Zel'dovich ICs, n uniform in [-2.5, -1], rms 0.5"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +146,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device copy to run first (counter calibration)")
+    ap.add_argument("--mixed-steps", type=int, default=10,
+                    help="timed steps of each mixed-precision run (0 skips them)")
+    ap.add_argument("--serving", type=int, default=40, help="requests of the serving run (0 skips it)")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--batched", type=int, default=0,
+                    help="boxes of the batched-ensemble run (slots vs one at a time); 0 skips it")
+    ap.add_argument("--batched-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -102,7 +188,6 @@ def main():
     log(f"initial conditions done in {time.perf_counter() - t:.1f} s")
     box = CubeBox(spec, tiles_per_batch=args.tiles_per_batch)
     box.compress(pos, vel)
-    del pos, vel
     log("compressed; warmup ...")
     box.step(args.warmup)
     torch.cuda.synchronize()
@@ -116,8 +201,56 @@ def main():
     stages = box.profile_read()
     box.profile(False)
     diag = box.diagnostics()
+    F, n_coarse = box.F, box.n_coarse
     box.close()
+    del box
+    torch.cuda.empty_cache()
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    # the same input with the 16-bit spectrum stores
+    mixed = {}
+    for prec in ("bf16", "fp16") if args.mixed_steps > 0 else ():
+        mb = CubeBox(spec, tiles_per_batch=args.tiles_per_batch, precision=prec)
+        mb.compress(pos, vel)
+        mb.step(1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mb.step(args.mixed_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        mb.close()
+        del mb
+        torch.cuda.empty_cache()
+        mixed[prec] = {"value": n * args.mixed_steps / el, "ms_per_step": 1e3 * el / args.mixed_steps,
+                       "steps": args.mixed_steps}
+        log(f"{prec}: {1e3 * el / args.mixed_steps:.1f} ms/step")
+    del pos, vel
+
+    serving = None
+    if args.serving > 0:
+        log(f"serving: {args.serving} requests ...")
+        reqs = make_requests("serving", args.serving, 5000)
+        budget = 240 * 10 ** 9
+        res, wall = run_server(reqs, args.serving_slots, budget, 2, realtime=True)
+        serving = serving_report(reqs, res, wall, args.serving_slots, budget, "fp16")
+        del reqs
+        log(f"serving p50 {serving['p50_ms']:.0f} ms, p99 {serving['p99_ms']:.0f} ms, "
+            f"{serving['particle_steps_per_s']:.3e} particle-steps/s")
+
+    batched = None
+    if args.batched > 0:
+        log(f"batched ensemble: {args.batched} boxes ...")
+        reqs = make_requests("batched", args.batched, 4000)
+        budget = 240 * 10 ** 9
+        res_k, wall_k = run_server(reqs, args.batched_slots, budget, -1, realtime=False)
+        res_1, wall_1 = run_server(reqs, 1, budget, -1, realtime=False)
+        ps = sum(sp.n_side ** 3 * st for sp, _, _, st, _ in reqs)
+        batched = {"boxes": len(reqs), "slots": args.batched_slots, "particles": sum(sp.n_side ** 3 for sp, *_ in reqs),
+                   "steps_per_box": 16, "concurrent_particle_steps_per_s": ps / wall_k,
+                   "one_at_a_time_particle_steps_per_s": ps / wall_1, "speedup": wall_1 / wall_k,
+                   "workload": "sides from {64,96,128,192,256}, n uniform in [-2.5,-1], rms 0.5, FP32"}
+        del reqs
+        log(f"batched: {batched['speedup']:.2f}x over one at a time")
 
     total_stage_ms = sum(s["total_ms"] for s in stages)
     for s in sorted(stages, key=lambda s: -s["total_ms"]):
@@ -146,7 +279,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{spec.name}: {spec.n_side}^3 particles, {spec.tiles_per_dim}^3 tiles, "
-                        f"fine FFT box {box.F}^3 per tile, coarse mesh {box.n_coarse}^3, r_cut "
+                        f"fine FFT box {F}^3 per tile, coarse mesh {n_coarse}^3, r_cut "
                         f"{spec.r_cut_fine} fine cells, Zel'dovich ICs P(k)~k^{spec.spectral_index} rms "
                         f"{spec.rms_disp}, 6 B/particle state, FP32 meshes",
             "n_particles": n,
@@ -165,6 +298,9 @@ def main():
             "bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": base,
+        "mixed": mixed,
+        "serving": serving,
+        "batched": batched,
         "diagnostics": {"mass": diag["mass"], "max_carry": diag["max_carry"], "max_u": diag["max_u"],
                         "saturations": diag["saturations"]},
         "stages_ms_per_step": {s["name"]: s["total_ms"] / args.steps for s in stages if s["launches"]},

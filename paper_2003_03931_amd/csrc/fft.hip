@@ -46,7 +46,7 @@ struct Dft;
 
 template <bool INV>
 struct Dft<2, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         float2 t = a[0];
         a[0] = cadd(t, a[1]);
         a[1] = csub(t, a[1]);
@@ -55,7 +55,7 @@ struct Dft<2, INV> {
 
 template <bool INV>
 struct Dft<3, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         const float s3 = 0.86602540378443864676f;
         float2 t = cadd(a[1], a[2]);
         float2 m = csub(a[0], cscale(t, 0.5f));
@@ -68,7 +68,7 @@ struct Dft<3, INV> {
 
 template <bool INV>
 struct Dft<4, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
         float2 t2 = cadd(a[1], a[3]), t3 = mul_j<INV>(csub(a[1], a[3]));
         a[0] = cadd(t0, t2);
@@ -80,7 +80,7 @@ struct Dft<4, INV> {
 
 template <bool INV>
 struct Dft<5, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
         const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
         float2 b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
@@ -99,7 +99,7 @@ struct Dft<5, INV> {
 
 template <bool INV>
 struct Dft<7, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         const float c1 = 0.62348980185873353053f, c2 = -0.22252093395631440429f, c3 = -0.90096886790241912624f;
         const float s1 = 0.78183148246802980871f, s2 = 0.97492791218182360702f, s3 = 0.43388373911755812048f;
         float2 b1 = cadd(a[1], a[6]), b2 = cadd(a[2], a[5]), b3 = cadd(a[3], a[4]);
@@ -123,7 +123,7 @@ struct Dft<7, INV> {
 
 template <bool INV>
 struct Dft<8, INV> {
-    __device__ static void run(float2* a) {
+    __device__ __forceinline__ static void run(float2* a) {
         const float c = 0.70710678118654752440f;
         float2 e[4] = {a[0], a[2], a[4], a[6]};
         float2 o[4] = {a[1], a[3], a[5], a[7]};
@@ -216,8 +216,9 @@ struct Plan;
     template <>                                                                  \
     struct Plan<NN> {                                                            \
         template <class L, bool INV>                                             \
-        __device__ static void run(float2* lds, const float2* __restrict__ tw,   \
-                                   int tid = threadIdx.x) {                      \
+        __device__ __forceinline__ static void run(float2* lds,                  \
+                                                   const float2* __restrict__ tw, \
+                                                   int tid = threadIdx.x) {      \
             run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw, tid);                \
         }                                                                        \
     };
@@ -333,34 +334,34 @@ struct SpecStore;
 template <>
 struct SpecStore<SPEC_F32> {
     using T = float2;
-    __device__ static float2 get(T v, float) { return v; }
-    __device__ static T put(float2 v, float, bool&) { return v; }
+    __device__ __forceinline__ static float2 get(T v, float) { return v; }
+    __device__ __forceinline__ static T put(float2 v, float, bool&) { return v; }
 };
 
 template <>
 struct SpecStore<SPEC_BF16> {
     using T = uint32_t;
-    __device__ static float2 get(T v, float) {
+    __device__ __forceinline__ static float2 get(T v, float) {
         return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
     }
-    __device__ static uint32_t bf16(float x) {
+    __device__ __forceinline__ static uint32_t bf16(float x) {
         const uint32_t b = __float_as_uint(x);
         return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
     }
-    __device__ static T put(float2 v, float, bool&) { return bf16(v.x) | (bf16(v.y) << 16); }
+    __device__ __forceinline__ static T put(float2 v, float, bool&) { return bf16(v.x) | (bf16(v.y) << 16); }
 };
 
 template <>
 struct SpecStore<SPEC_F16> {
     using T = uint32_t;
-    __device__ static float h2f(uint32_t bits) {
+    __device__ __forceinline__ static float h2f(uint32_t bits) {
         return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
     }
-    __device__ static uint32_t f2h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
-    __device__ static float2 get(T v, float scale) {
+    __device__ __forceinline__ static uint32_t f2h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+    __device__ __forceinline__ static float2 get(T v, float scale) {
         return make_float2(h2f(v & 0xffffu) * scale, h2f(v >> 16) * scale);
     }
-    __device__ static T put(float2 v, float scale, bool& bad) {
+    __device__ __forceinline__ static T put(float2 v, float scale, bool& bad) {
         const float a = v.x * scale, b = v.y * scale;
         bad = bad || !(fabsf(a) <= 65504.0f) || !(fabsf(b) <= 65504.0f);
         return f2h(a) | (f2h(b) << 16);
