@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--batched", type=int, default=0,
                     help="boxes of the batched-ensemble run (slots vs one at a time); 0 skips it")
     ap.add_argument("--batched-slots", type=int, default=8)
+    ap.add_argument("--allocator", default="torch", choices=["torch", "hip"],
+                    help="device memory of the boxes: torch's caching allocator or the library's hipMalloc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -186,7 +188,7 @@ def main():
     t = time.perf_counter()
     pos, vel = zeldovich_ics(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
     log(f"initial conditions done in {time.perf_counter() - t:.1f} s")
-    box = CubeBox(spec, tiles_per_batch=args.tiles_per_batch)
+    box = CubeBox(spec, tiles_per_batch=args.tiles_per_batch, allocator=args.allocator)
     box.compress(pos, vel)
     log("compressed; warmup ...")
     box.step(args.warmup)
@@ -210,7 +212,7 @@ def main():
     # the same input with the 16-bit spectrum stores
     mixed = {}
     for prec in ("bf16", "fp16") if args.mixed_steps > 0 else ():
-        mb = CubeBox(spec, tiles_per_batch=args.tiles_per_batch, precision=prec)
+        mb = CubeBox(spec, tiles_per_batch=args.tiles_per_batch, precision=prec, allocator=args.allocator)
         mb.compress(pos, vel)
         mb.step(1)
         torch.cuda.synchronize()
@@ -285,6 +287,7 @@ def main():
             "n_particles": n,
             "precision": "fp32",
             "tiles_per_batch": args.tiles_per_batch or "auto",
+            "allocator": args.allocator,
         },
         "roofline": {
             "bound": "hbm",

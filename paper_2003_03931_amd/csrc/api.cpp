@@ -206,6 +206,7 @@ struct cube_ctx {
     int64_t step = 0;
     double last_step_ms = 0.0;
     int32_t max_count = 0;            // largest cell count of the current state
+    int32_t max_block8 = 0;           // largest count of a 2x2x2 block of coarse cells
 
     ~cube_ctx() {
         if (sc_host) hipHostFree(sc_host);
@@ -374,14 +375,15 @@ void coarse_potential(cube_ctx* c) {
 
 // Storage format of the tile half spectra for the current state: the mixed
 // FP16 mode falls back to FP32 while a fine-cell density could exceed the
-// FP16 range (a cell gathers at most 8 coarse cells of max_count particles,
-// density f^3 per particle; the plane transform's gain is divided out).
+// FP16 range (a fine cell gathers the particles of at most one 2x2x2 block
+// of coarse cells, density f^3 per particle; the plane transform's gain is
+// divided out).
 int spec_format(const cube_ctx* c) {
     switch (c->desc.precision) {
         case CUBE_MIXED_BF16: return 1;
         case CUBE_MIXED_FP16: {
             const double f3 = (double)c->g.f * c->g.f * c->g.f;
-            return 8.0 * f3 * (double)c->max_count + 1.0 < 32768.0 ? 2 : 0;
+            return f3 * (double)c->max_block8 + 1.0 < 32768.0 ? 2 : 0;
         }
         default: return 0;
     }
@@ -393,7 +395,7 @@ void fine_potential(cube_ctx* c, int t0, int nt) {
     Profiler& P = c->prof;
     const int fmt = spec_format(c);
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
-    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_count),
+    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                         c->stream);
     if (!P.on) {
         fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
@@ -458,8 +460,9 @@ cube_status run_step(cube_ctx* c) {
         }
     }
     hipEvent_t es = P.on ? P.mark(s) : nullptr;
-    launch_fill_i32(&c->sc->max_count, 0, 1, s);
+    launch_fill_i32(&c->sc->max_count, 0, 2, s);          // max_count and max_block8
     exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &c->sc->max_count);
+    launch_max_block8(g, c->counts_new, &c->sc->max_block8, s);
     if (P.on) P.add(ST_SCAN, es, P.mark(s), 8.0 * (double)g.ncells);
     CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     cube_status st = sync(c);
@@ -490,6 +493,7 @@ cube_status run_step(cube_ctx* c) {
     }
     launch_step_epilogue(c->sc, s);
     c->max_count = c->sc_host->max_count;
+    c->max_block8 = c->sc_host->max_block8;
     std::swap(c->counts, c->counts_new);
     std::swap(c->offsets, c->offsets_new);
     c->step += 1;
@@ -669,11 +673,13 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     *c->sc_host = init;
     hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s);
     exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
+    launch_max_block8(g, c->counts, &c->sc->max_block8, s);
     launch_scatter_compressed(g, idx, qp, dvel, s0, c->A, c->counts, c->sc, n, s);
     hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s);
     st = sync(c);
     if (st != CUBE_OK) return st;
     c->max_count = c->sc_host->max_count;
+    c->max_block8 = c->sc_host->max_block8;
     c->has_state = true;
     c->step = 0;
     return CUBE_OK;
@@ -789,6 +795,7 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
     *c->sc_host = init;
     CUBE_HIP(hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s));
     exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
+    launch_max_block8(g, c->counts, &c->sc->max_block8, s);
     CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     int32_t total = -1;
     CUBE_HIP(hipMemcpyAsync(&total, c->offsets + g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -803,6 +810,7 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
         return fail(CUBE_INVALID, "counts do not sum to n_particles");
     }
     c->max_count = c->sc_host->max_count;
+    c->max_block8 = c->sc_host->max_block8;
     c->has_state = true;
     c->step = v->step;
     return CUBE_OK;
@@ -916,7 +924,7 @@ cube_status cube_debug_mesh(cube_ctx* c, int32_t what, int32_t tile, float* out)
         if (tile < 0 || tile >= g.ntiles) return fail(CUBE_INVALID, "tile out of range");
         const int64_t fcube = (int64_t)g.F * g.F * g.F;
         if (what == 2)
-            launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_real, fine_deposit_needs_wide(g, c->max_count),
+            launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                                 s);
         else fine_potential(c, tile, 1);
         CUBE_HIP(hipMemcpyAsync(out, c->fine_real, fcube * sizeof(float), hipMemcpyDeviceToDevice, s));

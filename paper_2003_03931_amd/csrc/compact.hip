@@ -7,9 +7,11 @@
 // cells along x inside one tile, so every segment's output is one contiguous
 // run of the new arrays.  Its particles can only come from the source window
 // (BX+2) x (BY+2) x (BZ+2).  Per source cell, one thread walks the cell's
-// particles in order twice: first to histogram their 27 move codes, then --
-// once each destination has ordered its 27 source cells by canonical index and
-// formed prefix counts -- to give every incoming particle its slot
+// particles in order twice: first to count, per destination cell of the brick
+// and move code, the arrivals (each such pair has exactly one source cell, so
+// its counter has one writer), then -- once each destination has ordered its
+// 27 source cells by canonical index and formed prefix counts -- to give
+// every incoming particle its slot
 //   new_offset[dest] + (arrivals from earlier source cells)
 //                    + (earlier same-code particles of its own source cell).
 // Slots are mapped in LDS and the planes copied run by run (coalesced); a
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                                                             const int32_t* __restrict__ off_new,
                                                             const uint8_t* __restrict__ dir, Planes src, Planes dst) {
     __shared__ int s_start[kMaxSrc], s_canon[kMaxSrc], s_cnt[kMaxSrc];
-    __shared__ uint16_t s_hist[kMaxSrc][27];
+    __shared__ uint16_t s_arr[kMaxDst][27];    // arrivals per (destination, code), then running ranks
     __shared__ int s_pre[kMaxDst][27];
     __shared__ int s_doff[kMaxDst + 1];
     __shared__ int s_run[kMaxDst + 1];      // per destination row segment: slot base
@@ -66,9 +68,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         const int st = off_old[c];
         s_start[h] = st;
         s_cnt[h] = off_old[c + 1] - st;
-#pragma unroll
-        for (int d = 0; d < 27; ++d) s_hist[h][d] = 0;
     }
+    for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
     for (int e = threadIdx.x; e <= ndst; e += kCThreads) {
         if (e < ndst) {
             const int ex = e % BX, ey = (e / BX) % BY, ez = e / (BX * BY);
@@ -108,8 +109,15 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (threadIdx.x == 0) s_pref[nsrc] = tot;
     }
     __syncthreads();
+    // destination cell (in the brick) of a code-d particle of source cell h, or -1
+    auto dest_of = [&](int h, int d) -> int {
+        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+        const int ex = hx + (d % 3 - 1) - 1, ey = hy + ((d / 3) % 3 - 1) - 1, ez = hz + (d / 9 - 1) - 1;
+        if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) return -1;
+        return ex + BX * (ey + BY * ez);
+    };
     // walk 1: each source cell's thread loads its move codes (8 in flight),
-    // stages them in LDS when the window fits, and histograms them
+    // stages them in LDS when the window fits, and counts its arrivals
     const int nwin = s_pref[nsrc];
     const bool staged = nwin <= kDirCap;
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
@@ -123,7 +131,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                 if (q0 + u >= n) break;
                 const int d = cq[u];
                 if (staged) s_dir[base + q0 + u] = (uint8_t)d;
-                if (d < 27) s_hist[h][d] = (uint16_t)(s_hist[h][d] + 1);
+                const int dc = d < 27 ? dest_of(h, d) : -1;
+                if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
             }
         }
     }
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
             int acc = 0;
             for (int d = 26; d >= 0; --d) {
                 s_pre[dcell][d] = acc;
-                acc += s_hist[srcs[d]][d];
+                acc += s_arr[dcell][d];
             }
         } else {
             // sources span tiles or wrap: order by canonical index in registers
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
 #pragma unroll
             for (int d = 0; d < 27; ++d) {
                 key[d] = s_canon[srcs[d]];
-                cnt[d] = s_hist[srcs[d]][d];
+                cnt[d] = s_arr[dcell][d];
             }
 #pragma unroll
             for (int d = 0; d < 27; ++d) {
@@ -170,10 +179,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         }
     }
     __syncthreads();
-    // reuse the histogram as running per-code counters
-    for (int h = threadIdx.x; h < nsrc; h += kCThreads)
-#pragma unroll
-        for (int d = 0; d < 27; ++d) s_hist[h][d] = 0;
+    // reuse the arrival counts as running ranks
+    for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
     __syncthreads();
 
     const bool use_slots = s_run[nrow] <= kSlots;
@@ -185,11 +192,11 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
             const int p = st + q;
             const int d = code(h, q);
             if (d >= 27) continue;
-            const int rank = s_hist[h][d];
-            s_hist[h][d] = (uint16_t)(rank + 1);
             const int ex = hx + (d % 3 - 1) - 1, ey = hy + ((d / 3) % 3 - 1) - 1, ez = hz + (d / 9 - 1) - 1;
             if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) continue;
             const int dcell = ex + BX * (ey + BY * ez);
+            const int rank = s_arr[dcell][d];
+            s_arr[dcell][d] = (uint16_t)(rank + 1);
             const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
             if (use_slots) {
                 const int row = ey + BY * ez;

@@ -12,9 +12,10 @@
 // and D = 512 / (target cells per coarse cell), so every CIC weight is an
 // integer multiple of 1/D per axis and of 1/D^3 in 3-D.  The FP32 output is
 // round(acc / D^3 / cell_volume - 1), the single rounding of the exact value.
-// A target cell gathers particles of at most 8 coarse cells, each weight at
-// most D^3, so 32-bit accumulators are exact whenever 8 D^3 max_count < 2^32
-// (the caller checks the state's largest cell count); otherwise 64-bit.
+// A target cell gathers particles of at most one 2 x 2 x 2 block of coarse
+// cells, each weight at most D^3, so 32-bit accumulators are exact whenever
+// D^3 times the largest such block count is below 2^32 (the caller checks the
+// state's block counts); otherwise 64-bit.
 #include "common.h"
 
 namespace cube {
@@ -24,15 +25,19 @@ namespace {
 enum DepositMode { DEP_COARSE = 0, DEP_FINE_TILED = 1, DEP_FINE_PERIODIC = 2, DEP_DIAG = 3 };
 
 constexpr int kDepThreads = 256;
-constexpr int kMaxSrc = 1000;   // (BW / cpc + 2)^3 for the largest source window
 
-template <int BW, int MODE, class ACC>
+// MAXSRC bounds the source window, (BW / cpc + 2)^3 coarse cells; MAPCAP is
+// the number of window particles whose source cell is looked up from a
+// per-particle map (larger windows fall back to a binary search).
+template <int BW, int MODE, class ACC, int MAXSRC, int MAPCAP>
 __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* __restrict__ offsets, Planes p,
                                                           float* __restrict__ out, int M, int cpc, int log2D,
                                                           double scale, int tile0) {
     __shared__ ACC acc[BW * BW * BW];
-    __shared__ int s_start[kMaxSrc];
-    __shared__ int s_pref[kMaxSrc + 1];
+    __shared__ int s_start[MAXSRC];
+    __shared__ int s_pref[MAXSRC + 1];
+    __shared__ int s_rel[MAXSRC];                // window coordinates + 1, 8 bits each
+    __shared__ uint16_t s_map[MAPCAP];
     __shared__ int s_scan[kDepThreads / kWave + 1];
 
     const int nbx = (M + BW - 1) / BW;
@@ -59,8 +64,8 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
 
     for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) acc[i] = 0;
 
-    // per-thread run of up to 4 source cells: counts, then a block scan
-    constexpr int kPer = (kMaxSrc + kDepThreads - 1) / kDepThreads;
+    // per-thread run of up to kPer source cells: counts, then a block scan
+    constexpr int kPer = (MAXSRC + kDepThreads - 1) / kDepThreads;
     int my_cnt[kPer];
     int run = 0;
 #pragma unroll
@@ -69,6 +74,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         int cnt = 0;
         if (s < nsrc) {
             const int rx = s % nsa[0], ry = (s / nsa[0]) % nsa[1], rz = s / (nsa[0] * nsa[1]);
+            s_rel[s] = rx | (ry << 8) | (rz << 16);
             int fc[3] = {S0[0] + rx, S0[1] + ry, S0[2] + rz};
             bool ok = true;
             if (MODE == DEP_FINE_TILED) {
@@ -92,10 +98,15 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
     }
     int total;
     int base = block_exclusive_scan(run, s_scan, &total);
+    const bool mapped = total <= MAPCAP;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int s = threadIdx.x * kPer + q;
-        if (s < nsrc) s_pref[s] = base;
+        if (s < nsrc) {
+            s_pref[s] = base;
+            if (mapped)
+                for (int j = 0; j < my_cnt[q]; ++j) s_map[base + j] = (uint16_t)s;
+        }
         base += my_cnt[q];
     }
     if (threadIdx.x == 0) s_pref[nsrc] = total;
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
             const int e = base + u * kDepThreads + threadIdx.x;
             src_of[u] = -1;
             if (e < total) {
-                const int s = find_cell(s_pref, nsrc, e);
+                const int s = mapped ? (int)s_map[e] : find_cell(s_pref, nsrc, e);
                 const int pidx = s_start[s] + (e - s_pref[s]);
                 src_of[u] = s;
 #pragma unroll
@@ -122,7 +133,8 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         for (int u = 0; u < U; ++u) {
             const int s = src_of[u];
             if (s < 0) continue;
-            const int rel[3] = {s % nsa[0] - 1, (s / nsa[0]) % nsa[1] - 1, s / (nsa[0] * nsa[1]) - 1};
+            const int rl = s_rel[s];
+            const int rel[3] = {(rl & 255) - 1, ((rl >> 8) & 255) - 1, (rl >> 16) - 1};
             int i0[3];
             unsigned w1[3];
 #pragma unroll
@@ -170,6 +182,37 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
     }
 }
 
+// largest particle count of any 2 x 2 x 2 block of coarse cells (periodic).
+// Cells are visited in storage order (the +x, +y, +z neighbours are then
+// mostly 1, Tc and Tc^2 entries ahead); one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_max_block8(Geom g, const int32_t* __restrict__ counts,
+                                                      int32_t* __restrict__ out) {
+    __shared__ int red[256 / kWave];
+    const int64_t tc3 = (int64_t)g.Tc * g.Tc * g.Tc;
+    int v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.ncells;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tile = i / tc3;
+        const int local = (int)(i - tile * tc3);
+        const int tx = (int)(tile % g.nt), ty = (int)((tile / g.nt) % g.nt), tz = (int)(tile / ((int64_t)g.nt * g.nt));
+        const int cx = tx * g.Tc + local % g.Tc, cy = ty * g.Tc + (local / g.Tc) % g.Tc;
+        const int cz = tz * g.Tc + local / (g.Tc * g.Tc);
+        const int x1 = cx + 1 == g.Nc ? 0 : cx + 1, y1 = cy + 1 == g.Nc ? 0 : cy + 1;
+        const int z1 = cz + 1 == g.Nc ? 0 : cz + 1;
+        const int sum = counts[i] + counts[canon(g, x1, cy, cz)] + counts[canon(g, cx, y1, cz)] +
+                        counts[canon(g, x1, y1, cz)] + counts[canon(g, cx, cy, z1)] + counts[canon(g, x1, cy, z1)] +
+                        counts[canon(g, cx, y1, z1)] + counts[canon(g, x1, y1, z1)];
+        v = max(v, sum);
+    }
+    v = wave_max(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / kWave; ++w) v = max(v, red[w]);
+        atomicMax(out, v);
+    }
+}
+
 int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
@@ -184,9 +227,8 @@ void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, floa
     const int nb = (g.Nc + BW - 1) / BW;
     // acc in units of 2^-27 particle; density = mass / H^3 with H = r / f
     const double scale = std::ldexp(1.0, -27) * ((double)g.f * g.f * g.f) / ((double)g.r * g.r * g.r);
-    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE, unsigned long long>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s,
-                       g, offsets, p,
-                       reinterpret_cast<float*>(mesh), g.Nc, 1, 9, scale, 0);
+    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE, unsigned long long, 1000, 10240>), dim3(nb * nb * nb),
+                       dim3(kDepThreads), 0, s, g, offsets, p, reinterpret_cast<float*>(mesh), g.Nc, 1, 9, scale, 0);
 }
 
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
@@ -197,21 +239,35 @@ void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int ti
     // acc in units of D^-3 fine-cell masses; density = mass / h^3 = mass * f^3
     const double scale = std::ldexp(1.0, -3 * log2D) * ((double)g.f * g.f * g.f);
     const dim3 grid(nb * nb * nb, ntiles), block(kDepThreads);
-#define CUBE_DEP(MODE, T) \
-    hipLaunchKernelGGL((k_deposit<BW, MODE, T>), grid, block, 0, s, g, offsets, p, mesh, g.F, g.r, log2D, scale, tile0)
+    // source window (16 / r + 2)^3: 6^3 for r >= 4, 10^3 for r = 2
+#define CUBE_DEP(MODE, T, SRC) \
+    hipLaunchKernelGGL((k_deposit<BW, MODE, T, SRC, 2048>), grid, block, 0, s, g, offsets, p, mesh, g.F, g.r, log2D, \
+                       scale, tile0)
+#define CUBE_DEP_SRC(MODE, T) \
+    do {                                          \
+        if (g.r >= 4) CUBE_DEP(MODE, T, 216);     \
+        else CUBE_DEP(MODE, T, 1000);             \
+    } while (0)
     if (g.periodic) {
-        if (wide) CUBE_DEP(DEP_FINE_PERIODIC, unsigned long long);
-        else CUBE_DEP(DEP_FINE_PERIODIC, unsigned int);
+        if (wide) CUBE_DEP_SRC(DEP_FINE_PERIODIC, unsigned long long);
+        else CUBE_DEP_SRC(DEP_FINE_PERIODIC, unsigned int);
     } else {
-        if (wide) CUBE_DEP(DEP_FINE_TILED, unsigned long long);
-        else CUBE_DEP(DEP_FINE_TILED, unsigned int);
+        if (wide) CUBE_DEP_SRC(DEP_FINE_TILED, unsigned long long);
+        else CUBE_DEP_SRC(DEP_FINE_TILED, unsigned int);
     }
+#undef CUBE_DEP_SRC
 #undef CUBE_DEP
 }
 
-bool fine_deposit_needs_wide(const Geom& g, int max_count) {
-    // 8 coarse cells x D^3 per particle must stay below 2^32
-    return (double)max_count * 8.0 * std::ldexp(1.0, 3 * g.log2D) >= 4294967296.0;
+bool fine_deposit_needs_wide(const Geom& g, int max_block8) {
+    // a fine cell gathers the particles of at most one 2 x 2 x 2 block of
+    // coarse cells, each weighing at most D^3 units: stay below 2^32
+    return (double)max_block8 * std::ldexp(1.0, 3 * g.log2D) >= 4294967296.0;
+}
+
+void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s) {
+    const int64_t want = (g.ncells + 255) / 256;
+    hipLaunchKernelGGL(k_max_block8, dim3((unsigned)std::min<int64_t>(want, 4096)), dim3(256), 0, s, g, counts, out);
 }
 
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, hipStream_t s) {
@@ -220,9 +276,9 @@ void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2
     const int nb = (g.ns + BW - 1) / BW;
     const int log2D = ilog2(512 / H);
     const double scale = std::ldexp(1.0, -3 * log2D);
-    hipLaunchKernelGGL((k_deposit<BW, DEP_DIAG, unsigned long long>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s,
-                       g, offsets, p,
-                       reinterpret_cast<float*>(mesh), g.ns, H, log2D, scale, 0);
+    hipLaunchKernelGGL((k_deposit<BW, DEP_DIAG, unsigned long long, 1000, 10240>), dim3(nb * nb * nb),
+                       dim3(kDepThreads), 0, s, g, offsets, p, reinterpret_cast<float*>(mesh), g.ns, H, log2D,
+                       scale, 0);
 }
 
 }  // namespace cube

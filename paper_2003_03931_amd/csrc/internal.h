@@ -64,6 +64,7 @@ struct StepScalars {
     int64_t saturations; // clamped velocity components (cumulative)
     int32_t overflow;    // a 16-bit spectrum value was out of range (cleared by the prologue)
     int32_t max_count;   // largest cell count of the newest counts (set by the scan)
+    int32_t max_block8;  // largest count of a 2x2x2 block of coarse cells in the newest counts
     // per-block maxima land in 64 slots (spreads atomic contention); the
     // epilogue folds them into max_u / max_carry
     int32_t umax_slot[64];
@@ -108,7 +109,9 @@ void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, floa
 // wide selects 64-bit accumulators (needed when fine_deposit_needs_wide)
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
                          float* mesh, bool wide, hipStream_t s);
-bool fine_deposit_needs_wide(const Geom& g, int max_count);
+bool fine_deposit_needs_wide(const Geom& g, int max_block8);
+// atomicMax(*out, largest count of a periodic 2 x 2 x 2 block of coarse cells)
+void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s);
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
                          hipStream_t s);
 
