@@ -389,23 +389,27 @@ int spec_format(const cube_ctx* c) {
     }
 }
 
-// fine potentials of tiles [t0, t0 + nt) into ctx->fine_real
-void fine_potential(cube_ctx* c, int t0, int nt) {
+// fine potentials of tiles [t0, t0 + nt) into ctx->fine_real: over the
+// whole box when `full`, else over the tile plus the 2 cells the gather's
+// interpolation and differences reach (all of the box for a periodic tile)
+void fine_potential(cube_ctx* c, int t0, int nt, bool full = false) {
     const Geom& g = c->g;
     Profiler& P = c->prof;
     const int fmt = spec_format(c);
+    const bool whole = full || g.periodic;
+    const int lo = whole ? 0 : g.b - 2, hi = whole ? g.F : g.b + g.T + 2;
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                         c->stream);
     if (!P.on) {
         fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
-                           c->stream);
+                           lo, hi, c->stream);
         return;
     }
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) ev[i] = P.get();
     fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
-                       c->stream, ev);
+                       lo, hi, c->stream, ev);
     const double f3 = (double)g.F * g.F * g.F, fc3 = (double)g.Fc * g.Fc * g.Fc;
     // bytes per stored half-spectrum value: 8 (FP32) or 4 (16-bit pairs)
     const double h3 = (double)g.F * g.F * (g.F / 2 + 1) * (fmt == 0 ? 1.0 : 0.5);
@@ -414,9 +418,12 @@ void fine_potential(cube_ctx* c, int t0, int nt) {
     // deposit: FP32 mesh write + offsets read + 3 position bytes per source
     P.add(ST_FINE_DEP, e0, ev[0], nt * (4.0 * f3 + 4.0 * fc3 + 3.0 * src));
     // xy planes: real mesh in, half spectrum out (and back); z: half spectrum in and out
+    // z pass: every pencil in, only z in the window out; C2R: the window's
+    // planes in, the window out
+    const double wf = (double)(hi - lo) / g.F, w3 = (double)(hi - lo) * (hi - lo) * (hi - lo);
     P.add(ST_FFT_R2C, ev[0], ev[1], nt * (4.0 * f3 + 8.0 * h3));
-    P.add(ST_FFT_ZG, ev[1], ev[2], nt * 16.0 * h3);
-    P.add(ST_FFT_C2R, ev[2], ev[3], nt * (8.0 * h3 + 4.0 * f3));
+    P.add(ST_FFT_ZG, ev[1], ev[2], nt * 8.0 * h3 * (1.0 + wf));
+    P.add(ST_FFT_C2R, ev[2], ev[3], nt * (8.0 * h3 * wf + 4.0 * w3));
 }
 
 GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
@@ -926,7 +933,7 @@ cube_status cube_debug_mesh(cube_ctx* c, int32_t what, int32_t tile, float* out)
         if (what == 2)
             launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                                 s);
-        else fine_potential(c, tile, 1);
+        else fine_potential(c, tile, 1, true);
         CUBE_HIP(hipMemcpyAsync(out, c->fine_real, fcube * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
         return fail(CUBE_INVALID, "unknown mesh");

@@ -30,9 +30,11 @@ namespace cube {
 namespace {
 
 constexpr int kCThreads = 256;
+static_assert(kCThreads == 4 * kWave, "the prefix ranks split the 27 codes over four waves");
 constexpr int kMaxBX = 16;
 constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
 constexpr int kMaxDst = kMaxBX * 2 * 2;
+static_assert(kMaxDst <= kWave, "one lane per destination cell");
 constexpr int kSlots = 1024;
 constexpr int kDirCap = 4096;                      // staged move codes of the source window
 
@@ -109,9 +111,9 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (threadIdx.x == 0) s_pref[nsrc] = tot;
     }
     __syncthreads();
-    // destination cell (in the brick) of a code-d particle of source cell h, or -1
-    auto dest_of = [&](int h, int d) -> int {
-        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+    // destination cell (in the brick) of a code-d particle of the source cell
+    // at window coordinates (hx, hy, hz), or -1
+    auto dest_of = [&](int hx, int hy, int hz, int d) -> int {
         const int ex = hx + (d % 3 - 1) - 1, ey = hy + ((d / 3) % 3 - 1) - 1, ez = hz + (d / 9 - 1) - 1;
         if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) return -1;
         return ex + BX * (ey + BY * ez);
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     const bool staged = nwin <= kDirCap;
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
         const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
+        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
         for (int q0 = 0; q0 < n; q0 += 8) {
             int cq[8];
 #pragma unroll
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                 if (q0 + u >= n) break;
                 const int d = cq[u];
                 if (staged) s_dir[base + q0 + u] = (uint8_t)d;
-                const int dc = d < 27 ? dest_of(h, d) : -1;
+                const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
                 if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
             }
         }
@@ -139,42 +142,50 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     __syncthreads();
     auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
 
-    // arrivals from earlier source cells, per destination and code
-    for (int dcell = threadIdx.x; dcell < ndst; dcell += kCThreads) {
-        const int ex = dcell % BX + 1, ey = (dcell / BX) % BY + 1, ez = dcell / (BX * BY) + 1;
-        int srcs[27];
-        bool lexi = true;        // are the 27 sources ordered like their codes (descending)?
-        int prev = 0x7fffffff;
-        for (int d = 0; d < 27; ++d) {
-            const int hs = (ex - (d % 3 - 1)) + SX * ((ey - ((d / 3) % 3 - 1)) + SY * (ez - (d / 9 - 1)));
-            srcs[d] = hs;
-        }
-        for (int d = 0; d < 27; ++d) {
-            const int c = s_canon[srcs[d]];
-            lexi = lexi && (c < prev);
-            prev = c;
-        }
-        if (lexi) {
-            // canonical order = descending code: suffix sums
-            int acc = 0;
-            for (int d = 26; d >= 0; --d) {
-                s_pre[dcell][d] = acc;
-                acc += s_arr[dcell][d];
-            }
-        } else {
-            // sources span tiles or wrap: order by canonical index in registers
+    // Arrivals from earlier source cells, per destination and code.  Lane =
+    // destination; its 27 source cells are ranked by canonical index.  When
+    // they lie in one tile the order is the reversed code order (suffix sums,
+    // wave 0); otherwise each of the four waves ranks a quarter of the codes
+    // (the wave index is uniform, so the unrolled ranges stay in registers).
+    {
+        const int dcell = threadIdx.x & (kWave - 1), sub = threadIdx.x / kWave;
+        if (dcell < ndst) {
+            const int ex = dcell % BX + 1, ey = (dcell / BX) % BY + 1, ez = dcell / (BX * BY) + 1;
             int key[27], cnt[27];
+            bool lexi = true;
 #pragma unroll
             for (int d = 0; d < 27; ++d) {
-                key[d] = s_canon[srcs[d]];
+                const int hs = (ex - (d % 3 - 1)) + SX * ((ey - ((d / 3) % 3 - 1)) + SY * (ez - (d / 9 - 1)));
+                key[d] = s_canon[hs];
                 cnt[d] = s_arr[dcell][d];
+                if (d > 0) lexi = lexi && (key[d] < key[d - 1]);
             }
+            if (lexi) {
+                if (sub == 0) {
+                    int acc = 0;
 #pragma unroll
-            for (int d = 0; d < 27; ++d) {
-                int acc = 0;
-#pragma unroll
-                for (int d2 = 0; d2 < 27; ++d2) acc += (key[d2] < key[d]) ? cnt[d2] : 0;
-                s_pre[dcell][d] = acc;
+                    for (int d = 26; d >= 0; --d) {
+                        s_pre[dcell][d] = acc;
+                        acc += cnt[d];
+                    }
+                }
+            } else {
+#define CUBE_PRE_RANGE(D0, D1)                                                                         \
+    _Pragma("unroll") for (int d = D0; d < D1; ++d) {                                                  \
+        int acc = 0;                                                                                   \
+        _Pragma("unroll") for (int d2 = 0; d2 < 27; ++d2) acc += (key[d2] < key[d]) ? cnt[d2] : 0;     \
+        s_pre[dcell][d] = acc;                                                                         \
+    }
+                if (sub == 0) {
+                    CUBE_PRE_RANGE(0, 7)
+                } else if (sub == 1) {
+                    CUBE_PRE_RANGE(7, 14)
+                } else if (sub == 2) {
+                    CUBE_PRE_RANGE(14, 21)
+                } else {
+                    CUBE_PRE_RANGE(21, 27)
+                }
+#undef CUBE_PRE_RANGE
             }
         }
     }

@@ -471,12 +471,18 @@ template <int N, int FMT>
 __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                              float* __restrict__ real_tiles,
                                                              const float2* __restrict__ tw_g, int nplanes,
-                                                             float sc_in) {
+                                                             float sc_in, int lo, int hi) {
     using S = SpecStore<FMT>;
     constexpr int NH = N / 2 + 1;
     constexpr int HALF = N / 2;
     constexpr int RS = N + 2;
     constexpr int TOT = N * NH;
+    // only the window [lo, hi)^3 of each tile is produced: planes lo..hi-1,
+    // and in each plane the rows and columns lo..hi-1
+    const int W = hi - lo;
+    const int jlo = lo / 2, jhi = (hi + 1) / 2;
+    const int st_y = (int)threadIdx.x / W, st_x = (int)threadIdx.x % W;           // once per thread
+    const int step_y = kPlaneThreads / W, step_x = kPlaneThreads % W;
     constexpr int PER = (TOT + kPlaneThreads - 1) / kPlaneThreads;
     constexpr int KIT = (N + kWave - 1) / kWave;
     constexpr int NW = kPlaneThreads / kWave;
@@ -486,7 +492,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     typename S::T pv[PER];
     auto prefetch = [&](int pl) {
-        const typename S::T* src = spec_tiles + (int64_t)(pl / N) * N * N * NH + (int64_t)(pl % N) * N * NH;
+        const typename S::T* src = spec_tiles + (int64_t)(pl / W) * N * N * NH + (int64_t)(lo + pl % W) * N * NH;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
         asm volatile("" : "+v"(tid));
         Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, true>(lds, tw, tid);
         // complex row Z(k) = A(k) + i B(k) over k = 0..N-1 (Hermitian extension of A, B)
-        for (int j = wv; j < HALF; j += NW) {
+        for (int j = jlo + wv; j < jhi; j += NW) {
             float2* row = lds + j * RS;
             float2 vz[KIT];
 #pragma unroll
@@ -532,12 +538,18 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
         }
         __syncthreads();
         Plan<N>::template run<Lay<HALF, 1, RS, false, kPlaneThreads>, true>(lds, tw, tid);
-        float* dst = real_tiles + (int64_t)(plane / N) * N * N * N + (int64_t)(plane % N) * N * N;
-        for (int e = threadIdx.x; e < HALF * N; e += kPlaneThreads) {
-            const int j = e / N, x = e % N;
-            const float2 v = lds[j * RS + x];
-            dst[(2 * j) * N + x] = v.x;
-            dst[(2 * j + 1) * N + x] = v.y;
+        float* dst = real_tiles + (int64_t)(plane / W) * N * N * N + (int64_t)(lo + plane % W) * N * N;
+        // element e = (y - lo) W + (x - lo), walked with increments instead of divisions
+        int y = lo + st_y, x = lo + st_x;
+        for (int e = threadIdx.x; e < W * W; e += kPlaneThreads) {
+            const float2 v = lds[(y >> 1) * RS + x];
+            dst[y * N + x] = (y & 1) ? v.y : v.x;
+            x += step_x;
+            y += step_y;
+            if (x >= hi) {
+                x -= W;
+                ++y;
+            }
         }
     }
 }
@@ -548,7 +560,8 @@ template <int N, int FMT>
 __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                             const float2* __restrict__ tw_g,
                                                             const float* __restrict__ green, float sc_in,
-                                                            float sc_out, int32_t* __restrict__ flag) {
+                                                            float sc_out, int32_t* __restrict__ flag, int lo,
+                                                            int hi) {
     using S = SpecStore<FMT>;
     using T = typename S::T;
     constexpr int NH = N / 2 + 1;
@@ -594,8 +607,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
     __syncthreads();
     Plan<N>::template run<L, true>(lds, tw);
     bool bad = false;
-    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
-        const int w = e % W, i = e / W;
+    for (int e = threadIdx.x; e < W * (hi - lo); e += kFftThreads) {       // only z in [lo, hi) is used
+        const int w = e % W, i = lo + e / W;
         g[(int64_t)i * PLANE + w] = S::put(lds[w * LDN + i], sc_out, bad);
     }
     if (FMT == SPEC_F16) raise_flag(bad, flag);
@@ -613,7 +626,7 @@ int device_cus() {
 
 template <int N, int FMT>
 void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* tw, const float* green,
-                      int32_t* flag, hipStream_t s, hipEvent_t* ev) {
+                      int32_t* flag, int lo, int hi, hipStream_t s, hipEvent_t* ev) {
     constexpr int NH = N / 2 + 1;
     using T = typename SpecStore<FMT>::T;
     T* spec_tiles = static_cast<T*>(spec);
@@ -637,22 +650,24 @@ void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* t
                        nplanes, rho_store, flag);
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw,
-                       green, rho_load, phi_store, flag);
+                       green, rho_load, phi_store, flag, lo, hi);
     if (ev) hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL((k_c2r_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, spec_tiles, real_tiles, tw,
-                       nplanes, phi_load);
+    const int out_planes = (hi - lo) * ntiles;
+    hipLaunchKernelGGL((k_c2r_plane<N, FMT>), dim3(std::min(out_planes, device_cus())), dim3(kPlaneThreads), 0, s,
+                       spec_tiles, real_tiles, tw, out_planes, phi_load, lo, hi);
     if (ev) hipEventRecord(ev[3], s);
 }
 
 template <int N>
 void launch_tiles(float* real_tiles, void* spec, int ntiles, const float2* tw, const float* green, int fmt,
-                  int32_t* flag, hipStream_t s, hipEvent_t* ev) {
-    if (fmt == SPEC_BF16) launch_tiles_fmt<N, SPEC_BF16>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
-    else if (fmt == SPEC_F16) launch_tiles_fmt<N, SPEC_F16>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
-    else launch_tiles_fmt<N, SPEC_F32>(real_tiles, spec, ntiles, tw, green, flag, s, ev);
+                  int32_t* flag, int lo, int hi, hipStream_t s, hipEvent_t* ev) {
+    if (fmt == SPEC_BF16) launch_tiles_fmt<N, SPEC_BF16>(real_tiles, spec, ntiles, tw, green, flag, lo, hi, s, ev);
+    else if (fmt == SPEC_F16) launch_tiles_fmt<N, SPEC_F16>(real_tiles, spec, ntiles, tw, green, flag, lo, hi, s, ev);
+    else launch_tiles_fmt<N, SPEC_F32>(real_tiles, spec, ntiles, tw, green, flag, lo, hi, s, ev);
 }
 
-using TilesFn = void (*)(float*, void*, int, const float2*, const float*, int, int32_t*, hipStream_t, hipEvent_t*);
+using TilesFn = void (*)(float*, void*, int, const float2*, const float*, int, int32_t*, int, int, hipStream_t,
+                         hipEvent_t*);
 
 TilesFn tiles_for(int n) {
     switch (n) {
@@ -719,9 +734,9 @@ bool fft_supported(int n) { return pass_for(n) != nullptr; }
 bool fft_tiles_supported(int n) { return tiles_for(n) != nullptr; }
 
 void fft_tiles_convolve(float* real_tiles, void* spec_tiles, int n, int ntiles, const float2* tw,
-                        const float* green_octant, int spec_format, int32_t* range_flag, hipStream_t s,
-                        hipEvent_t* ev) {
-    tiles_for(n)(real_tiles, spec_tiles, ntiles, tw, green_octant, spec_format, range_flag, s, ev);
+                        const float* green_octant, int spec_format, int32_t* range_flag, int out_lo, int out_hi,
+                        hipStream_t s, hipEvent_t* ev) {
+    tiles_for(n)(real_tiles, spec_tiles, ntiles, tw, green_octant, spec_format, range_flag, out_lo, out_hi, s, ev);
 }
 
 void fft_make_twiddles(int n, float2* dev_table, hipStream_t s) {

@@ -131,12 +131,14 @@ void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void
 // a real even octant table through half spectra (n^2 (n/2+1) complex per
 // tile, workspace) -> potentials in place.  spec_format: 0 FP32 complex,
 // 1 BF16 pairs, 2 scaled FP16 pairs (4 bytes per complex value); with FP16 an
-// out-of-range value sets *range_flag = 1.  ev (optional, 4 events) is
-// recorded before the first and after each of the three sweeps.
+// out-of-range value sets *range_flag = 1.  Only the window [out_lo, out_hi)^3
+// of each potential is written (the rest of the real mesh keeps the density).
+// ev (optional, 4 events) is recorded before the first and after each of the
+// three sweeps.
 bool fft_tiles_supported(int n);
 void fft_tiles_convolve(float* real_tiles, void* spec_tiles, int n, int ntiles, const float2* tw,
-                        const float* green_octant, int spec_format, int32_t* range_flag, hipStream_t s,
-                        hipEvent_t* ev = nullptr);
+                        const float* green_octant, int spec_format, int32_t* range_flag, int out_lo, int out_hi,
+                        hipStream_t s, hipEvent_t* ev = nullptr);
 
 // ---- green.hip ----------------------------------------------------------
 // FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).
