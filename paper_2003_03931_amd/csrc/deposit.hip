@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
 
     const int D = 1 << log2D;
     const int halfD = D >> 1;
-    constexpr int U = 4;                       // particles per thread with loads in flight
+    constexpr int U = 8;                       // particles per thread with loads in flight
     for (int base = 0; base < total; base += kDepThreads * U) {
         int mm[U][3], src_of[U];
 #pragma unroll

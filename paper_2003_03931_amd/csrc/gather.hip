@@ -118,38 +118,65 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const float* fmesh = A.fine_real + (int64_t)k * g.F * g.F * g.F;   // tile k of the batch
     const int F = g.F, ox = g.b + lf[0] - 2, oy = g.b + lf[1] - 2, oz = g.b + lf[2] - 2;
     const bool per = g.periodic != 0;
-    stage_to_lds<kGatherThreads, 16>(
-        kFineLds, fmesh, s_fine,
-        [=](int e) {
+    // Every load of the staging phase (fine potential with halo, coarse
+    // potential with halo, row offsets) is issued before the first wait: one
+    // memory latency per block instead of one per round.
+    const int CX = BXc + 4, CY = BYc + 4, CZ = BZc + 4;
+    const float* cmesh = reinterpret_cast<const float*>(A.coarse);
+    const int Nc = g.Nc, cx0 = gc[0] - 2, cy0 = gc[1] - 2, cz0 = gc[2] - 2;
+    const int ncoarse = CX * CY * CZ, nrowoff = nrows * (BXc + 1);
+    constexpr int UF = (kFineLds + kGatherThreads - 1) / kGatherThreads;
+    constexpr int UC = (kMaxCoarseLds + kGatherThreads - 1) / kGatherThreads;
+    constexpr int UR = (kMaxRows * (kMaxRowLen + 1) + kGatherThreads - 1) / kGatherThreads;
+    float fv[UF], cv[UC];
+    int rv[UR];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < kFineLds) {
             int fx = ox + e % kLX, fy = oy + (e / kLX) % kLY, fz = oz + e / (kLX * kLY);
             if (per) {
                 fx = fx < 0 ? fx + F : (fx >= F ? fx - F : fx);
                 fy = fy < 0 ? fy + F : (fy >= F ? fy - F : fy);
                 fz = fz < 0 ? fz + F : (fz >= F ? fz - F : fz);
             }
-            return ((int64_t)fz * F + fy) * F + fx;
-        },
-        [](int e) { return e; });
-    // coarse potential of the brick's coarse cells plus 2 (periodic)
-    const int CX = BXc + 4, CY = BYc + 4, CZ = BZc + 4;
-    const float* cmesh = reinterpret_cast<const float*>(A.coarse);
-    const int Nc = g.Nc, cx0 = gc[0] - 2, cy0 = gc[1] - 2, cz0 = gc[2] - 2;
-    stage_to_lds<kGatherThreads, 4>(
-        CX * CY * CZ, cmesh, s_coarse,
-        [=](int e) {
+            fv[u] = fmesh[((int64_t)fz * F + fy) * F + fx];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < ncoarse) {
             int cx = cx0 + e % CX, cy = cy0 + (e / CX) % CY, cz = cz0 + e / (CX * CY);
             cx = cx < 0 ? cx + Nc : (cx >= Nc ? cx - Nc : cx);
             cy = cy < 0 ? cy + Nc : (cy >= Nc ? cy - Nc : cy);
             cz = cz < 0 ? cz + Nc : (cz >= Nc ? cz - Nc : cz);
-            return 2 * (((int64_t)cz * Nc + cy) * Nc + cx);
-        },
-        [](int e) { return e; });
-    // particle ranges: rows of BXc contiguous cells
-    for (int e = threadIdx.x; e < nrows * (BXc + 1); e += kGatherThreads) {
-        const int row = e / (BXc + 1), j = e % (BXc + 1);
-        const int ry = row % BYc, rz = row / BYc;
-        const int64_t c0 = canon(g, gc[0], gc[1] + ry, gc[2] + rz);
-        s_rowoff[row][j] = A.offsets[c0 + j];
+            cv[u] = cmesh[2 * (((int64_t)cz * Nc + cy) * Nc + cx)];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < nrowoff) {
+            const int row = e / (BXc + 1), j = e % (BXc + 1);
+            const int ry = row % BYc, rz = row / BYc;
+            rv[u] = A.offsets[canon(g, gc[0], gc[1] + ry, gc[2] + rz) + j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < kFineLds) s_fine[e] = fv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < ncoarse) s_coarse[e] = cv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+        const int e = threadIdx.x + u * kGatherThreads;
+        if (e < nrowoff) s_rowoff[e / (BXc + 1)][e % (BXc + 1)] = rv[u];
     }
     const int HX = BXc + 2, HY = BYc + 2, HZ = BZc + 2;
     if (MODE == GATHER_STEP)
