@@ -122,9 +122,13 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     // stages them in LDS when the window fits, and counts its arrivals
     const int nwin = s_pref[nsrc];
     const bool staged = nwin <= kDirCap;
+    // Most particles keep their cell (code 13): those are counted in a
+    // register, so only the movers go through LDS read-modify-writes.
+    constexpr int kStay = 13;
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
         const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
         const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+        int stay = 0;
         for (int q0 = 0; q0 < n; q0 += 8) {
             int cq[8];
 #pragma unroll
@@ -134,10 +138,16 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                 if (q0 + u >= n) break;
                 const int d = cq[u];
                 if (staged) s_dir[base + q0 + u] = (uint8_t)d;
-                const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
-                if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
+                if (d == kStay) {
+                    ++stay;
+                } else {
+                    const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
+                    if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
+                }
             }
         }
+        const int dstay = dest_of(hx, hy, hz, kStay);
+        if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)stay;       // the only writer of this entry
     }
     __syncthreads();
     auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
@@ -196,31 +206,43 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
 
     const bool use_slots = s_run[nrow] <= kSlots;
     // walk 2: slot of every particle that lands in this brick
+    // (four particles per iteration so that their LDS reads overlap; stayers
+    // are ranked by a register counter, movers by the LDS counters)
     for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
         const int st = s_start[h], n = s_cnt[h];
         const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-        for (int q = 0; q < n; ++q) {
-            const int p = st + q;
-            const int d = code(h, q);
-            if (d >= 27) continue;
-            const int ex = hx + (d % 3 - 1) - 1, ey = hy + ((d / 3) % 3 - 1) - 1, ez = hz + (d / 9 - 1) - 1;
-            if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) continue;
-            const int dcell = ex + BX * (ey + BY * ez);
-            const int rank = s_arr[dcell][d];
-            s_arr[dcell][d] = (uint16_t)(rank + 1);
-            const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
-            if (use_slots) {
-                const int row = ey + BY * ez;
-                const int first = s_doff[BX * row];
-                const int slot = s_run[row] + (o - first);
-                if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
-            } else if (o >= 0 && o < g.n) {
+        const int dstay = dest_of(hx, hy, hz, kStay);
+        int stay = 0;
+        for (int q0 = 0; q0 < n; q0 += 4) {
+            int dq[4];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dst.m[a][o] = src.m[a][p];
-                    dst.u[a][o] = src.u[a][p];
+            for (int u = 0; u < 4; ++u) dq[u] = (q0 + u < n) ? code(h, q0 + u) : 255;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int d = dq[u];
+                const int dcell = d == kStay ? dstay : (d < 27 ? dest_of(hx, hy, hz, d) : -1);
+                if (dcell < 0) continue;
+                int rank;
+                if (d == kStay) {
+                    rank = stay++;
+                } else {
+                    rank = s_arr[dcell][d];
+                    s_arr[dcell][d] = (uint16_t)(rank + 1);
                 }
-                if (dst.ids) dst.ids[o] = src.ids[p];
+                const int p = st + q0 + u;
+                const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
+                if (use_slots) {
+                    const int row = dcell / BX;
+                    const int slot = s_run[row] + (o - s_doff[BX * row]);
+                    if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
+                } else if (o >= 0 && o < g.n) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        dst.m[a][o] = src.m[a][p];
+                        dst.u[a][o] = src.u[a][p];
+                    }
+                    if (dst.ids) dst.ids[o] = src.ids[p];
+                }
             }
         }
     }
