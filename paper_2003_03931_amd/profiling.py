@@ -87,11 +87,15 @@ def traffic_summary(fetch_dir, write_dir, copy_bytes, out_path, command):
     frows = _counter_rows(fetch_dir, "FETCH_SIZE")
     wrows = _counter_rows(write_dir, "WRITE_SIZE")
     # the calibration dispatch: a copy-like kernel whose write count is the
-    # known size; the same dispatch id in the fetch run gives its read count
-    cands = [(abs(v * 1024.0 - copy_bytes), did) for did, k, v in wrows if any(c in k for c in COPY_KERNELS)]
+    # known size and which also reads (the buffer's fill writes the same
+    # size but reads nothing); the same dispatch id in the fetch run gives
+    # its read count
+    fetch_of = {d: v for d, _, v in frows}
+    cands = [(fetch_of.get(did, 0.0), did) for did, k, v in wrows
+             if any(c in k for c in COPY_KERNELS) and abs(v * 1024.0 - copy_bytes) < 0.05 * copy_bytes]
     if not cands:
         raise SystemExit("no copy kernel in the WRITE_SIZE run: run the bench with --calibrate-copy")
-    _, did = min(cands)
+    _, did = max(cands)
     wv = [v for d, _, v in wrows if d == did][0]
     fv = [v for d, _, v in frows if d == did][0]
     f_scale = copy_bytes / (fv * 1024.0)
