@@ -378,7 +378,7 @@ __device__ __forceinline__ void raise_flag(bool bad, int32_t* flag) {
 // whole z-plane in LDS: rows 2j and 2j+1 are transformed together as one
 // complex row and separated with the Hermitian symmetry, then the N/2+1
 // columns are transformed along y.  The inverse runs the same steps backwards.
-constexpr int kPlaneThreads = 512;
+constexpr int kPlaneThreads = 1024;
 
 // Persistent: each workgroup walks planes blockIdx.x, +gridDim.x, ...; the
 // next plane's global loads are issued into registers before the current
@@ -571,15 +571,17 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
     constexpr int U = 10;
     __shared__ float2 lds[W * LDN];
     __shared__ float2 tw[N];
-    __shared__ float gl[W * NH];                   // G(kz folded, this block's (ky, kx))
+    __shared__ float gl[W * NH];                   // G of this block's (ky, kx) pencils, by folded kz
     const int c0 = blockIdx.x * W;                 // flattened (ky, kx) of the first pencil
     T* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
     for (int i = threadIdx.x; i < N; i += kFftThreads) tw[i] = tw_g[i];
+    // table is pencil-major ([ky][kx][kz], kz fastest): consecutive lanes read
+    // consecutive kz of one pencil and keep that order in LDS (gl[w][kz])
     for (int e = threadIdx.x; e < W * NH; e += kFftThreads) {
-        const int w = e % W, fz = e / W;
+        const int fz = e % NH, w = e / NH;
         const int c = c0 + w;
         const int ky = c / NH, kx = c - ky * NH;
-        gl[e] = green[((int64_t)fz * NH + fold(ky, N)) * NH + kx];
+        gl[e] = green[((int64_t)fold(ky, N) * NH + kx) * NH + fz];
     }
     // element e: pencil w = e % W, kz = e / W (16 consecutive words per kz)
     for (int base = 0; base < W * N; base += kFftThreads * U) {
@@ -600,7 +602,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
     Plan<N>::template run<L, false>(lds, tw);
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
         const int w = e % W, i = e / W;
-        const float gv = gl[fold(i, N) * W + w];
+        const float gv = gl[w * NH + fold(i, N)];
         const float2 v = lds[w * LDN + i];
         lds[w * LDN + i] = make_float2(v.x * gv, v.y * gv);
     }

@@ -106,9 +106,13 @@ __global__ void k_truncate_kernel(double* __restrict__ K, int A, int a, double s
     K[i] = (dx * dx + dy * dy + dz * dz <= a * a) ? K[i] * scale : 0.0;
 }
 
-__global__ void k_to_float(const double* __restrict__ in, float* __restrict__ out, int64_t n, double scale) {
+// FP32 copy of the octant, stored pencil-major [ky][kx][kz] (kz fastest):
+// the z-pencil pass reads each pencil's kz profile as one contiguous run
+__global__ void k_to_float_pencils(const double* __restrict__ in, float* __restrict__ out, int M, double scale) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (float)(in[i] * scale);
+    if (i >= (int64_t)M * M * M) return;
+    const int fx = (int)(i % M), fy = (int)((i / M) % M), fz = (int)(i / ((int64_t)M * M));
+    out[((int64_t)fy * M + fx) * M + fz] = (float)(in[i] * scale);
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -151,8 +155,8 @@ void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s) {
     hipLaunchKernelGGL(k_cos_axis, dim3(blocks_for((int64_t)M * M * M)), dim3(256), 0, s, b1, b0, M, M, A, 2, A, M,
                        F, 0);
     // fold in the inverse-transform normalisation and round once to FP32
-    hipLaunchKernelGGL(k_to_float, dim3(blocks_for((int64_t)M * M * M)), dim3(256), 0, s, b0, octant,
-                       (int64_t)M * M * M, 1.0 / ((double)F * F * F));
+    hipLaunchKernelGGL(k_to_float_pencils, dim3(blocks_for((int64_t)M * M * M)), dim3(256), 0, s, b0, octant, M,
+                       1.0 / ((double)F * F * F));
 }
 
 }  // namespace cube

@@ -128,7 +128,7 @@ void fft3d_convolve(float2* data, int n, int batch, const float2* tw, const void
                     int table_kind, hipStream_t s, hipEvent_t* ev = nullptr);
 
 // Real tile meshes (ntiles cubes of n^3 floats, [z][y][x]) -> convolution with
-// a real even octant table through half spectra (n^2 (n/2+1) complex per
+// a real even octant table (pencil-major, as build_fine_green writes it) through half spectra (n^2 (n/2+1) complex per
 // tile, workspace) -> potentials in place.  spec_format: 0 FP32 complex,
 // 1 BF16 pairs, 2 scaled FP16 pairs (4 bytes per complex value); with FP16 an
 // out-of-range value sets *range_flag = 1.  Only the window [out_lo, out_hi)^3
@@ -141,7 +141,9 @@ void fft_tiles_convolve(float* real_tiles, void* spec_tiles, int n, int ntiles, 
                         hipStream_t s, hipEvent_t* ev = nullptr);
 
 // ---- green.hip ----------------------------------------------------------
-// FP64 octant tables, already divided by n^3 (the inverse-FFT normalisation).
+// Octant tables computed in FP64, already divided by n^3 (the inverse-FFT
+// normalisation): coarse FP64 [kz][ky][kx]; fine rounded to FP32 and stored
+// pencil-major [ky][kx][kz] for the z-pencil pass.
 void build_coarse_green(const Geom& g, double* octant, hipStream_t s);
 void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s);
 size_t fine_green_workspace_bytes(const Geom& g);
