@@ -477,8 +477,8 @@ cube_status run_step(cube_ctx* c) {
     if (P.on) P.flush();
     if (c->sc_host->overflow)
         return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range: use CUBE_MIXED_BF16 or CUBE_FP32");
-    // the fast compaction's 16-bit per-code counts bound the source cells' counts
-    if (c->sc_host->far_count == 0 && c->max_count <= 65535) {
+    // the fast compaction's 16-bit counts and prefixes bound the old and new cell counts
+    if (c->sc_host->far_count == 0 && c->max_count <= 65535 && c->sc_host->max_count <= 65535) {
         hipEvent_t ec = P.on ? P.mark(s) : nullptr;
         launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, c->B, c->A, s);
         // 6 B + move code read, 6 B written, old and new offsets read

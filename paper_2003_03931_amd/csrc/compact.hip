@@ -16,8 +16,8 @@
 //                    + (earlier same-code particles of its own source cell).
 // Slots are mapped in LDS and the planes copied run by run (coalesced); a
 // brick with more arrivals than the map holds scatters directly instead.
-// Per-code counts are 16-bit: the caller takes this path only when no cell
-// holds more than 65535 particles.  Deterministic, no global atomics.
+// Per-code counts and prefixes are 16-bit: the caller takes this path only
+// when no cell of the old or the new counts holds more than 65535 particles.  Deterministic, no global atomics.
 //
 // General path: the new keys are sorted stably with the LSD radix sort and the
 // planes are permuted.
@@ -30,13 +30,13 @@ namespace cube {
 namespace {
 
 constexpr int kCThreads = 256;
-static_assert(kCThreads == 4 * kWave, "the prefix ranks split the 27 codes over four waves");
+static_assert(kCThreads >= 4 * kWave, "the prefix ranks split the 27 codes over four waves");
 constexpr int kMaxBX = 16;
 constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
 constexpr int kMaxDst = kMaxBX * 2 * 2;
 static_assert(kMaxDst <= kWave, "one lane per destination cell");
 constexpr int kSlots = 1024;
-constexpr int kDirCap = 4096;                      // staged move codes of the source window
+constexpr int kDirCap = 3072;                      // staged move codes of the source window
 
 struct CompactShape {
     int BX, BY, BZ;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                                                             const uint8_t* __restrict__ dir, Planes src, Planes dst) {
     __shared__ int s_start[kMaxSrc], s_canon[kMaxSrc], s_cnt[kMaxSrc];
     __shared__ uint16_t s_arr[kMaxDst][27];    // arrivals per (destination, code), then running ranks
-    __shared__ int s_pre[kMaxDst][27];
+    __shared__ uint16_t s_pre[kMaxDst][27];    // arrivals from earlier source cells (< the new count <= 65535)
     __shared__ int s_doff[kMaxDst + 1];
     __shared__ int s_run[kMaxDst + 1];      // per destination row segment: slot base
     __shared__ int s_slot[kSlots];
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     // Arrivals from earlier source cells, per destination and code.  Lane =
     // destination; its 27 source cells are ranked by canonical index.  When
     // they lie in one tile the order is the reversed code order (suffix sums,
-    // wave 0); otherwise each of the four waves ranks a quarter of the codes
+    // wave 0); otherwise each of the first four waves ranks a quarter of the codes
     // (the wave index is uniform, so the unrolled ranges stay in registers).
     {
         const int dcell = threadIdx.x & (kWave - 1), sub = threadIdx.x / kWave;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                     int acc = 0;
 #pragma unroll
                     for (int d = 26; d >= 0; --d) {
-                        s_pre[dcell][d] = acc;
+                        s_pre[dcell][d] = (uint16_t)acc;
                         acc += cnt[d];
                     }
                 }
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     _Pragma("unroll") for (int d = D0; d < D1; ++d) {                                                  \
         int acc = 0;                                                                                   \
         _Pragma("unroll") for (int d2 = 0; d2 < 27; ++d2) acc += (key[d2] < key[d]) ? cnt[d2] : 0;     \
-        s_pre[dcell][d] = acc;                                                                         \
+        s_pre[dcell][d] = (uint16_t)acc;                                                               \
     }
                 if (sub == 0) {
                     CUBE_PRE_RANGE(0, 7)
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                     CUBE_PRE_RANGE(7, 14)
                 } else if (sub == 2) {
                     CUBE_PRE_RANGE(14, 21)
-                } else {
+                } else if (sub == 3) {
                     CUBE_PRE_RANGE(21, 27)
                 }
 #undef CUBE_PRE_RANGE

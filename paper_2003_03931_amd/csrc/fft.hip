@@ -146,6 +146,73 @@ struct Dft<8, INV> {
     }
 };
 
+// e^{-+2 pi i m / n} for the internal twiddles of the composite DFTs below
+// (forward: exp(-2 pi i m / n); inverse: the conjugate)
+template <bool INV>
+__device__ __forceinline__ float2 rot(float2 a, float c, float s) {
+    return INV ? make_float2(a.x * c - a.y * s, a.x * s + a.y * c) : make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// 16 = 4 x 4: DFT-4 over n1 (n = n2 + 4 n1), twiddle w16^(n2 k1), DFT-4 over n2;
+// output index k1 + 4 k2
+template <bool INV>
+struct Dft<16, INV> {
+    __device__ __forceinline__ static void run(float2* a) {
+        const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;   // cos, sin(pi/8)
+        const float c2 = 0.70710678118654752440f;                                 // cos(pi/4)
+        float2 t[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            float2 v[4] = {a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]};
+            Dft<4, INV>::run(v);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) t[n2][k1] = v[k1];
+        }
+        // w16^m for m = n2 k1: 1 (m=0), (c1,s1) m=1, (c2,c2) m=2, (s1,c1) m=3,
+        // -i m=4, (-c2,c2) m=6, (-c1,-s1) m=9
+        t[1][1] = rot<INV>(t[1][1], c1, s1);
+        t[1][2] = rot<INV>(t[1][2], c2, c2);
+        t[1][3] = rot<INV>(t[1][3], s1, c1);
+        t[2][1] = rot<INV>(t[2][1], c2, c2);
+        t[2][2] = mul_j<INV>(t[2][2]);
+        t[2][3] = rot<INV>(t[2][3], -c2, c2);
+        t[3][1] = rot<INV>(t[3][1], s1, c1);
+        t[3][2] = rot<INV>(t[3][2], -c2, c2);
+        t[3][3] = rot<INV>(t[3][3], -c1, -s1);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 v[4] = {t[0][k1], t[1][k1], t[2][k1], t[3][k1]};
+            Dft<4, INV>::run(v);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = v[k2];
+        }
+    }
+};
+
+// 10 = 2 x 5: DFT-5 over n2 (n = n1 + 2 n2), twiddle w10^(n1 k2), DFT-2 over
+// n1; output index k2 + 5 k1
+template <bool INV>
+struct Dft<10, INV> {
+    __device__ __forceinline__ static void run(float2* a) {
+        const float c36 = 0.80901699437494742410f, s36 = 0.58778525229247312917f;
+        const float c72 = 0.30901699437494742410f, s72 = 0.95105651629515357212f;
+        float2 e[5] = {a[0], a[2], a[4], a[6], a[8]};
+        float2 o[5] = {a[1], a[3], a[5], a[7], a[9]};
+        Dft<5, INV>::run(e);
+        Dft<5, INV>::run(o);
+        // w10^k2 for k2 = 1..4: (cos, sin) of 36, 72, 108, 144 degrees
+        o[1] = rot<INV>(o[1], c36, s36);
+        o[2] = rot<INV>(o[2], c72, s72);
+        o[3] = rot<INV>(o[3], -c72, s72);
+        o[4] = rot<INV>(o[4], -c36, s36);
+#pragma unroll
+        for (int k2 = 0; k2 < 5; ++k2) {
+            a[k2] = cadd(e[k2], o[k2]);
+            a[k2 + 5] = csub(e[k2], o[k2]);
+        }
+    }
+};
+
 // ---- one Stockham pass over P pencils in LDS -----------------------------
 // Layout L: P pencils, element i of pencil w at lds[w*SP + i*SE]; with WFAST
 // consecutive threads take consecutive pencils (strided pencils), otherwise
@@ -230,7 +297,7 @@ CUBE_FFT_PLAN(80, 5, 4, 4)
 CUBE_FFT_PLAN(96, 3, 4, 8)
 CUBE_FFT_PLAN(112, 7, 4, 4)
 CUBE_FFT_PLAN(128, 2, 8, 8)
-CUBE_FFT_PLAN(160, 5, 4, 8)
+CUBE_FFT_PLAN(160, 16, 10)
 CUBE_FFT_PLAN(192, 3, 8, 8)
 CUBE_FFT_PLAN(224, 7, 4, 8)
 CUBE_FFT_PLAN(256, 4, 8, 8)
@@ -240,6 +307,18 @@ CUBE_FFT_PLAN(448, 7, 8, 8)
 CUBE_FFT_PLAN(512, 8, 8, 8)
 CUBE_FFT_PLAN(1024, 4, 4, 8, 8)
 #undef CUBE_FFT_PLAN
+
+// Plan of the z-pencil pass: 16 pencils per 256-thread workgroup, where short
+// radices keep every thread busy (a radix-16 pass would use 160 of 256).
+template <int N>
+struct PlanZ : Plan<N> {};
+template <>
+struct PlanZ<160> {
+    template <class L, bool INV>
+    __device__ __forceinline__ static void run(float2* lds, const float2* __restrict__ tw, int tid = threadIdx.x) {
+        run_passes<160, L, INV, 1, 5, 4, 8>(lds, tw, tid);
+    }
+};
 
 template <int N>
 constexpr int pencils() { return N <= 256 ? 16 : 8; }
@@ -599,7 +678,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
     }
     __syncthreads();
     using L = Lay<W, 1, LDN, false, kFftThreads>;
-    Plan<N>::template run<L, false>(lds, tw);
+    PlanZ<N>::template run<L, false>(lds, tw);
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
         const int w = e % W, i = e / W;
         const float gv = gl[w * NH + fold(i, N)];
@@ -607,7 +686,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
         lds[w * LDN + i] = make_float2(v.x * gv, v.y * gv);
     }
     __syncthreads();
-    Plan<N>::template run<L, true>(lds, tw);
+    PlanZ<N>::template run<L, true>(lds, tw);
     bool bad = false;
     for (int e = threadIdx.x; e < W * (hi - lo); e += kFftThreads) {       // only z in [lo, hi) is used
         const int w = e % W, i = lo + e / W;
