@@ -110,6 +110,20 @@ __device__ inline int find_cell(const int* offs, int len, int p) {
     return lo;
 }
 
+// The same search with a fixed number of steps (len <= 2^LOG2): the largest
+// index i < len with offs[i] <= p.  With no data-dependent trip count, the
+// searches of several unrolled elements overlap their LDS latencies.
+template <int LOG2>
+__device__ __forceinline__ int find_cell_fixed(const int* offs, int len, int p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 1 << (LOG2 - 1); step > 0; step >>= 1) {
+        const int mid = lo + step;
+        if (mid < len && offs[mid] <= p) lo = mid;
+    }
+    return lo;
+}
+
 }  // namespace cube
 
 namespace cube {

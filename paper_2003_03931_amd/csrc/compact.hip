@@ -34,9 +34,12 @@ static_assert(kCThreads >= 4 * kWave, "the prefix ranks split the 27 codes over 
 constexpr int kMaxBX = 16;
 constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
 constexpr int kMaxDst = kMaxBX * 2 * 2;
+static_assert(kMaxSrc <= 512, "fixed-step search over the source window");
 static_assert(kMaxDst <= kWave, "one lane per destination cell");
 constexpr int kSlots = 1024;
 constexpr int kDirCap = 3072;                      // staged move codes of the source window
+constexpr int kMovCap = 768;
+constexpr int kSrcLog2 = 9;                        // 2^9 >= kMaxSrc                       // movers of the window handled one thread per particle
 
 struct CompactShape {
     int BX, BY, BZ;
@@ -54,6 +57,10 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     __shared__ int s_pref[kMaxSrc + 1];
     __shared__ int s_scan[kCThreads / kWave + 1];
     __shared__ uint8_t s_dir[kDirCap];
+    __shared__ uint16_t s_mv[kDirCap + 1];     // movers before each window particle (window order)
+    __shared__ uint16_t s_mov[kMovCap];        // window index of each mover
+    __shared__ uint16_t s_mrank[kMovCap];      // mover's rank among its cell's same-code particles
+    __shared__ int s_hxyz[kMaxSrc];            // window coordinates of each source cell, 8 bits each
 
     const int BX = sh.BX, BY = sh.BY, BZ = sh.BZ;
     const int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
@@ -67,6 +74,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         const int64_t c = canon(g, wrapi(B0[0] + hx - 1, g.Nc), wrapi(B0[1] + hy - 1, g.Nc),
                                 wrapi(B0[2] + hz - 1, g.Nc));
         s_canon[h] = (int)c;
+        s_hxyz[h] = hx | (hy << 8) | (hz << 16);
         const int st = off_old[c];
         s_start[h] = st;
         s_cnt[h] = off_old[c + 1] - st;
@@ -118,36 +126,93 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) return -1;
         return ex + BX * (ey + BY * ez);
     };
-    // walk 1: each source cell's thread loads its move codes (8 in flight),
-    // stages them in LDS when the window fits, and counts its arrivals
+    // Walk 1.  Most particles keep their cell (code 13).  When the window's
+    // codes fit in LDS they are staged one lane per particle, and a block
+    // scan counts the movers before every particle: a stayer's rank in its
+    // cell is then its in-cell index minus the movers before it, with no
+    // per-cell walk.  The movers (listed by the scan) are ranked by their
+    // cell's thread, so per-thread work follows the few movers, not the
+    // crowded cells.  Blocks with too many movers, or windows too large to
+    // stage, walk each source cell serially.
     const int nwin = s_pref[nsrc];
     const bool staged = nwin <= kDirCap;
-    // Most particles keep their cell (code 13): those are counted in a
-    // register, so only the movers go through LDS read-modify-writes.
     constexpr int kStay = 13;
-    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-        const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
-        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-        int stay = 0;
-        for (int q0 = 0; q0 < n; q0 += 8) {
-            int cq[8];
+    bool bal = false;
+    if (staged) {
+        stage_to_lds<kCThreads, kDirCap / kCThreads>(
+            nwin, dir, s_dir,
+            [&](int e) {
+                const int h = find_cell_fixed<kSrcLog2>(s_pref, nsrc, e);
+                return (int64_t)s_start[h] + (e - s_pref[h]);
+            },
+            [](int e) { return e; });
+        __syncthreads();
+        constexpr int K = kDirCap / kCThreads;
+        int nm = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) cq[u] = (q0 + u < n) ? (int)dir[st + q0 + u] : 255;
+        for (int j = 0; j < K; ++j) {
+            const int e = threadIdx.x * K + j;
+            nm += (e < nwin && s_dir[e] != kStay) ? 1 : 0;
+        }
+        int tot;
+        int mb = block_exclusive_scan(nm, s_scan, &tot);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (q0 + u >= n) break;
-                const int d = cq[u];
-                if (staged) s_dir[base + q0 + u] = (uint8_t)d;
-                if (d == kStay) {
-                    ++stay;
-                } else {
-                    const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
-                    if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
+        for (int j = 0; j < K; ++j) {
+            const int e = threadIdx.x * K + j;
+            if (e < nwin) {
+                s_mv[e] = (uint16_t)mb;
+                if (s_dir[e] != kStay) {
+                    if (mb < kMovCap) s_mov[mb] = (uint16_t)e;
+                    ++mb;
                 }
             }
         }
-        const int dstay = dest_of(hx, hy, hz, kStay);
-        if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)stay;       // the only writer of this entry
+        if (threadIdx.x == 0) s_mv[nwin] = (uint16_t)tot;
+        bal = tot <= kMovCap;
+        __syncthreads();
+    }
+    if (bal) {
+        for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+            const int start = s_pref[h], end = s_pref[h + 1];
+            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            const int m0 = s_mv[start], m1 = s_mv[end];
+            const int dstay = dest_of(hx, hy, hz, kStay);
+            if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)((end - start) - (m1 - m0));
+            for (int m = m0; m < m1; ++m) {
+                const int d = s_dir[s_mov[m]];
+                const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
+                if (dc >= 0) {
+                    const int r = s_arr[dc][d];
+                    s_arr[dc][d] = (uint16_t)(r + 1);
+                    s_mrank[m] = (uint16_t)r;
+                }
+            }
+        }
+    } else {
+        for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+            const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
+            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            int stay = 0;
+            for (int q0 = 0; q0 < n; q0 += 8) {
+                int cq[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    cq[u] = (q0 + u < n) ? (staged ? (int)s_dir[base + q0 + u] : (int)dir[st + q0 + u]) : 255;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (q0 + u >= n) break;
+                    const int d = cq[u];
+                    if (d == kStay) {
+                        ++stay;
+                    } else {
+                        const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
+                        if (dc >= 0) s_arr[dc][d] = (uint16_t)(s_arr[dc][d] + 1);
+                    }
+                }
+            }
+            const int dstay = dest_of(hx, hy, hz, kStay);
+            if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)stay;       // the only writer of this entry
+        }
     }
     __syncthreads();
     auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
@@ -200,48 +265,74 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         }
     }
     __syncthreads();
-    // reuse the arrival counts as running ranks
-    for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
-    __syncthreads();
-
     const bool use_slots = s_run[nrow] <= kSlots;
-    // walk 2: slot of every particle that lands in this brick
-    // (four particles per iteration so that their LDS reads overlap; stayers
-    // are ranked by a register counter, movers by the LDS counters)
-    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-        const int st = s_start[h], n = s_cnt[h];
-        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-        const int dstay = dest_of(hx, hy, hz, kStay);
-        int stay = 0;
-        for (int q0 = 0; q0 < n; q0 += 4) {
-            int dq[4];
+    auto place = [&](int dcell, int d, int rank, int p) {
+        const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
+        if (use_slots) {
+            const int row = dcell / BX;
+            const int slot = s_run[row] + (o - s_doff[BX * row]);
+            if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
+        } else if (o >= 0 && o < g.n) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) dq[u] = (q0 + u < n) ? code(h, q0 + u) : 255;
+            for (int a = 0; a < 3; ++a) {
+                dst.m[a][o] = src.m[a][p];
+                dst.u[a][o] = src.u[a][p];
+            }
+            if (dst.ids) dst.ids[o] = src.ids[p];
+        }
+    };
+    if (bal) {
+        // walk 2, one thread per window particle (four searches in flight)
+        constexpr int U = 4;
+        for (int e0 = threadIdx.x; e0 < nwin; e0 += kCThreads * U) {
+            int hv[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int d = dq[u];
-                const int dcell = d == kStay ? dstay : (d < 27 ? dest_of(hx, hy, hz, d) : -1);
-                if (dcell < 0) continue;
-                int rank;
-                if (d == kStay) {
-                    rank = stay++;
-                } else {
-                    rank = s_arr[dcell][d];
-                    s_arr[dcell][d] = (uint16_t)(rank + 1);
-                }
-                const int p = st + q0 + u;
-                const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
-                if (use_slots) {
-                    const int row = dcell / BX;
-                    const int slot = s_run[row] + (o - s_doff[BX * row]);
-                    if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
-                } else if (o >= 0 && o < g.n) {
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kCThreads;
+                hv[u] = e < nwin ? find_cell_fixed<kSrcLog2>(s_pref, nsrc, e) : -1;
+            }
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        dst.m[a][o] = src.m[a][p];
-                        dst.u[a][o] = src.u[a][p];
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kCThreads, h = hv[u];
+                if (h < 0) continue;
+                const int d = s_dir[e];
+                const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+                const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
+                if (dc < 0) continue;
+                const int start = s_pref[h];
+                const int rank = d == kStay ? (e - start) - ((int)s_mv[e] - (int)s_mv[start]) : (int)s_mrank[s_mv[e]];
+                place(dc, d, rank, s_start[h] + (e - start));
+            }
+        }
+    } else {
+        // reuse the arrival counts as running ranks
+        for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
+        __syncthreads();
+        // walk 2: slot of every particle that lands in this brick (four
+        // particles per iteration so that their LDS reads overlap; stayers are
+        // ranked by a register counter, movers by the LDS counters)
+        for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+            const int st = s_start[h], n = s_cnt[h];
+            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            const int dstay = dest_of(hx, hy, hz, kStay);
+            int stay = 0;
+            for (int q0 = 0; q0 < n; q0 += 4) {
+                int dq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) dq[u] = (q0 + u < n) ? code(h, q0 + u) : 255;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int d = dq[u];
+                    const int dcell = d == kStay ? dstay : (d < 27 ? dest_of(hx, hy, hz, d) : -1);
+                    if (dcell < 0) continue;
+                    int rank;
+                    if (d == kStay) {
+                        rank = stay++;
+                    } else {
+                        rank = s_arr[dcell][d];
+                        s_arr[dcell][d] = (uint16_t)(rank + 1);
                     }
-                    if (dst.ids) dst.ids[o] = src.ids[p];
+                    place(dcell, d, rank, st + q0 + u);
                 }
             }
         }

@@ -33,6 +33,7 @@ template <int BW, int MODE, class ACC, int MAXSRC, int MAPCAP>
 __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* __restrict__ offsets, Planes p,
                                                           float* __restrict__ out, int M, int cpc, int log2D,
                                                           double scale, int tile0) {
+    static_assert(MAXSRC <= 1024, "fixed-step search over the source window");
     __shared__ ACC acc[BW * BW * BW];
     __shared__ int s_start[MAXSRC];
     __shared__ int s_pref[MAXSRC + 1];
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
             const int e = base + u * kDepThreads + threadIdx.x;
             src_of[u] = -1;
             if (e < total) {
-                const int s = mapped ? (int)s_map[e] : find_cell(s_pref, nsrc, e);
+                const int s = mapped ? (int)s_map[e] : find_cell_fixed<(MAXSRC <= 256 ? 8 : 10)>(s_pref, nsrc, e);
                 const int pidx = s_start[s] + (e - s_pref[s]);
                 src_of[u] = s;
 #pragma unroll

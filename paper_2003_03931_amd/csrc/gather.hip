@@ -29,6 +29,7 @@ constexpr int kMinR = 4;                                 // coarse cells of >= 4
 constexpr int kMaxCoarseLds = (kBX / kMinR + 4) * (kBY / kMinR + 4) * (kBZ / kMinR + 4);
 constexpr int kMaxRows = (kBY / kMinR) * (kBZ / kMinR);
 constexpr int kMaxRowLen = kBX / kMinR;
+static_assert(kMaxRows <= 8 && kMaxRowLen <= 8, "fixed three-step searches of rows and cells");
 constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
 constexpr int kGatherThreads = 256;
 
@@ -213,9 +214,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     // software pipeline: the next particle's bytes are in flight while the
     // current one is computed
     auto locate = [&](int e, int& p, int& lx, int& ly, int& lz) {
-        const int row = find_cell(s_rowpref, nrows, e);
+        const int row = find_cell_fixed<3>(s_rowpref, nrows, e);      // nrows <= 8
         p = s_rowoff[row][0] + (e - s_rowpref[row]);
-        lx = find_cell(s_rowoff[row], BXc, p);
+        lx = find_cell_fixed<3>(s_rowoff[row], BXc, p);              // BXc <= 8
         ly = row % BYc;
         lz = row / BYc;
     };

@@ -194,10 +194,36 @@ def test_general_compaction_path_far_movers():
     assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
 
 
+def test_many_one_cell_movers():
+    """Velocities that carry most particles into a neighbouring cell but
+    never further: the fast compaction with more movers than its per-particle
+    mover list holds (per-cell walks), against the oracle."""
+    from oracle import codec, pm, step
+    box, ref = oracle_state("t4")
+    # drift per step = u s (256 / H) dt quanta; with |u| <= 127 and s = 0.25
+    # it stays below 256 (one cell) while about half the particles change cell
+    u = np.clip(ref.u.astype(np.int64) * 3, -127, 127).astype(np.int8)
+    M = int(np.abs(u.astype(np.int64)).max())
+    fast = codec.State(box, ref.counts.copy(), ref.m.copy(), u, 0.25, M, ref.ids.copy())
+    o, info = step.step(pm.Solver(box), fast, return_info=True)
+    assert info["max_carry"] == 1
+    with gpu_box("t4") as g:
+        load_state(g, fast)
+        g.step(1)
+        st = g.get_state()
+        diag = g.diagnostics()
+    assert diag["max_carry"] == 1
+    assert st["counts"].sum() == ref.n
+    d = _compare_by_id(box, st, o)
+    assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
+
+
 def _dense_state(n_dense, seed=77):
     """t4 box with n_dense particles packed into one coarse cell (the rest
-    uniform): exercises the wide (64-bit) fine deposit and, above 65535 per
-    cell, the sorted compaction."""
+    uniform): 300 keeps the 32-bit fine deposit and the staged compaction,
+    1500 overflows the compaction's staged window (per-cell walks from
+    memory), 70000 needs the wide (64-bit) fine deposit and the sorted
+    compaction."""
     import oracle
     from oracle import codec
     spec = config("t4")
@@ -210,7 +236,7 @@ def _dense_state(n_dense, seed=77):
     return box, codec.compress(box, pos.astype(np.float32), vel.astype(np.float32), with_ids=True)
 
 
-@pytest.mark.parametrize("n_dense", [300, 70000])
+@pytest.mark.parametrize("n_dense", [300, 1500, 70000])
 def test_dense_cell_paths(n_dense):
     from oracle import cic, pm, step
     box, ref = _dense_state(n_dense)
