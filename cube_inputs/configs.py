@@ -38,6 +38,7 @@ class BoxSpec:
     rms_disp: float        # rms |psi| of the Zel'dovich displacement
     seed: int
     steps: int
+    fd_order: int = 2      # 2- or 4-point central-difference gradients
 
     def with_(self, **kw):
         return replace(self, **kw)

@@ -44,10 +44,10 @@ class FloatSolver:
         box = self.box
         x = np.asarray(pos, dtype=np.float64)
         rho_c = cic.deposit(x / box.H, box.n_coarse) / box.H ** 3 - 1.0
-        g_c = fd_gradient(solve(rho_c, self.Gc), box.H)
+        g_c = fd_gradient(solve(rho_c, self.Gc), box.H, box.fd_order)
         a_c = cic.gather(g_c, x / box.H).T
         rho_f = cic.deposit(x / box.h, box.n_fine) / box.h ** 3 - 1.0
-        g_f = fd_gradient(solve(rho_f, self.Gf), box.h)
+        g_f = fd_gradient(solve(rho_f, self.Gf), box.h, box.fd_order)
         a_f = cic.gather(g_f, x / box.h).T
         return a_f, a_c
 

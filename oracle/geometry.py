@@ -24,12 +24,13 @@ class Box:
     r_cut_fine: int
     dt: float
     v_headroom: float = 2.0
+    fd_order: int = 2                 # R13: 2- or 4-point gradient on both meshes
 
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.n_side, spec.tiles_per_dim, spec.fine_per_spacing,
                    spec.coarse_ratio, spec.buffer_fine, spec.r_cut_fine,
-                   float(spec.dt), float(spec.v_headroom))
+                   float(spec.dt), float(spec.v_headroom), int(getattr(spec, "fd_order", 2)))
 
     # ---- derived sizes -------------------------------------------------
     @property
@@ -77,12 +78,16 @@ class Box:
                       self.buffer_fine, self.r_cut_fine)
         assert self.n_fine % r == 0 and self.n_fine % self.tiles_per_dim == 0
         assert self.T % r == 0 and b % r == 0
+        assert self.fd_order in (2, 4)
         if self.tiles_per_dim == 1:
             assert b == 0 and 2 * a < self.F
         else:
-            # R11: a + 3 <= b keeps every target's stencil inside the exact
-            # part of the tile box
-            assert a <= b - 3
+            # R11: a target's CIC nodes lie in [-1, T] of the tile, its
+            # gradient reads the potential fd_order/2 cells further out, that
+            # potential reads the density a cells further still, and a density
+            # cell is complete one cell inside the buffer's edge: a <= b - 3
+            # for 2-point gradients, a <= b - 4 for 4-point ones
+            assert a <= b - 2 - self.fd_order // 2
             assert self.F // r <= self.n_coarse
         return self
 

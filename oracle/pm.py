@@ -10,6 +10,9 @@ Per mesh (Eq. (1) applied to the potential, R13):
     rho   = CIC mass / cell volume - 1           (R10, R18: nominal mean removed)
     phi   = IDFT( G * DFT(rho) )                 (R12, R14)
     g     = -(phi(c+e) - phi(c-e)) / (2 * cell)  (2-point central difference)
+            or -(8 (phi(c+e) - phi(c-e)) - (phi(c+2e) - phi(c-2e))) / (12 * cell)
+                                                 (4-point, the optional R13 variant;
+                                                  Box.fd_order picks one for both meshes)
     a     = CIC-gather(g_fine) + CIC-gather(g_coarse)
 
 Positions come straight from the fixed-point state: fine-box coordinates
@@ -19,7 +22,7 @@ Removing the nominal mean density 1 instead of the exact box mean changes only
 the k = 0 mode, i.e. a constant potential whose difference-gradient is zero.
 
 Pins (tests/test_oracle_pm.py): Eq. (1) equivalence of potential-plus-FD with
-the kernel -i sin(k h)/h G; exact momentum conservation (pairwise symmetry,
+the kernel -i sin(k h)/h G (4-point: -i (8 sin(k h) - sin(2 k h))/(6 h) G); exact momentum conservation (pairwise symmetry,
 random sets); zero force on a uniform lattice; single-particle force against
 the Ewald sum and 1/(4 pi r^2); tiling invariance (tiled fine force equals the
 single-periodic-mesh fine force with the same kernel).
@@ -35,11 +38,18 @@ from . import cic, green
 from .geometry import Box
 
 
-def fd_gradient(phi, cell: float) -> np.ndarray:
-    """g = -grad phi by 2-point central differences on a periodic array."""
+def fd_gradient(phi, cell: float, order: int = 2) -> np.ndarray:
+    """g = -grad phi by 2- or 4-point central differences on a periodic array."""
+    if order not in (2, 4):
+        raise ValueError("fd order must be 2 or 4")
     g = np.empty((3,) + phi.shape, dtype=np.float64)
     for ax in range(3):
-        g[ax] = -(np.roll(phi, -1, axis=ax) - np.roll(phi, 1, axis=ax)) / (2.0 * cell)
+        d1 = np.roll(phi, -1, axis=ax) - np.roll(phi, 1, axis=ax)      # phi(c+e) - phi(c-e)
+        if order == 2:
+            g[ax] = -d1 / (2.0 * cell)
+        else:
+            d2 = np.roll(phi, -2, axis=ax) - np.roll(phi, 2, axis=ax)  # phi(c+2e) - phi(c-2e)
+            g[ax] = -(8.0 * d1 - d2) / (12.0 * cell)
     return g
 
 
@@ -114,7 +124,7 @@ def _tile_force(box, Q, counts, offsets, t, Gf, want_phi=False):
     tgt = tile_targets(box, offsets, t)
     X = tile_box_coords(box, Q[tgt], origin)
     periodic = box.tiles_per_dim == 1
-    acc = cic.gather(fd_gradient(phi, box.h), X, periodic=periodic).T
+    acc = cic.gather(fd_gradient(phi, box.h, box.fd_order), X, periodic=periodic).T
     pot = cic.gather(phi, X, periodic=periodic) if want_phi else None
     return tgt, acc, pot
 
@@ -187,14 +197,15 @@ def tile_force_sampled(box: Box, counts, offsets, m, t, Gf):
     rho = cic.deposit(tile_box_coords(box, Qs, origin), box.F, periodic=periodic) / box.h ** 3 - 1.0
     phi = solve(rho, Gf)
     tgt, Qt = quanta_of_cells(box, counts, offsets, m, np.arange(t * Tc ** 3, (t + 1) * Tc ** 3))
-    acc = cic.gather(fd_gradient(phi, box.h), tile_box_coords(box, Qt, origin), periodic=periodic).T
+    acc = cic.gather(fd_gradient(phi, box.h, box.fd_order), tile_box_coords(box, Qt, origin),
+                     periodic=periodic).T
     return tgt, Qt, acc
 
 
 def coarse_force_at(box: Box, rho_c, Gc, Q):
     """Coarse-mesh acceleration at global quanta Q for a given coarse density
     rho_c (mass per cell volume minus 1)."""
-    g = fd_gradient(solve(rho_c, Gc), box.H)
+    g = fd_gradient(solve(rho_c, Gc), box.H, box.fd_order)
     return cic.gather(g, (np.asarray(Q, dtype=np.float64) + 0.5) / 256.0, periodic=True).T
 
 
@@ -218,7 +229,7 @@ class Solver:
         offsets = state.offsets()
         phi_c = coarse_potential(box, Q, self.Gc)
         Xc = (Q.astype(np.float64) + 0.5) / 256.0
-        a_c = cic.gather(fd_gradient(phi_c, box.H), Xc, periodic=True).T
+        a_c = cic.gather(fd_gradient(phi_c, box.H, box.fd_order), Xc, periodic=True).T
         a_f, p_f = _fine_all(box, Q, counts, offsets, self.Gf, want_phi, workers)
         a = a_f + a_c
         extra = ()

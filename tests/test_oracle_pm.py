@@ -25,22 +25,57 @@ def test_fd_gradient_closed_form():
     assert np.max(np.abs(g[1])) < 1e-15 and np.max(np.abs(g[2])) < 1e-15
 
 
-def test_potential_plus_difference_equals_eq1_kernel():
+def test_fd4_gradient_closed_form():
+    """4-point central difference of a sine wave: the derivative's Fourier
+    factor is (8 sin(kh) - sin(2kh)) / (6h), exactly."""
+    n, h, m = 16, 0.5, 3
+    i = np.arange(n)
+    k = 2 * np.pi * m / (n * h)
+    phi = np.sin(k * i * h)[None, None, :] * np.ones((n, n, n))
+    g = pm.fd_gradient(phi, h, order=4)
+    expect = -np.cos(k * i * h) * (8 * np.sin(k * h) - np.sin(2 * k * h)) / (6 * h)
+    assert np.max(np.abs(g[2] - expect[None, None, :])) < 1e-14
+    assert np.max(np.abs(g[0])) < 1e-15 and np.max(np.abs(g[1])) < 1e-15
+
+
+def test_fd_orders_converge_at_their_order():
+    """Halving the cell of a resolved wave cuts the 2-point error by 4 and
+    the 4-point error by 16 (leading terms (kh)^2/6 and (kh)^4/30)."""
+    def err(n, order):
+        h = 1.0 / n
+        x = (np.arange(n) + 0.5) * h
+        k = 2 * np.pi
+        phi = np.cos(k * x)[:, None, None] * np.ones((n, 2, 2))
+        g = pm.fd_gradient(phi, h, order=order)[0][:, 0, 0]
+        return np.max(np.abs(g - k * np.sin(k * x))) / k
+    for order, ratio, lead in ((2, 4.0, lambda kh: kh ** 2 / 6), (4, 16.0, lambda kh: kh ** 4 / 30)):
+        e1, e2 = err(64, order), err(128, order)
+        assert abs(e1 / e2 - ratio) < 0.01 * ratio
+        assert abs(e2 / lead(2 * np.pi / 128) - 1) < 0.01
+    with pytest.raises(ValueError):
+        pm.fd_gradient(np.zeros((4, 4, 4)), 1.0, order=3)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_potential_plus_difference_equals_eq1_kernel(order):
     """Eq. (1): F^i = IDFT(rho_hat K^i).  The potential-plus-difference route
-    is Eq. (1) with K^i(k) = -i sin(k_i h)/h * G(k)."""
+    is Eq. (1) with K^i(k) = -i sin(k_i h)/h * G(k) for 2-point differences and
+    -i (8 sin(k_i h) - sin(2 k_i h))/(6h) * G(k) for 4-point ones."""
     box = box_of("c1")
     rng = np.random.default_rng(0)
     n, h = box.n_coarse, box.H
     rho = rng.standard_normal((n, n, n))
     G = green.coarse_green(box)
-    g = pm.fd_gradient(pm.solve(rho, G), h)
+    g = pm.fd_gradient(pm.solve(rho, G), h, order)
     modes = np.fft.fftfreq(n, d=1.0 / n)
     kx = 2 * np.pi * modes / (n * h)
     kz = 2 * np.pi * np.fft.rfftfreq(n, d=1.0 / n) / (n * h)
     ks = [kx[:, None, None], kx[None, :, None], kz[None, None, :]]
     rk = np.fft.rfftn(rho)
     for ax in range(3):
-        K = -1j * np.sin(ks[ax] * h) / h * G
+        kh = ks[ax] * h
+        D = np.sin(kh) / h if order == 2 else (8 * np.sin(kh) - np.sin(2 * kh)) / (6 * h)
+        K = -1j * D * G
         F = np.fft.irfftn(rk * K, s=(n, n, n), axes=(0, 1, 2))
         assert np.max(np.abs(F - g[ax])) < 1e-13 * np.max(np.abs(g[ax]))
 
@@ -50,9 +85,9 @@ def _state_from_positions(box, pos):
     return codec.compress(box, pos, np.zeros_like(pos), with_ids=True)
 
 
-@pytest.mark.parametrize("name", ["c1", "t4"])
-def test_pair_forces_are_antisymmetric(name):
-    box = box_of(name)
+@pytest.mark.parametrize("name,order", [("c1", 2), ("t4", 2), ("c1", 4), ("t4", 4)])
+def test_pair_forces_are_antisymmetric(name, order):
+    box = Box.from_spec(config(name).with_(fd_order=order)).validate()
     sol = pm.Solver(box)
     # in t4 the pair straddles a tile face (tile side 16 spacings)
     pos = [[15.3, 9.7, 20.2], [17.1, 8.9, 21.4]] if name == "t4" else \
@@ -96,11 +131,12 @@ def test_uniform_lattice_feels_no_force(name):
     assert np.max(np.abs(a)) < 1e-12
 
 
-def test_tiling_invariance():
-    """R11: with a <= b - 3 the tiled short-range force equals the fine force
-    of one periodic mesh carrying the same truncated kernel."""
-    box = box_of("t4")
-    spec = config("t4")
+@pytest.mark.parametrize("order", [2, 4])
+def test_tiling_invariance(order):
+    """R11: with a <= b - 2 - order/2 the tiled short-range force equals the
+    fine force of one periodic mesh carrying the same truncated kernel."""
+    spec = config("t4").with_(fd_order=order)
+    box = Box.from_spec(spec).validate()
     pos, vel = zeldovich_ics(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
     st = codec.compress(box, pos, vel)
     _, a_f, a_c = pm.Solver(box).forces(st, parts=True)
@@ -108,6 +144,22 @@ def test_tiling_invariance():
     bf, bc = fsol.parts(st.positions())
     assert np.max(np.abs(a_f - bf)) < 1e-12 * np.max(np.abs(bf))
     assert np.max(np.abs(a_c - bc)) < 1e-12 * np.max(np.abs(bc))
+
+
+def test_fd4_buffer_bound_is_tight():
+    """With 4-point gradients one more buffer cell is needed: at a = b - 3
+    the tiled fine force no longer equals the single-mesh one, and the
+    geometry check refuses that box."""
+    spec = config("t4").with_(fd_order=4, r_cut_fine=config("t4").buffer_fine - 3)
+    box = Box.from_spec(spec)
+    with pytest.raises(AssertionError):
+        box.validate()
+    Box.from_spec(spec.with_(fd_order=2)).validate()
+    pos, vel = zeldovich_ics(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
+    st = codec.compress(box, pos, vel)
+    a_f, _ = pm._fine_all(box, st.quanta(), st.counts, st.offsets(), green.fine_green(box), False, 1)
+    bf, _ = float_mode.FloatSolver(box).parts(st.positions())
+    assert np.max(np.abs(a_f - bf)) > 1e-7 * np.max(np.abs(bf))
 
 
 def _single_source_field(box, src):
