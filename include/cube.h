@@ -77,13 +77,19 @@ typedef enum {
  *   coarse_ratio      r, fine cells per coarse cell (power of two, 2..16).
  *   buffer_fine       b, tile buffer in fine cells (multiple of r; 0 if n_t == 1).
  *   r_cut_fine        a, force-split radius in fine cells; needs a <= b - 3
- *                     (n_t > 1) or 2a < tile side (n_t == 1).
+ *                     (n_t > 1, 2-point gradients), a <= b - 4 (n_t > 1,
+ *                     4-point gradients) or 2a < tile side (n_t == 1).
  *   dt                time step (units of the dynamical time).
  *   v_headroom        h_v >= 1, velocity-scale headroom (2 is the default).
  *   precision         cube_precision.
  *   with_ids          nonzero: carry a uint32 particle id plane (tests only; not
  *                     part of the 6 bytes per particle).
  *   tiles_per_batch   tiles whose fine meshes are in flight at once (0 = auto).
+ *   fd_order          central-difference gradient of both potentials (Sec. II,
+ *                     Eq. (1) taken through the potential): 2 = two-point
+ *                     (phi(c+1) - phi(c-1)) / 2h, 4 = four-point
+ *                     (8 (phi(c+1) - phi(c-1)) - (phi(c+2) - phi(c-2))) / 12h;
+ *                     0 means 2, anything else is CUBE_INVALID.
  * Derived: coarse cells per side N_c = n_side f / r, tile side T = n_side f / n_t
  * fine cells, tile FFT box F = T + 2b; every FFT side must factor into 2,3,5,7.
  */
@@ -99,7 +105,7 @@ typedef struct {
     int32_t precision;
     int32_t with_ids;
     int32_t tiles_per_batch;
-    int32_t reserved;
+    int32_t fd_order;
 } cube_box_desc;
 
 typedef struct cube_ctx cube_ctx;

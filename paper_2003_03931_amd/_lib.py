@@ -34,7 +34,7 @@ class BoxDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("with_ids", ctypes.c_int32),
         ("tiles_per_batch", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fd_order", ctypes.c_int32),
     ]
 
 

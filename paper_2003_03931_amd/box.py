@@ -23,7 +23,7 @@ def desc_from(spec, with_ids=False, tiles_per_batch=0, precision=CUBE_FP32):
     return BoxDesc(int(spec.n_side), int(spec.tiles_per_dim), int(spec.fine_per_spacing),
                    int(spec.coarse_ratio), int(spec.buffer_fine), int(spec.r_cut_fine),
                    float(spec.dt), float(spec.v_headroom), int(precision), 1 if with_ids else 0,
-                   int(tiles_per_batch), 0)
+                   int(tiles_per_batch), int(getattr(spec, "fd_order", 2)))
 
 
 def footprint(spec, tiles_per_batch=0, precision=CUBE_FP32, with_ids=False):
@@ -76,7 +76,7 @@ class TorchAllocator:
 class CubeBox:
     """One box: owns a cube_ctx.  `spec` carries the geometry fields of
     cube_box_desc (n_side, tiles_per_dim, fine_per_spacing, coarse_ratio,
-    buffer_fine, r_cut_fine, dt, v_headroom)."""
+    buffer_fine, r_cut_fine, dt, v_headroom, and optionally fd_order)."""
 
     def __init__(self, spec, with_ids=False, tiles_per_batch=0, device=0, precision=CUBE_FP32,
                  allocator="torch"):

@@ -237,6 +237,9 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     g.b = d->buffer_fine;
     g.a = d->r_cut_fine;
     if (g.ns <= 0 || g.nt <= 0 || g.a <= 0) return fail(CUBE_INVALID, "sizes must be positive");
+    if (d->fd_order != 0 && d->fd_order != 2 && d->fd_order != 4)
+        return fail(CUBE_INVALID, "fd_order must be 2 or 4 (0 means 2)");
+    g.fdr = d->fd_order == 4 ? 2 : 1;
     if (!is_pow2(g.f) || !is_pow2(g.r) || g.r < 2 || g.r > 16 || g.r < g.f)
         return fail(CUBE_INVALID, "fine_per_spacing and coarse_ratio must be powers of two, 2 <= r <= 16, r >= f");
     const int64_t nfine = (int64_t)g.ns * g.f;
@@ -252,7 +255,12 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
         g.F = g.T;
         g.periodic = 1;
     } else {
-        if (g.a > g.b - 3) return fail(CUBE_INVALID, "tiles need r_cut <= buffer - 3");
+        // a target's CIC nodes lie within one cell of its tile, the gradient
+        // reads fdr cells further, the truncated kernel a cells further, and
+        // a density cell is complete one cell inside the buffer's edge
+        if (g.a > g.b - 2 - g.fdr)
+            return fail(CUBE_INVALID, g.fdr == 1 ? "tiles need r_cut <= buffer - 3"
+                                                 : "tiles with 4-point gradients need r_cut <= buffer - 4");
         g.F = g.T + 2 * g.b;
         g.periodic = 0;
         if (g.F / g.r > g.Nc) return fail(CUBE_INVALID, "tile box larger than the periodic box");
@@ -390,14 +398,15 @@ int spec_format(const cube_ctx* c) {
 }
 
 // fine potentials of tiles [t0, t0 + nt) into ctx->fine_real: over the
-// whole box when `full`, else over the tile plus the 2 cells the gather's
-// interpolation and differences reach (all of the box for a periodic tile)
+// whole box when `full`, else over the tile plus the 1 + fdr cells the
+// gather's interpolation and differences reach (all of the box for a
+// periodic tile)
 void fine_potential(cube_ctx* c, int t0, int nt, bool full = false) {
     const Geom& g = c->g;
     Profiler& P = c->prof;
     const int fmt = spec_format(c);
     const bool whole = full || g.periodic;
-    const int lo = whole ? 0 : g.b - 2, hi = whole ? g.F : g.b + g.T + 2;
+    const int lo = whole ? 0 : g.b - 1 - g.fdr, hi = whole ? g.F : g.b + g.T + 1 + g.fdr;
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                         c->stream);

@@ -3,12 +3,15 @@
 // tile; Sec. III-A: positions and velocities are re-encoded after the update).
 //
 // One workgroup per brick of 32 x 16 x 8 fine cells of one tile.  It stages
-// the tile's fine potential over the brick plus a 2-cell halo and the coarse
-// potential over the brick's coarse cells plus a 2-cell halo in LDS, then
-// walks the brick's particles (its coarse cells' contiguous ranges):
+// the tile's fine potential over the brick plus a halo of H cells and the
+// coarse potential over the brick's coarse cells plus H cells in LDS (H = 2
+// for 2-point differences, 3 for 4-point ones: the CIC nodes reach one cell
+// out, the difference stencil H - 1 more), then walks the brick's particles
+// (its coarse cells' contiguous ranges):
 //   * decode (Eq. (2)) into fine and coarse coordinates, exactly;
 //   * a = CIC-gather of -grad phi_f + CIC-gather of -grad phi_c, gradients by
-//     2-point central differences taken on the fly from the LDS potentials;
+//     2- or 4-point central differences taken on the fly from the LDS
+//     potentials;
 //   * kick in FP64:  u' = clamp(rint((u s + a dt) / s'), -127, 127);
 //   * drift in cell-local quanta, exactly in FP64:
 //       X = m + 1/2 + ((u' s') (256/H)) dt,  q = floor(X),
@@ -23,15 +26,20 @@ namespace cube {
 namespace {
 
 constexpr int kBX = 32, kBY = 16, kBZ = 8;              // brick, fine cells
-constexpr int kLX = kBX + 4, kLY = kBY + 4, kLZ = kBZ + 4;
-constexpr int kFineLds = kLX * kLY * kLZ;                // 8640 floats
 constexpr int kMinR = 4;                                 // coarse cells of >= 4 fine cells
-constexpr int kMaxCoarseLds = (kBX / kMinR + 4) * (kBY / kMinR + 4) * (kBZ / kMinR + 4);
 constexpr int kMaxRows = (kBY / kMinR) * (kBZ / kMinR);
 constexpr int kMaxRowLen = kBX / kMinR;
 static_assert(kMaxRows <= 8 && kMaxRowLen <= 8, "fixed three-step searches of rows and cells");
 constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
 constexpr int kGatherThreads = 256;
+
+// LDS extents for a halo of H cells: H = 2 (8640 fine floats) or 3 (11704)
+template <int H>
+struct Halo {
+    static constexpr int LX = kBX + 2 * H, LY = kBY + 2 * H, LZ = kBZ + 2 * H;
+    static constexpr int FINE = LX * LY * LZ;
+    static constexpr int COARSE = (kBX / kMinR + 2 * H) * (kBY / kMinR + 2 * H) * (kBZ / kMinR + 2 * H);
+};
 
 struct LdsGrid {
     const float* p;
@@ -39,41 +47,55 @@ struct LdsGrid {
     __device__ float at(int x, int y, int z) const { return p[(z * sxy) + y * sx + x]; }
 };
 
-// CIC gather of -grad(phi): i0/t per axis in LDS-grid coordinates.
-__device__ __forceinline__ void gather_force(const LdsGrid& phi, const int i0[3], const float t[3], float inv2h,
+// w0 (-D phi)(i0) + w1 (-D phi)(i0 + 1) from v[j] = phi(i0 - R + j), without
+// the 1/(2h) or 1/(12h) factor: D phi(n) = phi(n+1) - phi(n-1) for R = 1,
+// 8 (phi(n+1) - phi(n-1)) - (phi(n+2) - phi(n-2)) for R = 2.
+template <int R>
+__device__ __forceinline__ float neg_diff_interp(const float* v, float w0, float w1) {
+    if constexpr (R == 1)
+        return w0 * (v[0] - v[2]) + w1 * (v[1] - v[3]);
+    else
+        return w0 * (8.0f * (v[1] - v[3]) - (v[0] - v[4])) + w1 * (8.0f * (v[2] - v[4]) - (v[1] - v[5]));
+}
+
+// CIC gather of -grad(phi) with a difference stencil of reach R: i0/t per
+// axis in LDS-grid coordinates, `scale` the difference's 1/(2h) or 1/(12h).
+template <int R>
+__device__ __forceinline__ void gather_force(const LdsGrid& phi, const int i0[3], const float t[3], float scale,
                                              float out[3]) {
     const float w[3][2] = {{1.0f - t[0], t[0]}, {1.0f - t[1], t[1]}, {1.0f - t[2], t[2]}};
     float ax = 0.f, ay = 0.f, az = 0.f;
+    float v[2 * R + 2];
 #pragma unroll
     for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
         for (int oy = 0; oy < 2; ++oy) {
             const int y = i0[1] + oy, z = i0[2] + oz;
-            const float xm = phi.at(i0[0] - 1, y, z), x0 = phi.at(i0[0], y, z);
-            const float x1 = phi.at(i0[0] + 1, y, z), x2 = phi.at(i0[0] + 2, y, z);
-            ax += w[1][oy] * w[2][oz] * (w[0][0] * (xm - x1) + w[0][1] * (x0 - x2));
+#pragma unroll
+            for (int j = 0; j < 2 * R + 2; ++j) v[j] = phi.at(i0[0] - R + j, y, z);
+            ax += w[1][oy] * w[2][oz] * neg_diff_interp<R>(v, w[0][0], w[0][1]);
         }
 #pragma unroll
     for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
         for (int ox = 0; ox < 2; ++ox) {
             const int x = i0[0] + ox, z = i0[2] + oz;
-            const float ym = phi.at(x, i0[1] - 1, z), y0 = phi.at(x, i0[1], z);
-            const float y1 = phi.at(x, i0[1] + 1, z), y2 = phi.at(x, i0[1] + 2, z);
-            ay += w[0][ox] * w[2][oz] * (w[1][0] * (ym - y1) + w[1][1] * (y0 - y2));
+#pragma unroll
+            for (int j = 0; j < 2 * R + 2; ++j) v[j] = phi.at(x, i0[1] - R + j, z);
+            ay += w[0][ox] * w[2][oz] * neg_diff_interp<R>(v, w[1][0], w[1][1]);
         }
 #pragma unroll
     for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
         for (int ox = 0; ox < 2; ++ox) {
             const int x = i0[0] + ox, y = i0[1] + oy;
-            const float zm = phi.at(x, y, i0[2] - 1), z0 = phi.at(x, y, i0[2]);
-            const float z1 = phi.at(x, y, i0[2] + 1), z2 = phi.at(x, y, i0[2] + 2);
-            az += w[0][ox] * w[1][oy] * (w[2][0] * (zm - z1) + w[2][1] * (z0 - z2));
+#pragma unroll
+            for (int j = 0; j < 2 * R + 2; ++j) v[j] = phi.at(x, y, i0[2] - R + j);
+            az += w[0][ox] * w[1][oy] * neg_diff_interp<R>(v, w[2][0], w[2][1]);
         }
-    out[0] = ax * inv2h;
-    out[1] = ay * inv2h;
-    out[2] = az * inv2h;
+    out[0] = ax * scale;
+    out[1] = ay * scale;
+    out[2] = az * scale;
 }
 
 __device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3], const float t[3]) {
@@ -89,8 +111,10 @@ __device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3
     return acc;
 }
 
-template <int MODE>
+template <int MODE, int H>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
+    constexpr int kLX = Halo<H>::LX, kLY = Halo<H>::LY;
+    constexpr int kFineLds = Halo<H>::FINE, kMaxCoarseLds = Halo<H>::COARSE;
     __shared__ float s_fine[kFineLds];
     __shared__ float s_coarse[kMaxCoarseLds];
     __shared__ int s_rowoff[kMaxRows][kMaxRowLen + 1];
@@ -115,16 +139,16 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const int lc[3] = {lf[0] / r, lf[1] / r, lf[2] / r};
     const int gc[3] = {tx * g.Tc + lc[0], ty * g.Tc + lc[1], tz * g.Tc + lc[2]};
 
-    // fine potential of the brick plus 2 cells: tile-box coords b + lf - 2 ...
+    // fine potential of the brick plus H cells: tile-box coords b + lf - H ...
     const float* fmesh = A.fine_real + (int64_t)k * g.F * g.F * g.F;   // tile k of the batch
-    const int F = g.F, ox = g.b + lf[0] - 2, oy = g.b + lf[1] - 2, oz = g.b + lf[2] - 2;
+    const int F = g.F, ox = g.b + lf[0] - H, oy = g.b + lf[1] - H, oz = g.b + lf[2] - H;
     const bool per = g.periodic != 0;
     // Every load of the staging phase (fine potential with halo, coarse
     // potential with halo, row offsets) is issued before the first wait: one
     // memory latency per block instead of one per round.
-    const int CX = BXc + 4, CY = BYc + 4, CZ = BZc + 4;
+    const int CX = BXc + 2 * H, CY = BYc + 2 * H, CZ = BZc + 2 * H;
     const float* cmesh = reinterpret_cast<const float*>(A.coarse);
-    const int Nc = g.Nc, cx0 = gc[0] - 2, cy0 = gc[1] - 2, cz0 = gc[2] - 2;
+    const int Nc = g.Nc, cx0 = gc[0] - H, cy0 = gc[1] - H, cz0 = gc[2] - H;
     const int ncoarse = CX * CY * CZ, nrowoff = nrows * (BXc + 1);
     constexpr int UF = (kFineLds + kGatherThreads - 1) / kGatherThreads;
     constexpr int UC = (kMaxCoarseLds + kGatherThreads - 1) / kGatherThreads;
@@ -197,8 +221,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const LdsGrid cphi{s_coarse, CX, CX * CY};
     const int D = 1 << g.log2D, halfD = D >> 1;
     const float invD = 1.0f / (float)D;
-    const float inv2h = (float)g.f * 0.5f;                   // 1 / (2h)
-    const float inv2H = (float)g.f / (2.0f * (float)r);      // 1 / (2H)
+    constexpr int R = H - 1;                                 // difference reach
+    // 1 / (2h) and 1 / (2H), or 1 / (12h) and 1 / (12H)
+    const float scale_f = R == 1 ? (float)g.f * 0.5f : (float)g.f / 12.0f;
+    const float scale_c = R == 1 ? (float)g.f / (2.0f * (float)r) : (float)g.f / (12.0f * (float)r);
     double s = 0.0, s_next = 0.0, inv_s_next = 0.0;
     if (MODE == GATHER_STEP) {
         s = A.sc->s;
@@ -247,13 +273,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         float ft[3], ct[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            // fine: brick-relative position in 1/D cells, LDS origin at -2
+            // fine: brick-relative position in 1/D cells, LDS origin at -H
             const int Pf = 2 * (lcell[a] * 256 + m[a]) + 1 - halfD;
-            fi[a] = (Pf >> g.log2D) + 2;
+            fi[a] = (Pf >> g.log2D) + H;
             ft[a] = (float)(Pf & (D - 1)) * invD;
-            // coarse: brick-relative in 1/512 coarse cells, LDS origin at -2
+            // coarse: brick-relative in 1/512 coarse cells, LDS origin at -H
             const int Pc = 2 * (lcell[a] * 256 + m[a]) + 1 - 256;
-            ci[a] = (Pc >> 9) + 2;
+            ci[a] = (Pc >> 9) + H;
             ct[a] = (float)(Pc & 511) * (1.0f / 512.0f);
         }
         if (MODE == GATHER_POTENTIAL) {
@@ -261,8 +287,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             continue;
         }
         float af[3], ac[3];
-        gather_force(fphi, fi, ft, inv2h, af);
-        gather_force(cphi, ci, ct, inv2H, ac);
+        gather_force<R>(fphi, fi, ft, scale_f, af);
+        gather_force<R>(cphi, ci, ct, scale_c, ac);
         const float acc[3] = {af[0] + ac[0], af[1] + ac[1], af[2] + ac[2]};
         if (MODE == GATHER_FORCE) {
 #pragma unroll
@@ -365,14 +391,20 @@ bool gather_supported(const Geom& g) {
     return g.T % kBX == 0 && g.T % kBY == 0 && g.r >= kMinR && kBZ % g.r == 0;
 }
 
+template <int H>
+void launch_gather_halo(const GatherArgs& a, const dim3& grid, hipStream_t s) {
+    if (a.mode == GATHER_STEP)
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H>), grid, dim3(kGatherThreads), 0, s, a);
+    else if (a.mode == GATHER_FORCE)
+        hipLaunchKernelGGL((k_gather<GATHER_FORCE, H>), grid, dim3(kGatherThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gather<GATHER_POTENTIAL, H>), grid, dim3(kGatherThreads), 0, s, a);
+}
+
 void launch_gather(const GatherArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)gather_blocks_per_tile(a.g), a.ntiles);
-    if (a.mode == GATHER_STEP)
-        hipLaunchKernelGGL(k_gather<GATHER_STEP>, grid, dim3(kGatherThreads), 0, s, a);
-    else if (a.mode == GATHER_FORCE)
-        hipLaunchKernelGGL(k_gather<GATHER_FORCE>, grid, dim3(kGatherThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_gather<GATHER_POTENTIAL>, grid, dim3(kGatherThreads), 0, s, a);
+    if (a.g.fdr == 2) launch_gather_halo<3>(a, grid, s);
+    else launch_gather_halo<2>(a, grid, s);
 }
 
 }  // namespace cube

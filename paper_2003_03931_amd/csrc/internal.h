@@ -28,6 +28,7 @@ struct Geom {
     int hc;        // buffer in coarse cells (b / r)
     int log2D;     // log2(512 / r): fine-coordinate fraction bits
     int periodic;  // 1 when the single tile is the periodic box
+    int fdr;       // reach of the gradient stencil: 1 (2-point) or 2 (4-point)
     int64_t ncells;   // Nc^3
     int64_t n;        // ns^3 particles
     int ntiles;       // nt^3

@@ -53,6 +53,23 @@ def test_invalid_descriptor_is_rejected_without_a_gpu():
     bad3 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 7, 0, 0, 0)     # unknown precision
     assert lib.cube_init(ctypes.byref(bad3), None, None, ctypes.byref(ctx)) == 1
     assert b"precision" in lib.cube_last_error()
+    bad4 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 0, 0, 0, 3)     # fd_order 3
+    assert lib.cube_init(ctypes.byref(bad4), None, None, ctypes.byref(ctx)) == 1
+    assert b"fd_order" in lib.cube_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
+def test_four_point_gradients_need_one_more_buffer_cell():
+    """a <= b - 3 suffices for 2-point gradients, 4-point ones need a <= b - 4
+    (the same bound the oracle's geometry check enforces)."""
+    from paper_2003_03931_amd._lib import BoxDesc, load
+    lib = load()
+    p, t = ctypes.c_int64(), ctypes.c_int64()
+    for a, order, ok in ((13, 2, True), (13, 0, True), (13, 4, False), (12, 4, True)):
+        d = BoxDesc(64, 4, 2, 4, 16, a, 0.05, 2.0, 0, 0, 0, order)
+        assert (lib.cube_footprint(ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)) == 0) == ok, (a, order)
+        if not ok:
+            assert b"buffer - 4" in lib.cube_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
