@@ -34,12 +34,11 @@ static_assert(kCThreads >= 4 * kWave, "the prefix ranks split the 27 codes over 
 constexpr int kMaxBX = 16;
 constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
 constexpr int kMaxDst = kMaxBX * 2 * 2;
-static_assert(kMaxSrc <= 512, "fixed-step search over the source window");
+static_assert(kMaxSrc <= 512, "a window particle's source cell takes 9 bits");
 static_assert(kMaxDst <= kWave, "one lane per destination cell");
 constexpr int kSlots = 1024;
 constexpr int kDirCap = 3072;                      // staged move codes of the source window
-constexpr int kMovCap = 768;
-constexpr int kSrcLog2 = 9;                        // 2^9 >= kMaxSrc                       // movers of the window handled one thread per particle
+constexpr int kMovCap = 768;                       // movers of the window handled one thread per particle
 
 struct CompactShape {
     int BX, BY, BZ;
@@ -48,19 +47,21 @@ struct CompactShape {
 __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape sh, const int32_t* __restrict__ off_old,
                                                             const int32_t* __restrict__ off_new,
                                                             const uint8_t* __restrict__ dir, Planes src, Planes dst) {
-    __shared__ int s_start[kMaxSrc], s_canon[kMaxSrc], s_cnt[kMaxSrc];
+    __shared__ int s_start[kMaxSrc];           // first old index of each source cell
+    __shared__ int s_hxyz[kMaxSrc];            // window coordinates of each source cell, 8 bits each
+    __shared__ int s_pref[kMaxSrc + 1];        // window position of each source cell's first particle
+    __shared__ uint16_t s_mvs[kMaxSrc];        // movers before each source cell (window order)
     __shared__ uint16_t s_arr[kMaxDst][27];    // arrivals per (destination, code), then running ranks
     __shared__ uint16_t s_pre[kMaxDst][27];    // arrivals from earlier source cells (< the new count <= 65535)
     __shared__ int s_doff[kMaxDst + 1];
-    __shared__ int s_run[kMaxDst + 1];      // per destination row segment: slot base
+    __shared__ int s_run[kMaxDst + 1];         // per destination row segment: slot base
     __shared__ int s_slot[kSlots];
-    __shared__ int s_pref[kMaxSrc + 1];
     __shared__ int s_scan[kCThreads / kWave + 1];
-    __shared__ uint8_t s_dir[kDirCap];
-    __shared__ uint16_t s_mv[kDirCap + 1];     // movers before each window particle (window order)
+    // one word per window particle: source cell (bits 0-8), move code (9-13,
+    // 31 = farther than one cell), movers before it in window order (14-31)
+    __shared__ uint32_t s_e[kDirCap];
     __shared__ uint16_t s_mov[kMovCap];        // window index of each mover
     __shared__ uint16_t s_mrank[kMovCap];      // mover's rank among its cell's same-code particles
-    __shared__ int s_hxyz[kMaxSrc];            // window coordinates of each source cell, 8 bits each
 
     const int BX = sh.BX, BY = sh.BY, BZ = sh.BZ;
     const int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
@@ -69,22 +70,10 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     const int b = (int)xcd_logical_block();
     const int B0[3] = {(b % nbx) * BX, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * BZ};
 
-    for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-        const int64_t c = canon(g, wrapi(B0[0] + hx - 1, g.Nc), wrapi(B0[1] + hy - 1, g.Nc),
-                                wrapi(B0[2] + hz - 1, g.Nc));
-        s_canon[h] = (int)c;
-        s_hxyz[h] = hx | (hy << 8) | (hz << 16);
-        const int st = off_old[c];
-        s_start[h] = st;
-        s_cnt[h] = off_old[c + 1] - st;
-    }
     for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
-    for (int e = threadIdx.x; e <= ndst; e += kCThreads) {
-        if (e < ndst) {
-            const int ex = e % BX, ey = (e / BX) % BY, ez = e / (BX * BY);
-            s_doff[e] = off_new[canon(g, B0[0] + ex, B0[1] + ey, B0[2] + ez)];
-        }
+    for (int e = threadIdx.x; e < ndst; e += kCThreads) {
+        const int ex = e % BX, ey = (e / BX) % BY, ez = e / (BX * BY);
+        s_doff[e] = off_new[canon(g, B0[0] + ex, B0[1] + ey, B0[2] + ez)];
     }
     if ((int)threadIdx.x < nrow) {
         // arrivals of each of the BY*BZ row segments (each contiguous in the new order)
@@ -92,20 +81,24 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         const int64_t first = canon(g, B0[0], B0[1] + ey, B0[2] + ez);
         s_run[r + 1] = off_new[first + BX] - off_new[first];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_run[0] = 0;
-        for (int r = 1; r <= nrow; ++r) s_run[r] += s_run[r - 1];
-    }
-    __syncthreads();
-    // prefix over the source cells (two cells per thread at most)
+    // source cells (two per thread at most): start, window coordinates and
+    // count, then the prefix of the counts over the window
     {
         constexpr int kPer = (kMaxSrc + kCThreads - 1) / kCThreads;
         int c[kPer], run = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int h = threadIdx.x * kPer + q;
-            c[q] = h < nsrc ? s_cnt[h] : 0;
+            c[q] = 0;
+            if (h < nsrc) {
+                const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+                const int64_t cc = canon(g, wrapi(B0[0] + hx - 1, g.Nc), wrapi(B0[1] + hy - 1, g.Nc),
+                                         wrapi(B0[2] + hz - 1, g.Nc));
+                const int st = off_old[cc];
+                c[q] = off_old[cc + 1] - st;
+                s_start[h] = st;
+                s_hxyz[h] = hx | (hy << 8) | (hz << 16);
+            }
             run += c[q];
         }
         int tot;
@@ -119,6 +112,10 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (threadIdx.x == 0) s_pref[nsrc] = tot;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        s_run[0] = 0;
+        for (int r = 1; r <= nrow; ++r) s_run[r] += s_run[r - 1];
+    }
     // destination cell (in the brick) of a code-d particle of the source cell
     // at window coordinates (hx, hy, hz), or -1
     auto dest_of = [&](int hx, int hy, int hz, int d) -> int {
@@ -126,60 +123,83 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         if (ex < 0 || ex >= BX || ey < 0 || ey >= BY || ez < 0 || ez >= BZ) return -1;
         return ex + BX * (ey + BY * ez);
     };
-    // Walk 1.  Most particles keep their cell (code 13).  When the window's
-    // codes fit in LDS they are staged one lane per particle, and a block
-    // scan counts the movers before every particle: a stayer's rank in its
-    // cell is then its in-cell index minus the movers before it, with no
-    // per-cell walk.  The movers (listed by the scan) are ranked by their
-    // cell's thread, so per-thread work follows the few movers, not the
-    // crowded cells.  Blocks with too many movers, or windows too large to
-    // stage, walk each source cell serially.
+    // Walk 1.  Most particles keep their cell (code 13).  When the window fits
+    // in LDS every particle gets one word: its source cell (each cell's thread
+    // fills its range), its code (staged one lane per particle, all loads in
+    // flight) and the number of movers before it (a block scan).  A stayer's
+    // rank in its cell is then its in-cell index minus the movers before it;
+    // the movers (listed by the scan) are ranked by their cell's thread, so
+    // per-thread work follows the few movers, not the crowded cells.  Blocks
+    // with too many movers, or windows too large to stage, walk each source
+    // cell serially.
     const int nwin = s_pref[nsrc];
     const bool staged = nwin <= kDirCap;
     constexpr int kStay = 13;
+    constexpr int kFar = 31;
     bool bal = false;
+    int nmov = 0;
     if (staged) {
-        stage_to_lds<kCThreads, kDirCap / kCThreads>(
-            nwin, dir, s_dir,
-            [&](int e) {
-                const int h = find_cell_fixed<kSrcLog2>(s_pref, nsrc, e);
-                return (int64_t)s_start[h] + (e - s_pref[h]);
-            },
-            [](int e) { return e; });
+        for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
+            const int e0 = s_pref[h], e1 = s_pref[h + 1];
+            for (int e = e0; e < e1; ++e) s_e[e] = (uint32_t)h;
+        }
         __syncthreads();
         constexpr int K = kDirCap / kCThreads;
+        {
+            int hv[K], cv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int e = threadIdx.x + j * kCThreads;
+                hv[j] = 0;
+                cv[j] = 0;
+                if (e < nwin) {
+                    const int h = (int)s_e[e];
+                    hv[j] = h;
+                    cv[j] = dir[(int64_t)s_start[h] + (e - s_pref[h])];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int e = threadIdx.x + j * kCThreads;
+                if (e < nwin) s_e[e] = (uint32_t)hv[j] | ((uint32_t)(cv[j] < 27 ? cv[j] : kFar) << 9);
+            }
+        }
+        __syncthreads();
+        // movers before every window particle: K consecutive particles per thread
+        uint32_t ev[K];
         int nm = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int e = threadIdx.x * K + j;
-            nm += (e < nwin && s_dir[e] != kStay) ? 1 : 0;
+            ev[j] = e < nwin ? s_e[e] : (uint32_t)(kStay << 9);
+            nm += ((ev[j] >> 9) & 31) != kStay ? 1 : 0;
         }
-        int tot;
-        int mb = block_exclusive_scan(nm, s_scan, &tot);
+        int mb = block_exclusive_scan(nm, s_scan, &nmov);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int e = threadIdx.x * K + j;
             if (e < nwin) {
-                s_mv[e] = (uint16_t)mb;
-                if (s_dir[e] != kStay) {
+                s_e[e] = ev[j] | ((uint32_t)mb << 14);
+                if (((ev[j] >> 9) & 31) != kStay) {
                     if (mb < kMovCap) s_mov[mb] = (uint16_t)e;
                     ++mb;
                 }
             }
         }
-        if (threadIdx.x == 0) s_mv[nwin] = (uint16_t)tot;
-        bal = tot <= kMovCap;
+        bal = nmov <= kMovCap;
         __syncthreads();
     }
     if (bal) {
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
             const int start = s_pref[h], end = s_pref[h + 1];
             const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
-            const int m0 = s_mv[start], m1 = s_mv[end];
+            const int m0 = start < nwin ? (int)(s_e[start] >> 14) : nmov;
+            const int m1 = end < nwin ? (int)(s_e[end] >> 14) : nmov;
+            s_mvs[h] = (uint16_t)m0;
             const int dstay = dest_of(hx, hy, hz, kStay);
             if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)((end - start) - (m1 - m0));
             for (int m = m0; m < m1; ++m) {
-                const int d = s_dir[s_mov[m]];
+                const int d = (int)((s_e[s_mov[m]] >> 9) & 31);
                 const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
                 if (dc >= 0) {
                     const int r = s_arr[dc][d];
@@ -190,14 +210,15 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         }
     } else {
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-            const int st = s_start[h], n = s_cnt[h], base = s_pref[h];
+            const int st = s_start[h], base = s_pref[h], n = s_pref[h + 1] - base;
             const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
             int stay = 0;
             for (int q0 = 0; q0 < n; q0 += 8) {
                 int cq[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    cq[u] = (q0 + u < n) ? (staged ? (int)s_dir[base + q0 + u] : (int)dir[st + q0 + u]) : 255;
+                    cq[u] = (q0 + u < n) ? (staged ? (int)((s_e[base + q0 + u] >> 9) & 31) : (int)dir[st + q0 + u])
+                                         : 255;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     if (q0 + u >= n) break;
@@ -215,27 +236,27 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         }
     }
     __syncthreads();
-    auto code = [&](int h, int q) -> int { return staged ? s_dir[s_pref[h] + q] : dir[s_start[h] + q]; };
+    auto code = [&](int h, int q) -> int {
+        return staged ? (int)((s_e[s_pref[h] + q] >> 9) & 31) : (int)dir[s_start[h] + q];
+    };
 
     // Arrivals from earlier source cells, per destination and code.  Lane =
     // destination; its 27 source cells are ranked by canonical index.  When
-    // they lie in one tile the order is the reversed code order (suffix sums,
-    // wave 0); otherwise each of the first four waves ranks a quarter of the codes
-    // (the wave index is uniform, so the unrolled ranges stay in registers).
+    // they lie in one tile (the destination is not on a tile face) the order
+    // is the reversed code order (suffix sums, wave 0); otherwise each of the
+    // first four waves ranks a quarter of the codes (the wave index is
+    // uniform, so the unrolled ranges stay in registers).
     {
         const int dcell = threadIdx.x & (kWave - 1), sub = threadIdx.x / kWave;
         if (dcell < ndst) {
-            const int ex = dcell % BX + 1, ey = (dcell / BX) % BY + 1, ez = dcell / (BX * BY) + 1;
-            int key[27], cnt[27];
-            bool lexi = true;
+            const int ex = dcell % BX, ey = (dcell / BX) % BY, ez = dcell / (BX * BY);
+            const int gx = B0[0] + ex, gy = B0[1] + ey, gz = B0[2] + ez;
+            const int lx = gx % g.Tc, ly = gy % g.Tc, lz = gz % g.Tc;
+            const bool inner = lx >= 1 && lx <= g.Tc - 2 && ly >= 1 && ly <= g.Tc - 2 && lz >= 1 && lz <= g.Tc - 2;
+            int cnt[27];
 #pragma unroll
-            for (int d = 0; d < 27; ++d) {
-                const int hs = (ex - (d % 3 - 1)) + SX * ((ey - ((d / 3) % 3 - 1)) + SY * (ez - (d / 9 - 1)));
-                key[d] = s_canon[hs];
-                cnt[d] = s_arr[dcell][d];
-                if (d > 0) lexi = lexi && (key[d] < key[d - 1]);
-            }
-            if (lexi) {
+            for (int d = 0; d < 27; ++d) cnt[d] = s_arr[dcell][d];
+            if (inner) {
                 if (sub == 0) {
                     int acc = 0;
 #pragma unroll
@@ -244,11 +265,24 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                         acc += cnt[d];
                     }
                 }
-            } else {
+            } else if (sub < 4) {
+                // canonical index of the source cell at offset (ox, oy, oz) is
+                // Ax[ox+1] + Ay[oy+1] + Az[oz+1]; code d has offsets -carry
+                const int T3 = g.Tc * g.Tc * g.Tc;
+                int Ax[3], Ay[3], Az[3];
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    const int x = wrapi(gx + o - 1, g.Nc), y = wrapi(gy + o - 1, g.Nc), z = wrapi(gz + o - 1, g.Nc);
+                    Ax[o] = (x / g.Tc) * T3 + x % g.Tc;
+                    Ay[o] = (y / g.Tc) * g.nt * T3 + (y % g.Tc) * g.Tc;
+                    Az[o] = (z / g.Tc) * g.nt * g.nt * T3 + (z % g.Tc) * g.Tc * g.Tc;
+                }
+                auto key = [&](int d) { return Ax[2 - d % 3] + Ay[2 - (d / 3) % 3] + Az[2 - d / 9]; };
 #define CUBE_PRE_RANGE(D0, D1)                                                                         \
     _Pragma("unroll") for (int d = D0; d < D1; ++d) {                                                  \
+        const int kd = key(d);                                                                         \
         int acc = 0;                                                                                   \
-        _Pragma("unroll") for (int d2 = 0; d2 < 27; ++d2) acc += (key[d2] < key[d]) ? cnt[d2] : 0;     \
+        _Pragma("unroll") for (int d2 = 0; d2 < 27; ++d2) acc += (key(d2) < kd) ? cnt[d2] : 0;         \
         s_pre[dcell][d] = (uint16_t)acc;                                                               \
     }
                 if (sub == 0) {
@@ -257,7 +291,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
                     CUBE_PRE_RANGE(7, 14)
                 } else if (sub == 2) {
                     CUBE_PRE_RANGE(14, 21)
-                } else if (sub == 3) {
+                } else {
                     CUBE_PRE_RANGE(21, 27)
                 }
 #undef CUBE_PRE_RANGE
@@ -282,25 +316,25 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         }
     };
     if (bal) {
-        // walk 2, one thread per window particle (four searches in flight)
+        // walk 2, one thread per window particle (four in flight)
         constexpr int U = 4;
         for (int e0 = threadIdx.x; e0 < nwin; e0 += kCThreads * U) {
-            int hv[U];
+            uint32_t vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int e = e0 + u * kCThreads;
-                hv[u] = e < nwin ? find_cell_fixed<kSrcLog2>(s_pref, nsrc, e) : -1;
+                vv[u] = e < nwin ? s_e[e] : (uint32_t)(kFar << 9);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * kCThreads, h = hv[u];
-                if (h < 0) continue;
-                const int d = s_dir[e];
+                const int e = e0 + u * kCThreads;
+                const int h = (int)(vv[u] & 511), d = (int)((vv[u] >> 9) & 31), mv = (int)(vv[u] >> 14);
+                if (d >= 27) continue;
                 const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
-                const int dc = d < 27 ? dest_of(hx, hy, hz, d) : -1;
+                const int dc = dest_of(hx, hy, hz, d);
                 if (dc < 0) continue;
                 const int start = s_pref[h];
-                const int rank = d == kStay ? (e - start) - ((int)s_mv[e] - (int)s_mv[start]) : (int)s_mrank[s_mv[e]];
+                const int rank = d == kStay ? (e - start) - (mv - (int)s_mvs[h]) : (int)s_mrank[mv];
                 place(dc, d, rank, s_start[h] + (e - start));
             }
         }
@@ -312,7 +346,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         // particles per iteration so that their LDS reads overlap; stayers are
         // ranked by a register counter, movers by the LDS counters)
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-            const int st = s_start[h], n = s_cnt[h];
+            const int st = s_start[h], n = s_pref[h + 1] - s_pref[h];
             const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
             const int dstay = dest_of(hx, hy, hz, kStay);
             int stay = 0;

@@ -29,6 +29,7 @@ def test_c2_ten_steps_by_id():
     o = ref
     for i in range(nsteps):
         o = step.step(sol, o, workers=workers)
+        print(f"oracle step {i + 1}/{nsteps} done", flush=True)
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2003_03931_amd import CubeBox
