@@ -30,12 +30,7 @@ namespace cube {
 namespace {
 
 constexpr int kCThreads = 256;
-static_assert(kCThreads >= 4 * kWave, "the prefix ranks split the 27 codes over four waves");
 constexpr int kMaxBX = 16;
-constexpr int kMaxSrc = (kMaxBX + 2) * 4 * 4;     // BY = BZ = 2
-constexpr int kMaxDst = kMaxBX * 2 * 2;
-static_assert(kMaxSrc <= 512, "a window particle's source cell takes 9 bits");
-static_assert(kMaxDst <= kWave, "one lane per destination cell");
 constexpr int kSlots = 1024;
 constexpr int kDirCap = 3072;                      // staged move codes of the source window
 constexpr int kMovCap = 768;                       // movers of the window handled one thread per particle
@@ -44,17 +39,28 @@ struct CompactShape {
     int BX, BY, BZ;
 };
 
-__global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape sh, const int32_t* __restrict__ off_old,
+// Brick of BX x BYZ x BYZ destination cells (BX a power of two <= 16,
+// BYZ 1 or 2), fixed at compile time so that all window index arithmetic is
+// by constants.
+template <int BX, int BYZ>
+__global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_t* __restrict__ off_old,
                                                             const int32_t* __restrict__ off_new,
                                                             const uint8_t* __restrict__ dir, Planes src, Planes dst) {
-    __shared__ int s_start[kMaxSrc];           // first old index of each source cell
-    __shared__ int s_hxyz[kMaxSrc];            // window coordinates of each source cell, 8 bits each
-    __shared__ int s_pref[kMaxSrc + 1];        // window position of each source cell's first particle
-    __shared__ uint16_t s_mvs[kMaxSrc];        // movers before each source cell (window order)
-    __shared__ uint16_t s_arr[kMaxDst][27];    // arrivals per (destination, code), then running ranks
-    __shared__ uint16_t s_pre[kMaxDst][27];    // arrivals from earlier source cells (< the new count <= 65535)
-    __shared__ int s_doff[kMaxDst + 1];
-    __shared__ int s_run[kMaxDst + 1];         // per destination row segment: slot base
+    constexpr int BY = BYZ, BZ = BYZ;
+    constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    constexpr int nsrc = SX * SY * SZ, ndst = BX * BY * BZ, nrow = BY * BZ;
+    static_assert(nsrc <= 512, "a window particle's source cell takes 9 bits");
+    static_assert(ndst <= kWave, "one lane per destination cell");
+    __shared__ int s_start[nsrc];              // first old index of each source cell
+    __shared__ int s_hxyz[nsrc];               // window coordinates of each source cell, 8 bits each
+    __shared__ int s_pref[nsrc + 1];           // window position of each source cell's first particle
+    __shared__ uint16_t s_mvs[nsrc];           // movers before each source cell (window order)
+    __shared__ uint16_t s_arr[ndst][27];       // arrivals per (destination, code), then running ranks
+    __shared__ uint16_t s_pre[ndst][27];       // arrivals from earlier source cells (< the new count <= 65535)
+    __shared__ int s_doff[ndst + 1];
+    __shared__ int s_run[nrow + 1];            // per destination row segment: slot base
+    __shared__ uint8_t s_face[ndst];           // destination cells on a tile face
+    __shared__ int s_nface;
     __shared__ int s_slot[kSlots];
     __shared__ int s_scan[kCThreads / kWave + 1];
     // one word per window particle: source cell (bits 0-8), move code (9-13,
@@ -63,12 +69,11 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     __shared__ uint16_t s_mov[kMovCap];        // window index of each mover
     __shared__ uint16_t s_mrank[kMovCap];      // mover's rank among its cell's same-code particles
 
-    const int BX = sh.BX, BY = sh.BY, BZ = sh.BZ;
-    const int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
-    const int nsrc = SX * SY * SZ, ndst = BX * BY * BZ, nrow = BY * BZ;
     const int nbx = g.Nc / BX, nby = g.Nc / BY;
     const int b = (int)xcd_logical_block();
     const int B0[3] = {(b % nbx) * BX, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * BZ};
+    const int Nc = g.Nc;
+    auto wrap1 = [Nc](int x) { return x < 0 ? x + Nc : (x >= Nc ? x - Nc : x); };   // x in [-1, Nc]
 
     for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
     for (int e = threadIdx.x; e < ndst; e += kCThreads) {
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
     // source cells (two per thread at most): start, window coordinates and
     // count, then the prefix of the counts over the window
     {
-        constexpr int kPer = (kMaxSrc + kCThreads - 1) / kCThreads;
+        constexpr int kPer = (nsrc + kCThreads - 1) / kCThreads;
         int c[kPer], run = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
@@ -92,8 +97,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
             c[q] = 0;
             if (h < nsrc) {
                 const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-                const int64_t cc = canon(g, wrapi(B0[0] + hx - 1, g.Nc), wrapi(B0[1] + hy - 1, g.Nc),
-                                         wrapi(B0[2] + hz - 1, g.Nc));
+                const int64_t cc = canon(g, wrap1(B0[0] + hx - 1), wrap1(B0[1] + hy - 1), wrap1(B0[2] + hz - 1));
                 const int st = off_old[cc];
                 c[q] = off_old[cc + 1] - st;
                 s_start[h] = st;
@@ -240,62 +244,60 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
         return staged ? (int)((s_e[s_pref[h] + q] >> 9) & 31) : (int)dir[s_start[h] + q];
     };
 
-    // Arrivals from earlier source cells, per destination and code.  Lane =
-    // destination; its 27 source cells are ranked by canonical index.  When
-    // they lie in one tile (the destination is not on a tile face) the order
-    // is the reversed code order (suffix sums, wave 0); otherwise each of the
-    // first four waves ranks a quarter of the codes (the wave index is
-    // uniform, so the unrolled ranges stay in registers).
-    {
-        const int dcell = threadIdx.x & (kWave - 1), sub = threadIdx.x / kWave;
+    // Arrivals from earlier source cells, per destination and code: the 27
+    // source cells of a destination are ranked by canonical index.  When they
+    // lie in one tile (the destination is not on a tile face) the order is the
+    // reversed code order, and wave 0 forms suffix sums, one lane per
+    // destination.  Tile-face destinations (a few per brick) are listed and
+    // ranked by the whole block, one thread per (destination, code).
+    if (threadIdx.x < kWave) {
+        const int dcell = threadIdx.x;
+        bool face = false;
         if (dcell < ndst) {
-            const int ex = dcell % BX, ey = (dcell / BX) % BY, ez = dcell / (BX * BY);
-            const int gx = B0[0] + ex, gy = B0[1] + ey, gz = B0[2] + ez;
+            const int gx = B0[0] + dcell % BX, gy = B0[1] + (dcell / BX) % BY, gz = B0[2] + dcell / (BX * BY);
             const int lx = gx % g.Tc, ly = gy % g.Tc, lz = gz % g.Tc;
-            const bool inner = lx >= 1 && lx <= g.Tc - 2 && ly >= 1 && ly <= g.Tc - 2 && lz >= 1 && lz <= g.Tc - 2;
-            int cnt[27];
+            face = !(lx >= 1 && lx <= g.Tc - 2 && ly >= 1 && ly <= g.Tc - 2 && lz >= 1 && lz <= g.Tc - 2);
+            if (!face) {
+                int acc = 0;
 #pragma unroll
-            for (int d = 0; d < 27; ++d) cnt[d] = s_arr[dcell][d];
-            if (inner) {
-                if (sub == 0) {
-                    int acc = 0;
-#pragma unroll
-                    for (int d = 26; d >= 0; --d) {
-                        s_pre[dcell][d] = (uint16_t)acc;
-                        acc += cnt[d];
-                    }
+                for (int d = 26; d >= 0; --d) {
+                    const int c = s_arr[dcell][d];
+                    s_pre[dcell][d] = (uint16_t)acc;
+                    acc += c;
                 }
-            } else if (sub < 4) {
-                // canonical index of the source cell at offset (ox, oy, oz) is
-                // Ax[ox+1] + Ay[oy+1] + Az[oz+1]; code d has offsets -carry
-                const int T3 = g.Tc * g.Tc * g.Tc;
-                int Ax[3], Ay[3], Az[3];
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    const int x = wrapi(gx + o - 1, g.Nc), y = wrapi(gy + o - 1, g.Nc), z = wrapi(gz + o - 1, g.Nc);
-                    Ax[o] = (x / g.Tc) * T3 + x % g.Tc;
-                    Ay[o] = (y / g.Tc) * g.nt * T3 + (y % g.Tc) * g.Tc;
-                    Az[o] = (z / g.Tc) * g.nt * g.nt * T3 + (z % g.Tc) * g.Tc * g.Tc;
-                }
-                auto key = [&](int d) { return Ax[2 - d % 3] + Ay[2 - (d / 3) % 3] + Az[2 - d / 9]; };
-#define CUBE_PRE_RANGE(D0, D1)                                                                         \
-    _Pragma("unroll") for (int d = D0; d < D1; ++d) {                                                  \
-        const int kd = key(d);                                                                         \
-        int acc = 0;                                                                                   \
-        _Pragma("unroll") for (int d2 = 0; d2 < 27; ++d2) acc += (key(d2) < kd) ? cnt[d2] : 0;         \
-        s_pre[dcell][d] = (uint16_t)acc;                                                               \
-    }
-                if (sub == 0) {
-                    CUBE_PRE_RANGE(0, 7)
-                } else if (sub == 1) {
-                    CUBE_PRE_RANGE(7, 14)
-                } else if (sub == 2) {
-                    CUBE_PRE_RANGE(14, 21)
-                } else {
-                    CUBE_PRE_RANGE(21, 27)
-                }
-#undef CUBE_PRE_RANGE
             }
+        }
+        const uint64_t fm = __ballot(face);
+        if (face) s_face[__popcll(fm & ((1ull << dcell) - 1ull))] = (uint8_t)dcell;
+        if (dcell == 0) s_nface = __popcll(fm);
+    }
+    __syncthreads();
+    {
+        const int nface = s_nface;
+        const int T3 = g.Tc * g.Tc * g.Tc;
+        for (int t = threadIdx.x; t < nface * 27; t += kCThreads) {
+            const int f = t / 27, d = t - 27 * f;
+            const int dcell = s_face[f];
+            const int gx = B0[0] + dcell % BX, gy = B0[1] + (dcell / BX) % BY, gz = B0[2] + dcell / (BX * BY);
+            // canonical index of the source cell at offset (ox, oy, oz) is
+            // Ax[ox+1] + Ay[oy+1] + Az[oz+1]; code d has offsets -carry
+            int Ax[3], Ay[3], Az[3];
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                const int x = wrap1(gx + o - 1), y = wrap1(gy + o - 1), z = wrap1(gz + o - 1);
+                Ax[o] = (x / g.Tc) * T3 + x % g.Tc;
+                Ay[o] = (y / g.Tc) * g.nt * T3 + (y % g.Tc) * g.Tc;
+                Az[o] = (z / g.Tc) * g.nt * g.nt * T3 + (z % g.Tc) * g.Tc * g.Tc;
+            }
+            auto sel = [](const int* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); };
+            const int kd = sel(Ax, 2 - d % 3) + sel(Ay, 2 - (d / 3) % 3) + sel(Az, 2 - d / 9);
+            int acc = 0;
+#pragma unroll
+            for (int d2 = 0; d2 < 27; ++d2) {
+                const int k2 = Ax[2 - d2 % 3] + Ay[2 - (d2 / 3) % 3] + Az[2 - d2 / 9];
+                acc += (k2 < kd) ? (int)s_arr[dcell][d2] : 0;
+            }
+            s_pre[dcell][d] = (uint16_t)acc;
         }
     }
     __syncthreads();
@@ -386,7 +388,9 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, CompactShape
             const int i = base + u * kCThreads + threadIdx.x;
             ov[u] = -1;
             if (i < total) {
-                const int row = find_cell(s_run, nrow, i);
+                int row = 0;
+#pragma unroll
+                for (int r = 1; r < nrow; ++r) row += i >= s_run[r] ? 1 : 0;
                 const int o = s_doff[BX * row] + (i - s_run[row]);
                 const int p = s_slot[i];
                 if (o >= 0 && o < g.n && p >= 0 && p < g.n) {
@@ -455,10 +459,23 @@ CompactShape compact_shape(const Geom& g) {
     CompactShape sh;
     const int H = g.r / g.f;                       // particles per coarse cell ~ H^3
     sh.BY = sh.BZ = (H <= 2) ? 2 : 1;
-    int bx = std::min(g.Tc, kMaxBX);
-    while (bx + 2 > g.Nc || g.Tc % bx) bx /= 2;    // the window must not wrap onto itself
+    int bx = kMaxBX;
+    // a power of two dividing the tile side; the window must not wrap onto itself
+    while (bx > 1 && (bx > g.Tc || bx + 2 > g.Nc || g.Tc % bx)) bx /= 2;
     sh.BX = bx;
     return sh;
+}
+
+template <int BYZ>
+void launch_compact_yz(int bx, dim3 grid, const Geom& g, const int32_t* off_old, const int32_t* off_new,
+                       const uint8_t* dir, Planes src, Planes dst, hipStream_t s) {
+    switch (bx) {
+        case 16: hipLaunchKernelGGL((k_compact_fast<16, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+        case 8: hipLaunchKernelGGL((k_compact_fast<8, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+        case 4: hipLaunchKernelGGL((k_compact_fast<4, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+        case 2: hipLaunchKernelGGL((k_compact_fast<2, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+        default: hipLaunchKernelGGL((k_compact_fast<1, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+    }
 }
 
 }  // namespace
@@ -472,8 +489,9 @@ void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_
                          Planes src, Planes dst, hipStream_t s) {
     const CompactShape sh = compact_shape(g);
     const int64_t nb = (int64_t)(g.Nc / sh.BX) * (g.Nc / sh.BY) * (g.Nc / sh.BZ);
-    hipLaunchKernelGGL(k_compact_fast, dim3((unsigned)nb), dim3(kCThreads), 0, s, g, sh, offsets_old, offsets_new,
-                       dir, src, dst);
+    const dim3 grid((unsigned)nb);
+    if (sh.BY == 2) launch_compact_yz<2>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, s);
+    else launch_compact_yz<1>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, s);
 }
 
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir, const uint32_t* far_key,
