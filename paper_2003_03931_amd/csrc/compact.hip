@@ -52,16 +52,14 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     static_assert(nsrc <= 512, "a window particle's source cell takes 9 bits");
     static_assert(ndst <= kWave, "one lane per destination cell");
     __shared__ int s_start[nsrc];              // first old index of each source cell
-    __shared__ int s_hxyz[nsrc];               // window coordinates of each source cell, 8 bits each
     __shared__ int s_pref[nsrc + 1];           // window position of each source cell's first particle
-    __shared__ uint16_t s_mvs[nsrc];           // movers before each source cell (window order)
     __shared__ uint16_t s_arr[ndst][27];       // arrivals per (destination, code), then running ranks
     __shared__ uint16_t s_pre[ndst][27];       // arrivals from earlier source cells (< the new count <= 65535)
     __shared__ int s_doff[ndst + 1];
     __shared__ int s_run[nrow + 1];            // per destination row segment: slot base
     __shared__ uint8_t s_face[ndst];           // destination cells on a tile face
     __shared__ int s_nface;
-    __shared__ int s_slot[kSlots];
+    __shared__ uint16_t s_slot[kSlots];        // window index of the particle for each output slot
     __shared__ int s_scan[kCThreads / kWave + 1];
     // one word per window particle: source cell (bits 0-8), move code (9-13,
     // 31 = farther than one cell), movers before it in window order (14-31)
@@ -74,6 +72,12 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     const int B0[3] = {(b % nbx) * BX, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * BZ};
     const int Nc = g.Nc;
     auto wrap1 = [Nc](int x) { return x < 0 ? x + Nc : (x >= Nc ? x - Nc : x); };   // x in [-1, Nc]
+    // window coordinates of source cell h
+    auto win = [](int h, int& hx, int& hy, int& hz) {
+        hx = h % SX;
+        hy = (h / SX) % SY;
+        hz = h / (SX * SY);
+    };
 
     for (int i = threadIdx.x; i < ndst * 27; i += kCThreads) (&s_arr[0][0])[i] = 0;
     for (int e = threadIdx.x; e < ndst; e += kCThreads) {
@@ -101,7 +105,6 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
                 const int st = off_old[cc];
                 c[q] = off_old[cc + 1] - st;
                 s_start[h] = st;
-                s_hxyz[h] = hx | (hy << 8) | (hz << 16);
             }
             run += c[q];
         }
@@ -196,10 +199,10 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     if (bal) {
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
             const int start = s_pref[h], end = s_pref[h + 1];
-            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            int hx, hy, hz;
+            win(h, hx, hy, hz);
             const int m0 = start < nwin ? (int)(s_e[start] >> 14) : nmov;
             const int m1 = end < nwin ? (int)(s_e[end] >> 14) : nmov;
-            s_mvs[h] = (uint16_t)m0;
             const int dstay = dest_of(hx, hy, hz, kStay);
             if (dstay >= 0) s_arr[dstay][kStay] = (uint16_t)((end - start) - (m1 - m0));
             for (int m = m0; m < m1; ++m) {
@@ -215,7 +218,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     } else {
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
             const int st = s_start[h], base = s_pref[h], n = s_pref[h + 1] - base;
-            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            int hx, hy, hz;
+            win(h, hx, hy, hz);
             int stay = 0;
             for (int q0 = 0; q0 < n; q0 += 8) {
                 int cq[8];
@@ -255,7 +259,9 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
         bool face = false;
         if (dcell < ndst) {
             const int gx = B0[0] + dcell % BX, gy = B0[1] + (dcell / BX) % BY, gz = B0[2] + dcell / (BX * BY);
-            const int lx = gx % g.Tc, ly = gy % g.Tc, lz = gz % g.Tc;
+            const int lx = g.tc_shift >= 0 ? (gx & (g.Tc - 1)) : gx % g.Tc;
+            const int ly = g.tc_shift >= 0 ? (gy & (g.Tc - 1)) : gy % g.Tc;
+            const int lz = g.tc_shift >= 0 ? (gz & (g.Tc - 1)) : gz % g.Tc;
             face = !(lx >= 1 && lx <= g.Tc - 2 && ly >= 1 && ly <= g.Tc - 2 && lz >= 1 && lz <= g.Tc - 2);
             if (!face) {
                 int acc = 0;
@@ -285,9 +291,18 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
 #pragma unroll
             for (int o = 0; o < 3; ++o) {
                 const int x = wrap1(gx + o - 1), y = wrap1(gy + o - 1), z = wrap1(gz + o - 1);
-                Ax[o] = (x / g.Tc) * T3 + x % g.Tc;
-                Ay[o] = (y / g.Tc) * g.nt * T3 + (y % g.Tc) * g.Tc;
-                Az[o] = (z / g.Tc) * g.nt * g.nt * T3 + (z % g.Tc) * g.Tc * g.Tc;
+                int tx, ty, tz, lx, ly, lz;
+                if (g.tc_shift >= 0) {
+                    const int sft = g.tc_shift, msk = g.Tc - 1;
+                    tx = x >> sft; ty = y >> sft; tz = z >> sft;
+                    lx = x & msk; ly = y & msk; lz = z & msk;
+                } else {
+                    tx = x / g.Tc; ty = y / g.Tc; tz = z / g.Tc;
+                    lx = x - tx * g.Tc; ly = y - ty * g.Tc; lz = z - tz * g.Tc;
+                }
+                Ax[o] = tx * T3 + lx;
+                Ay[o] = ty * g.nt * T3 + ly * g.Tc;
+                Az[o] = tz * g.nt * g.nt * T3 + lz * g.Tc * g.Tc;
             }
             auto sel = [](const int* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); };
             const int kd = sel(Ax, 2 - d % 3) + sel(Ay, 2 - (d / 3) % 3) + sel(Az, 2 - d / 9);
@@ -301,13 +316,15 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
         }
     }
     __syncthreads();
-    const bool use_slots = s_run[nrow] <= kSlots;
-    auto place = [&](int dcell, int d, int rank, int p) {
+    const bool use_slots = s_run[nrow] <= kSlots && nwin <= 65536;
+    // particle p (window index e) goes to output o: through the slot map, or
+    // copied directly when the brick's arrivals exceed the map
+    auto place = [&](int dcell, int d, int rank, int e, int p) {
         const int o = s_doff[dcell] + s_pre[dcell][d] + rank;
         if (use_slots) {
             const int row = dcell / BX;
             const int slot = s_run[row] + (o - s_doff[BX * row]);
-            if (slot >= 0 && slot < kSlots) s_slot[slot] = p;
+            if (slot >= 0 && slot < kSlots) s_slot[slot] = (uint16_t)e;
         } else if (o >= 0 && o < g.n) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -318,27 +335,45 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
         }
     };
     if (bal) {
-        // walk 2, one thread per window particle (four in flight)
-        constexpr int U = 4;
-        for (int e0 = threadIdx.x; e0 < nwin; e0 += kCThreads * U) {
-            uint32_t vv[U];
+        // walk 2 visits only particles that can land in the brick: the
+        // stayers of its own cells (nrow contiguous window ranges) and the
+        // movers of the whole window
+        int rs[nrow], rp[nrow + 1];
+        rp[0] = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * kCThreads;
-                vv[u] = e < nwin ? s_e[e] : (uint32_t)(kFar << 9);
-            }
+        for (int r = 0; r < nrow; ++r) {
+            const int h0 = 1 + SX * ((1 + r % BY) + SY * (1 + r / BY));
+            rs[r] = s_pref[h0];
+            rp[r + 1] = rp[r] + (s_pref[h0 + BX] - rs[r]);
+        }
+        const int ni = rp[nrow];
+        for (int i = threadIdx.x; i < ni; i += kCThreads) {
+            int e = rs[0] + i;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * kCThreads;
-                const int h = (int)(vv[u] & 511), d = (int)((vv[u] >> 9) & 31), mv = (int)(vv[u] >> 14);
-                if (d >= 27) continue;
-                const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
-                const int dc = dest_of(hx, hy, hz, d);
-                if (dc < 0) continue;
-                const int start = s_pref[h];
-                const int rank = d == kStay ? (e - start) - (mv - (int)s_mvs[h]) : (int)s_mrank[mv];
-                place(dc, d, rank, s_start[h] + (e - start));
-            }
+            for (int r = 1; r < nrow; ++r)
+                if (i >= rp[r]) e = rs[r] + (i - rp[r]);
+            const uint32_t v = s_e[e];
+            if (((v >> 9) & 31) != kStay) continue;
+            const int h = (int)(v & 511);
+            int hx, hy, hz;
+            win(h, hx, hy, hz);
+            const int dc = (hx - 1) + BX * ((hy - 1) + BY * (hz - 1));
+            const int start = s_pref[h];
+            // a stayer's rank: its in-cell index minus the movers before it in its cell
+            const int rank = (e - start) - ((int)(v >> 14) - (int)(s_e[start] >> 14));
+            place(dc, kStay, rank, e, s_start[h] + (e - start));
+        }
+        for (int m = threadIdx.x; m < nmov; m += kCThreads) {
+            const int e = s_mov[m];
+            const uint32_t v = s_e[e];
+            const int d = (int)((v >> 9) & 31);
+            if (d >= 27) continue;
+            const int h = (int)(v & 511);
+            int hx, hy, hz;
+            win(h, hx, hy, hz);
+            const int dc = dest_of(hx, hy, hz, d);
+            if (dc < 0) continue;
+            place(dc, d, (int)s_mrank[m], e, s_start[h] + (e - s_pref[h]));
         }
     } else {
         // reuse the arrival counts as running ranks
@@ -348,8 +383,9 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
         // particles per iteration so that their LDS reads overlap; stayers are
         // ranked by a register counter, movers by the LDS counters)
         for (int h = threadIdx.x; h < nsrc; h += kCThreads) {
-            const int st = s_start[h], n = s_pref[h + 1] - s_pref[h];
-            const int hp = s_hxyz[h], hx = hp & 255, hy = (hp >> 8) & 255, hz = hp >> 16;
+            const int st = s_start[h], base = s_pref[h], n = s_pref[h + 1] - base;
+            int hx, hy, hz;
+            win(h, hx, hy, hz);
             const int dstay = dest_of(hx, hy, hz, kStay);
             int stay = 0;
             for (int q0 = 0; q0 < n; q0 += 4) {
@@ -368,7 +404,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
                         rank = s_arr[dcell][d];
                         s_arr[dcell][d] = (uint16_t)(rank + 1);
                     }
-                    place(dcell, d, rank, st + q0 + u);
+                    place(dcell, d, rank, base + q0 + u, st + q0 + u);
                 }
             }
         }
@@ -392,7 +428,12 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
 #pragma unroll
                 for (int r = 1; r < nrow; ++r) row += i >= s_run[r] ? 1 : 0;
                 const int o = s_doff[BX * row] + (i - s_run[row]);
-                const int p = s_slot[i];
+                const int e = s_slot[i];
+                int p = -1;
+                if (e < nwin) {
+                    const int h = staged ? (int)(s_e[e] & 511) : find_cell_fixed<9>(s_pref, nsrc, e);
+                    p = s_start[h] + (e - s_pref[h]);
+                }
                 if (o >= 0 && o < g.n && p >= 0 && p < g.n) {
                     ov[u] = o;
 #pragma unroll
