@@ -324,7 +324,7 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
     add(8 * g.ncells);
     add(8 * Mc * Mc * Mc);
     add(8 * (int64_t)g.Nc);
-    add(4 * batch * F3);
+    add(4 * (batch * F3 + kFineRealPad));
     add(8 * (int64_t)batch * g.F * g.F * Mf);
     add(4 * Mf * Mf * Mf);
     add(8 * (int64_t)g.F);
@@ -587,7 +587,7 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     CUBE_TRY(c->alloc_n(&c->coarse_green, Mc * Mc * Mc));
     CUBE_TRY(c->alloc_n(&c->tw_coarse, g.Nc));
     const int64_t fcube = (int64_t)g.F * g.F * g.F;
-    CUBE_TRY(c->alloc_n(&c->fine_real, (int64_t)c->batch * fcube));
+    CUBE_TRY(c->alloc_n(&c->fine_real, (int64_t)c->batch * fcube + kFineRealPad));
     CUBE_TRY(c->alloc(&c->fine_spec, (size_t)c->batch * g.F * g.F * (g.F / 2 + 1) * sizeof(float2)));
     CUBE_TRY(c->alloc_n(&c->fine_green, Mf * Mf * Mf));
     CUBE_TRY(c->alloc_n(&c->tw_fine, g.F));

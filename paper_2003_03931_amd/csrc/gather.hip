@@ -19,6 +19,8 @@
 //   * write (m', u') at the same index of the second particle buffer and a
 //     move code for the compaction; new-cell counts go to an LDS histogram
 //     over the brick's cells plus one cell, flushed once per brick.
+#include <type_traits>
+
 #include "common.h"
 
 namespace cube {
@@ -33,11 +35,10 @@ static_assert(kMaxRows <= 8 && kMaxRowLen <= 8, "fixed three-step searches of ro
 constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
 constexpr int kGatherThreads = 256;
 
-// LDS extents for a halo of H cells: H = 2 (8640 fine floats) or 3 (11704)
+// extents of the staged potentials for a halo of H cells
 template <int H>
 struct Halo {
     static constexpr int LX = kBX + 2 * H, LY = kBY + 2 * H, LZ = kBZ + 2 * H;
-    static constexpr int FINE = LX * LY * LZ;
     static constexpr int COARSE = (kBX / kMinR + 2 * H) * (kBY / kMinR + 2 * H) * (kBZ / kMinR + 2 * H);
 };
 
@@ -111,11 +112,19 @@ __device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3
     return acc;
 }
 
-template <int MODE, int H>
+// PER: the single periodic tile (the fine halo wraps, staged one float at a
+// time); otherwise every staged row is read as aligned float2s.  The row's
+// first wanted float has the parity of H (the buffer and the brick origin
+// are even), so odd H stages one extra float on the left and possibly one
+// past the row's end (the mesh allocation is padded for the last row).
+template <int MODE, int H, bool PER>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
-    constexpr int kLX = Halo<H>::LX, kLY = Halo<H>::LY;
-    constexpr int kFineLds = Halo<H>::FINE, kMaxCoarseLds = Halo<H>::COARSE;
-    __shared__ float s_fine[kFineLds];
+    constexpr int kLX = Halo<H>::LX, kLY = Halo<H>::LY, kLZ = Halo<H>::LZ;
+    constexpr int kSlack = H & 1;                  // floats staged before the wanted ones
+    constexpr int kRow2 = (kLX + kSlack + 1) / 2;  // float2 per staged row
+    constexpr int kSX = 2 * kRow2;                 // LDS row stride, floats
+    constexpr int kFineLds = kSX * kLY * kLZ, kMaxCoarseLds = Halo<H>::COARSE;
+    __shared__ __align__(8) float s_fine[kFineLds];
     __shared__ float s_coarse[kMaxCoarseLds];
     __shared__ int s_rowoff[kMaxRows][kMaxRowLen + 1];
     __shared__ int s_rowpref[kMaxRows + 1];
@@ -142,7 +151,6 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     // fine potential of the brick plus H cells: tile-box coords b + lf - H ...
     const float* fmesh = A.fine_real + (int64_t)k * g.F * g.F * g.F;   // tile k of the batch
     const int F = g.F, ox = g.b + lf[0] - H, oy = g.b + lf[1] - H, oz = g.b + lf[2] - H;
-    const bool per = g.periodic != 0;
     // Every load of the staging phase (fine potential with halo, coarse
     // potential with halo, row offsets) is issued before the first wait: one
     // memory latency per block instead of one per round.
@@ -150,29 +158,45 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const float* cmesh = reinterpret_cast<const float*>(A.coarse);
     const int Nc = g.Nc, cx0 = gc[0] - H, cy0 = gc[1] - H, cz0 = gc[2] - H;
     const int ncoarse = CX * CY * CZ, nrowoff = nrows * (BXc + 1);
-    constexpr int UF = (kFineLds + kGatherThreads - 1) / kGatherThreads;
+    constexpr int NS = kLX * kLY * kLZ;            // periodic: scalar elements
+    constexpr int NV = kRow2 * kLY * kLZ;          // tiled: float2 elements
+    constexpr int UF = ((PER ? NS : NV) + kGatherThreads - 1) / kGatherThreads;
     constexpr int UC = (kMaxCoarseLds + kGatherThreads - 1) / kGatherThreads;
     constexpr int UR = (kMaxRows * (kMaxRowLen + 1) + kGatherThreads - 1) / kGatherThreads;
-    float fv[UF], cv[UC];
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    using FV = typename std::conditional<PER, float, f2>::type;
+    FV fv[UF];
+    float cv[UC];
     int rv[UR];
+    const int ox_al = ox - kSlack;                 // even
+    const int a_off = PER ? 0 : kSlack;            // first wanted float within the staged row
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
         const int e = threadIdx.x + u * kGatherThreads;
-        if (e < kFineLds) {
-            int fx = ox + e % kLX, fy = oy + (e / kLX) % kLY, fz = oz + e / (kLX * kLY);
-            if (per) {
+        if constexpr (PER) {
+            if (e < NS) {
+                int fx = ox + e % kLX, fy = oy + (e / kLX) % kLY, fz = oz + e / (kLX * kLY);
                 fx = fx < 0 ? fx + F : (fx >= F ? fx - F : fx);
                 fy = fy < 0 ? fy + F : (fy >= F ? fy - F : fy);
                 fz = fz < 0 ? fz + F : (fz >= F ? fz - F : fz);
+                fv[u] = fmesh[(fz * F + fy) * F + fx];
             }
-            fv[u] = fmesh[((int64_t)fz * F + fy) * F + fx];
+        } else {
+            if (e < NV) {
+                const int x2 = e % kRow2, row = e / kRow2, y = row % kLY, z = row / kLY;
+                fv[u] = *reinterpret_cast<const f2*>(fmesh + ((oz + z) * F + (oy + y)) * F + ox_al + 2 * x2);
+            }
         }
     }
+    // window coordinates by float reciprocals (exact: e < 2^11, extents <= 2^8)
+    const float inv_cx = 1.0f / (float)CX, inv_cxy = 1.0f / (float)(CX * CY);
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
         const int e = threadIdx.x + u * kGatherThreads;
         if (e < ncoarse) {
-            int cx = cx0 + e % CX, cy = cy0 + (e / CX) % CY, cz = cz0 + e / (CX * CY);
+            const int ez = (int)(((float)e + 0.5f) * inv_cxy), rem = e - ez * (CX * CY);
+            const int ey = (int)(((float)rem + 0.5f) * inv_cx), ex = rem - ey * CX;
+            int cx = cx0 + ex, cy = cy0 + ey, cz = cz0 + ez;
             cx = cx < 0 ? cx + Nc : (cx >= Nc ? cx - Nc : cx);
             cy = cy < 0 ? cy + Nc : (cy >= Nc ? cy - Nc : cy);
             cz = cz < 0 ? cz + Nc : (cz >= Nc ? cz - Nc : cz);
@@ -191,7 +215,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
         const int e = threadIdx.x + u * kGatherThreads;
-        if (e < kFineLds) s_fine[e] = fv[u];
+        if constexpr (PER) {
+            if (e < NS) s_fine[((e / (kLX * kLY)) * kLY + (e / kLX) % kLY) * kSX + e % kLX] = fv[u];
+        } else {
+            if (e < NV) reinterpret_cast<f2*>(s_fine)[e] = fv[u];
+        }
     }
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
@@ -217,7 +245,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     }
     __syncthreads();
 
-    const LdsGrid fphi{s_fine, kLX, kLX * kLY};
+    const LdsGrid fphi{s_fine + a_off, kSX, kSX * kLY};
     const LdsGrid cphi{s_coarse, CX, CX * CY};
     const int D = 1 << g.log2D, halfD = D >> 1;
     const float invD = 1.0f / (float)D;
@@ -391,20 +419,26 @@ bool gather_supported(const Geom& g) {
     return g.T % kBX == 0 && g.T % kBY == 0 && g.r >= kMinR && kBZ % g.r == 0;
 }
 
-template <int H>
+template <int H, bool PER>
 void launch_gather_halo(const GatherArgs& a, const dim3& grid, hipStream_t s) {
     if (a.mode == GATHER_STEP)
-        hipLaunchKernelGGL((k_gather<GATHER_STEP, H>), grid, dim3(kGatherThreads), 0, s, a);
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
     else if (a.mode == GATHER_FORCE)
-        hipLaunchKernelGGL((k_gather<GATHER_FORCE, H>), grid, dim3(kGatherThreads), 0, s, a);
+        hipLaunchKernelGGL((k_gather<GATHER_FORCE, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_gather<GATHER_POTENTIAL, H>), grid, dim3(kGatherThreads), 0, s, a);
+        hipLaunchKernelGGL((k_gather<GATHER_POTENTIAL, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
 }
 
 void launch_gather(const GatherArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)gather_blocks_per_tile(a.g), a.ntiles);
-    if (a.g.fdr == 2) launch_gather_halo<3>(a, grid, s);
-    else launch_gather_halo<2>(a, grid, s);
+    const bool per = a.g.periodic != 0;
+    if (a.g.fdr == 2) {
+        if (per) launch_gather_halo<3, true>(a, grid, s);
+        else launch_gather_halo<3, false>(a, grid, s);
+    } else {
+        if (per) launch_gather_halo<2, true>(a, grid, s);
+        else launch_gather_halo<2, false>(a, grid, s);
+    }
 }
 
 }  // namespace cube

@@ -150,6 +150,9 @@ void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s);
 size_t fine_green_workspace_bytes(const Geom& g);
 
 // ---- gather.hip ---------------------------------------------------------
+// floats allocated after the last fine mesh of a batch: the gather stages
+// rows as aligned float2s and may read one float past a row's end
+constexpr int kFineRealPad = 16;
 enum GatherMode { GATHER_STEP = 0, GATHER_FORCE = 1, GATHER_POTENTIAL = 2 };
 struct GatherArgs {
     Geom g;
