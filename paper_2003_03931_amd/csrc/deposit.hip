@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
                                                           float* __restrict__ out, int M, int cpc, int log2D,
                                                           double scale, int tile0) {
     static_assert(MAXSRC <= 1024, "fixed-step search over the source window");
-    __shared__ ACC acc[BW * BW * BW];
+    __shared__ __align__(16) ACC acc[BW * BW * BW];
     __shared__ int s_start[MAXSRC];
     __shared__ int s_pref[MAXSRC + 1];
     __shared__ int s_rel[MAXSRC];                // window coordinates + 1, 8 bits each
@@ -63,7 +63,9 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
         box0[2] = tz * g.Tc - g.hc;
     }
 
-    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) acc[i] = 0;
+    static_assert(sizeof(acc) % sizeof(uint4) == 0, "accumulators are cleared 16 bytes at a time");
+    for (int i = threadIdx.x; i < (int)(sizeof(acc) / sizeof(uint4)); i += kDepThreads)
+        reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
 
     // per-thread run of up to kPer source cells: counts, then a block scan
     constexpr int kPer = (MAXSRC + kDepThreads - 1) / kDepThreads;
@@ -169,6 +171,25 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
     __syncthreads();
 
     // exact value * scale - 1, rounded once to FP32
+    if (MODE == DEP_FINE_TILED || MODE == DEP_FINE_PERIODIC) {
+        // real mesh of tile ky: four x-consecutive cells per float4 store (the
+        // block origin and the mesh side are multiples of 4, and so is bw[0])
+        constexpr int Q = BW / 4;
+        float* mesh = out + (int64_t)ky * M * M * M;
+        for (int i4 = threadIdx.x; i4 < Q * BW * BW; i4 += kDepThreads) {
+            const int ix = 4 * (i4 % Q), iy = (i4 / Q) % BW, iz = i4 / (Q * BW);
+            if (ix >= bw[0] || iy >= bw[1] || iz >= bw[2]) continue;
+            const ACC* a = &acc[(iz * BW + iy) * BW + ix];
+            float4 v;
+            v.x = (float)fma((double)a[0], scale, -1.0);
+            v.y = (float)fma((double)a[1], scale, -1.0);
+            v.z = (float)fma((double)a[2], scale, -1.0);
+            v.w = (float)fma((double)a[3], scale, -1.0);
+            const int64_t cell = (int64_t)(T0[0] + ix) + (int64_t)M * ((T0[1] + iy) + (int64_t)M * (T0[2] + iz));
+            *reinterpret_cast<float4*>(mesh + cell) = v;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) {
         const int ix = i % BW, iy = (i / BW) % BW, iz = i / (BW * BW);
         if (ix >= bw[0] || iy >= bw[1] || iz >= bw[2]) continue;
