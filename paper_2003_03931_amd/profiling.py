@@ -34,7 +34,7 @@ STAGE_KERNEL = {
     "fine_r2c_xy": "k_r2c_plane",
     "fine_z_green": "k_zconv_half",
     "fine_c2r_xy": "k_c2r_plane",
-    "gather_kick_drift": "k_gather<0>",
+    "gather_kick_drift": "k_gather<0,",
     "scan_counts": "k_tile_scan",
     "compact": "k_compact_fast",
 }
