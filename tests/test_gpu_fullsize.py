@@ -1,5 +1,8 @@
 """Parity at the full 1024^3 size, in the launch configuration the benchmark
-times (64 tiles per batch), on outputs the oracle can compute tile by tile.
+times (64 tiles per batch), on outputs the oracle can compute tile by tile:
+forces on 32 sampled tiles (the tiles holding the runs, their face
+neighbours, whose buffers hold run particles, and seeded others), the whole
+512^3 coarse potential, and one step on a run tile.
 
 Input: the 2-per-axis lattice (8 particles per coarse cell) whose CIC density
 is exactly uniform on both meshes, with runs of cells whose particles are
@@ -49,8 +52,20 @@ def full():
     g = CubeBox(spec, tiles_per_batch=BATCH)
     g.set_state(counts, m, u, S_V, M)
     acc = g.forces()
+    phi_gpu = g.debug_mesh(1).cpu().numpy()
+    nt = box.tiles_per_dim
     tiles = [ta, ta + 1, tb - 1, tb, 0]
-    print("gpu forces done", flush=True)
+    for t in (ta, ta + 1, tb - 1, tb):
+        for d in (1, nt, nt * nt):
+            for nb in (t - d, t + d):
+                if nb not in tiles:
+                    tiles.append(nb)
+    rng = np.random.default_rng(3002)
+    while len(tiles) < 32:
+        t = int(rng.integers(box.n_tiles))
+        if t not in tiles:
+            tiles.append(t)
+    print(f"gpu forces done; {len(tiles)} sampled tiles", flush=True)
 
     # ---- oracle: coarse density of the runs relative to the lattice
     lo, hi = LATTICE_BYTES
@@ -65,13 +80,19 @@ def full():
         dmass -= cic.deposit((Ql + 0.5) / 256.0, box.n_coarse)
     rho_c = dmass / box.H ** 3
     del dmass
+    Gc = green.coarse_green(box)
+    phi_rel = rel_l2(phi_gpu, pm.solve(rho_c, Gc).transpose(2, 1, 0))
+    del phi_gpu
+    print(f"coarse potential relative L2 {phi_rel:.3e}", flush=True)
     Gf = green.fine_green(box)
     per_tile = []
-    for t in tiles:
+    for i, t in enumerate(tiles):
         tgt, Qt, af = pm.tile_force_sampled(box, counts, off, m, t, Gf)
         per_tile.append((t, tgt, Qt, af))
+        if i % 8 == 7:
+            print(f"oracle tiles {i + 1}/{len(tiles)}", flush=True)
     Qall = np.concatenate([p[2] for p in per_tile])
-    ac = pm.coarse_force_at(box, rho_c, green.coarse_green(box), Qall)
+    ac = pm.coarse_force_at(box, rho_c, Gc, Qall)
     print("oracle forces done", flush=True)
     ref, k = {}, 0
     for t, tgt, Qt, af in per_tile:
@@ -88,7 +109,13 @@ def full():
     g.close()
     print("gpu step done", flush=True)
     return types.SimpleNamespace(box=box, spec=spec, counts=counts, off=off, m=m, u=u, M=M, ref=ref, got=got,
-                                 tiles=tiles, ta=ta, tb=tb, state=st)
+                                 tiles=tiles, ta=ta, tb=tb, state=st, phi_rel=phi_rel)
+
+
+def test_full_size_coarse_potential(full):
+    """The whole 512^3 coarse potential against the oracle's FP64 solve of the
+    same density (the lattice part is uniform, so the runs carry all of it)."""
+    assert full.phi_rel < 2e-6
 
 
 def test_full_size_forces_on_sampled_tiles(full):
@@ -97,8 +124,16 @@ def test_full_size_forces_on_sampled_tiles(full):
     err = rel_l2(a, b)
     print(f"sampled-tile force relative L2 {err:.3e} over {a.shape[0]} particles")
     assert err <= 1e-5
-    for t in (full.ta, full.tb - 1, full.tb):
-        assert rel_l2(full.got[t], full.ref[t][2]) <= 1e-5
+    # tiles whose own forces are substantial (the run tiles and neighbours
+    # with run particles in their buffers) meet the bar alone; on every tile
+    # the error is small against the force scale of the run tiles
+    scale = np.sqrt(np.mean(np.concatenate([full.ref[t][2] for t in (full.ta, full.tb)]) ** 2))
+    for t in full.tiles:
+        a_ref = full.ref[t][2]
+        if np.sqrt(np.mean(a_ref ** 2)) >= 0.1 * scale:
+            e = rel_l2(full.got[t], a_ref)
+            assert e <= 1e-5, (t, e)
+        assert np.abs(full.got[t] - a_ref).max() <= 1e-4 * scale, t
 
 
 def test_full_size_step_on_sampled_tile(full):
