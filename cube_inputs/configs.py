@@ -39,6 +39,7 @@ class BoxSpec:
     seed: int
     steps: int
     fd_order: int = 2      # 2- or 4-point central-difference gradients
+    vel_codec: int = 0     # 0 linear velocity bytes, 1 cell means + companded bytes
 
     def with_(self, **kw):
         return replace(self, **kw)

@@ -13,7 +13,9 @@ Simulations" (arXiv:2003.03931):
   mesh for the long-range force and per-tile fine meshes (tile plus buffer) for
   the short-range force.
 * Sec. III-A: fixed-point compression -- positions as a 1-byte offset inside the
-  parent coarse cell (Eq. (2)), cell-ordered storage with a per-cell count.
+  parent coarse cell (Eq. (2)), cell-ordered storage with a per-cell count;
+  optionally velocities as cell means plus companded bytes (Eq. (3)) with the
+  fast arctangent of Eq. (4).
 
 Where the paper is silent the oracle follows the numbered readings R1-R22
 listed in the design doc (units, codec details, CIC, Green's functions, integrator,
@@ -24,7 +26,7 @@ in ``tests/test_oracle_*.py``.
 """
 
 from .geometry import Box
-from . import codec, cic, green, pm, step, diag, ewald, float_mode
+from . import codec, cic, green, pm, step, diag, ewald, float_mode, vcodec
 
 __all__ = ["Box", "codec", "cic", "green", "pm", "step", "diag", "ewald",
-           "float_mode"]
+           "float_mode", "vcodec"]

@@ -9,13 +9,16 @@ in cell n_c stores the bin m in one byte and sits at the bin centre.  With the
 Storage (Sec. III-A): the m bytes in cell order plus a per-cell particle count
 (R5 canonical order, stable inside a cell).
 
-Velocities: the configs store one signed byte per axis with a per-box scale
-(R6, R7), replacing Eq. (3)'s cell-mean-plus-nonlinear form:
+Velocities, default (Box.vel_codec = 0): one signed byte per axis with a
+per-box scale (R6, R7) instead of Eq. (3)'s cell-mean-plus-nonlinear form:
 
     v = u * s,  u = clamp(rint(v / s), -127, 127),  s a power of two,
     s0 = pow2ceil(h_v * max|v| / 127),   s' = pow2ceil(h_v * M * s / 127)
 
 with M = max|u| after the previous kick.  rint is round-half-to-even (R17).
+With Box.vel_codec = 1 the state holds Eq. (3)'s form instead (vcodec.py):
+per-cell mean velocities v_c plus companded one-byte deviations, and s is the
+deviation scale sigma.
 
 Pins (tests/test_oracle_codec.py): exhaustive encode(decode(Q)) == Q for every
 quantum, the half-quantum bound on random positions, the velocity half-scale
@@ -88,6 +91,7 @@ class State:
     ids: Optional[np.ndarray] = None   # uint32 [N], test-only identity (R22)
     step: int = 0
     saturations: int = 0
+    vc: Optional[np.ndarray] = None    # float32 [N_c^3, 3] cell means (vel_codec 1)
 
     @property
     def n(self) -> int:
@@ -116,12 +120,15 @@ class State:
         return decode_positions(self.box, self.quanta())
 
     def velocities(self) -> np.ndarray:
+        if self.vc is not None:
+            from . import vcodec
+            return vcodec.decode(self.counts, self.vc, self.u.T, self.s)
         return self.u.T.astype(np.float64) * self.s
 
     def copy(self):
         return State(self.box, self.counts.copy(), self.m.copy(), self.u.copy(),
                      self.s, self.M, None if self.ids is None else self.ids.copy(),
-                     self.step, self.saturations)
+                     self.step, self.saturations, None if self.vc is None else self.vc.copy())
 
 
 def build_state(box: Box, Q, u, s: float, M: int, ids=None, step=0, saturations=0):
@@ -138,8 +145,29 @@ def build_state(box: Box, Q, u, s: float, M: int, ids=None, step=0, saturations=
                  step, saturations)
 
 
+def build_state_cell_mean(box: Box, Q, v, ids=None, step=0, saturations=0):
+    """Order particles by canonical cell, stably, count them, and encode the
+    velocities v (N, 3) against the cells' means (vel_codec 1, V1-V3)."""
+    from . import vcodec
+    Q = np.asarray(Q, dtype=np.int64)
+    cells = Q // 256
+    key = box.canon(cells[:, 0], cells[:, 1], cells[:, 2])
+    order = np.argsort(key, kind="stable")
+    counts = np.bincount(key, minlength=box.n_cells).astype(np.int64)
+    m = (Q[order] % 256).T.astype(np.uint8)
+    vc, u, sigma, sat = vcodec.encode(counts, np.asarray(v, dtype=np.float64)[order])
+    M = int(np.max(np.abs(u.astype(np.int64)))) if u.size else 0
+    return State(box, counts, np.ascontiguousarray(m), np.ascontiguousarray(u.T), sigma, M,
+                 None if ids is None else np.asarray(ids)[order].astype(np.uint32),
+                 step, saturations + sat, vc)
+
+
 def compress(box: Box, pos, vel, with_ids: bool = False) -> State:
     """Float positions/velocities (any order) -> compressed state."""
+    if box.vel_codec == 1:
+        ids = np.arange(np.asarray(pos).shape[0], dtype=np.uint32) if with_ids else None
+        v32 = np.asarray(vel, dtype=np.float32)     # the library takes FP32 velocities
+        return build_state_cell_mean(box, encode_positions(box, pos), v32, ids)
     Q = encode_positions(box, pos)
     s = initial_velocity_scale(box, vel)
     u, sat = encode_velocities(vel, s)          # (N, 3)

@@ -25,12 +25,14 @@ class Box:
     dt: float
     v_headroom: float = 2.0
     fd_order: int = 2                 # R13: 2- or 4-point gradient on both meshes
+    vel_codec: int = 0                # 0: linear bytes (R6); 1: cell means + Eq. (3) bytes (V1-V4)
 
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.n_side, spec.tiles_per_dim, spec.fine_per_spacing,
                    spec.coarse_ratio, spec.buffer_fine, spec.r_cut_fine,
-                   float(spec.dt), float(spec.v_headroom), int(getattr(spec, "fd_order", 2)))
+                   float(spec.dt), float(spec.v_headroom), int(getattr(spec, "fd_order", 2)),
+                   int(getattr(spec, "vel_codec", 0)))
 
     # ---- derived sizes -------------------------------------------------
     @property
@@ -79,6 +81,7 @@ class Box:
         assert self.n_fine % r == 0 and self.n_fine % self.tiles_per_dim == 0
         assert self.T % r == 0 and b % r == 0
         assert self.fd_order in (2, 4)
+        assert self.vel_codec in (0, 1)
         if self.tiles_per_dim == 1:
             assert b == 0 and 2 * a < self.F
         else:

@@ -18,6 +18,12 @@ Recount and compaction (Sec. III-A cell-ordered storage, R16): the new counts
 are a histogram of the new cells, and particles are reordered by a stable
 counting sort of the old order by new canonical cell.
 
+With the cell-mean velocity codec (Box.vel_codec = 1, vcodec.py V4) the kick
+decodes v = v_c + sigma tan(u pi / 255), adds a dt and keeps the result in
+FP32; the drift moves by that velocity (X = m + 1/2 + v' (256 / H) dt, exact
+in FP64), and after the stable reordering the velocities are re-encoded
+against the new cells' means.
+
 Pins: the dynamics tests (Zel'dovich plane wave, leapfrog order) exercise the
 same kick/drift through the float-state twin in float_mode.py; the compaction
 is pinned by brute force (tests/test_oracle_step.py).
@@ -53,13 +59,34 @@ def drift(box, state, u_new, s_new):
     return 256 * cell_new + m_new, carry
 
 
+def kick_cell_mean(box, state, acc):
+    """V4: decoded velocity plus a dt, held in FP32 (N, 3)."""
+    return (state.velocities() + acc * box.dt).astype(np.float32)
+
+
+def drift_velocity(box, state, v32):
+    """Drift by FP32 velocities in cell-local quanta (exact in FP64)."""
+    m = state.m.T.astype(np.float64)
+    X = (m + 0.5) + v32.astype(np.float64) * (256.0 / box.H) * box.dt
+    q = np.floor(X).astype(np.int64)
+    carry = np.floor_divide(q, 256)
+    cell_new = np.mod(state.quanta() // 256 + carry, box.n_coarse)
+    return 256 * cell_new + (q - 256 * carry), carry
+
+
 def step(solver: Solver, state, workers=None, return_info=False):
     box = solver.box
     acc = solver.forces(state, workers=workers)
-    u_new, s_new, M_new, sat = kick(box, state, acc)
-    Q_new, carry = drift(box, state, u_new, s_new)
-    new = codec.build_state(box, Q_new, u_new, s_new, M_new, state.ids,
-                            state.step + 1, state.saturations + sat)
+    if box.vel_codec == 1:
+        v32 = kick_cell_mean(box, state, acc)
+        Q_new, carry = drift_velocity(box, state, v32)
+        new = codec.build_state_cell_mean(box, Q_new, v32, state.ids, state.step + 1, state.saturations)
+        sat = new.saturations - state.saturations
+    else:
+        u_new, s_new, M_new, sat = kick(box, state, acc)
+        Q_new, carry = drift(box, state, u_new, s_new)
+        new = codec.build_state(box, Q_new, u_new, s_new, M_new, state.ids,
+                                state.step + 1, state.saturations + sat)
     if return_info:
         return new, {"acc": acc, "max_carry": int(np.max(np.abs(carry))) if carry.size else 0,
                      "saturations": sat}
