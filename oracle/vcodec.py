@@ -9,7 +9,8 @@ arctangent with the approximation of Eq. (4).  Readings (the paper gives the
 form of the map only through its reference):
 
 * V1  the cell velocity v_c is the mean of the velocities of the particles
-      stored in the cell, summed in FP64 and kept as FP32 (one value per
+      stored in the cell: summed in FP64 one particle after another in
+      storage order, divided by the count, and kept as FP32 (one value per
       axis and coarse cell); an empty cell has v_c = 0.
 * V2  deviation dv = v - v_c.  Decode: dv = sigma tan(u pi / 255) for
       u in [-127, 127].  Encode: u = clamp(rint(atan~(dv / sigma) 255 / pi)),
@@ -76,15 +77,17 @@ def decode_deviation(u, sigma: float):
 
 
 def cell_means(counts, v):
-    """V1: FP32 mean velocity (n_cells, 3) of cell-ordered velocities v (N, 3)."""
+    """V1: FP32 mean velocity (n_cells, 3) of cell-ordered velocities v (N, 3),
+    each cell summed sequentially in storage order."""
     counts = np.asarray(counts, dtype=np.int64)
     v = np.asarray(v, dtype=np.float64)
     off = np.zeros(counts.size + 1, dtype=np.int64)
     np.cumsum(counts, out=off[1:])
     sums = np.zeros((counts.size, 3))
+    for j in range(int(counts.max()) if counts.size else 0):
+        live = np.nonzero(counts > j)[0]          # cells with a (j+1)-th particle
+        sums[live] += v[off[live] + j]
     nz = counts > 0
-    if v.shape[0]:
-        sums[nz] = np.add.reduceat(v, off[:-1][nz], axis=0)
     mean = np.zeros((counts.size, 3))
     mean[nz] = sums[nz] / counts[nz, None]
     return mean.astype(np.float32)

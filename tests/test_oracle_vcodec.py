@@ -67,13 +67,20 @@ def test_round_trip_deviation_bound():
 
 
 def test_cell_means_brute_force():
+    """Sequential FP64 sums per cell, divided by the count, rounded to FP32
+    (a plain loop; counts up to 40 so the summation order matters)."""
     rng = np.random.default_rng(6)
-    counts = rng.integers(0, 5, 40)
-    v = rng.standard_normal((counts.sum(), 3))
+    counts = rng.integers(0, 40, 60)
+    counts[:3] = 0
+    v = rng.standard_normal((counts.sum(), 3)) * 10.0 ** rng.integers(-3, 3, (counts.sum(), 1))
     vc = vcodec.cell_means(counts, v)
     k = 0
     for c, n in enumerate(counts):
-        want = v[k:k + n].mean(axis=0) if n else np.zeros(3)
+        acc = [0.0, 0.0, 0.0]
+        for i in range(k, k + n):
+            for a in range(3):
+                acc[a] = acc[a] + float(v[i, a])
+        want = np.array([x / n for x in acc]) if n else np.zeros(3)
         assert np.array_equal(vc[c], want.astype(np.float32))
         k += n
     assert vc.dtype == np.float32
