@@ -69,6 +69,25 @@ typedef enum {
 } cube_precision;
 
 /*
+ * Velocity storage (Sec. III-A), one signed byte u per axis and particle in
+ * both cases:
+ *   CUBE_VEL_LINEAR     v = u s with one power-of-two scale s per box.
+ *   CUBE_VEL_CELL_MEAN  Eq. (3): v = v_c + sigma tan(u pi / 255), v_c the FP32
+ *                       mean velocity of the particle's coarse cell (three
+ *                       floats per cell, summed sequentially in storage
+ *                       order), sigma the power of two at or above the rms
+ *                       deviation; codes are encoded with the fast arctangent
+ *                       of Eq. (4).  In a step the kicked velocity is held in
+ *                       FP32 (24 bytes per particle of working planes) and
+ *                       re-encoded against the new cells after the
+ *                       reordering.
+ */
+typedef enum {
+    CUBE_VEL_LINEAR = 0,
+    CUBE_VEL_CELL_MEAN = 1
+} cube_vel_codec;
+
+/*
  * Box geometry (Sec. II: coarse mesh, tiles with buffers; Sec. III-A: the
  * coarse mesh also defines the position codec).
  *   n_side            particles per dimension; box side L = n_side spacings.
@@ -90,6 +109,7 @@ typedef enum {
  *                     (phi(c+1) - phi(c-1)) / 2h, 4 = four-point
  *                     (8 (phi(c+1) - phi(c-1)) - (phi(c+2) - phi(c-2))) / 12h;
  *                     0 means 2, anything else is CUBE_INVALID.
+ *   vel_codec         cube_vel_codec (0 = linear bytes, the default).
  * Derived: coarse cells per side N_c = n_side f / r, tile side T = n_side f / n_t
  * fine cells, tile FFT box F = T + 2b; every FFT side must factor into 2,3,5,7.
  */
@@ -106,6 +126,7 @@ typedef struct {
     int32_t with_ids;
     int32_t tiles_per_batch;
     int32_t fd_order;
+    int32_t vel_codec;
 } cube_box_desc;
 
 typedef struct cube_ctx cube_ctx;
@@ -119,9 +140,12 @@ typedef struct cube_ctx cube_ctx;
  *   counts    int32 particle count per coarse cell, N_c^3 entries, canonical
  *             cell order (tile-major, tile index x-fastest; x-fastest inside).
  *   ids       uint32 ids (only with with_ids; may be NULL otherwise).
- *   s_v       velocity scale (a power of two), M_u = max |u| of the stored u,
- *             step = number of steps taken.
+ *   s_v       velocity scale (a power of two; sigma with CUBE_VEL_CELL_MEAN),
+ *             M_u = max |u| of the stored u, step = number of steps taken.
  *   on_device nonzero: the pointers are device pointers, else host pointers.
+ *   vc[3]     CUBE_VEL_CELL_MEAN only: FP32 cell-mean velocity per axis, N_c^3
+ *             entries each in canonical cell order (required by set_state,
+ *             filled by get_state when non-NULL; ignored otherwise).
  */
 typedef struct {
     int64_t n_particles;
@@ -134,6 +158,7 @@ typedef struct {
     int32_t max_u;
     int32_t on_device;
     int64_t step;
+    float* vc[3];
 } cube_state_view;
 
 /* FP64 diagnostics of the current state (mass and momentum sums, energies)

@@ -5,8 +5,10 @@ this package only marshals arguments to it.
 """
 
 from ._lib import CubeError, load, LIB_PATH, SIGNATURES
-from .box import CubeBox, fft3d, desc_from, footprint, CUBE_FP32, CUBE_MIXED_BF16, CUBE_MIXED_FP16
+from .box import (CubeBox, fft3d, desc_from, footprint, CUBE_FP32, CUBE_MIXED_BF16, CUBE_MIXED_FP16,
+                  CUBE_VEL_LINEAR, CUBE_VEL_CELL_MEAN)
 from .server import CubeServer
 
 __all__ = ["CubeBox", "CubeServer", "CubeError", "fft3d", "footprint", "load", "desc_from", "LIB_PATH",
-           "SIGNATURES", "CUBE_FP32", "CUBE_MIXED_BF16", "CUBE_MIXED_FP16"]
+           "SIGNATURES", "CUBE_FP32", "CUBE_MIXED_BF16", "CUBE_MIXED_FP16", "CUBE_VEL_LINEAR",
+           "CUBE_VEL_CELL_MEAN"]

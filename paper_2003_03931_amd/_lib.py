@@ -35,6 +35,7 @@ class BoxDesc(ctypes.Structure):
         ("with_ids", ctypes.c_int32),
         ("tiles_per_batch", ctypes.c_int32),
         ("fd_order", ctypes.c_int32),
+        ("vel_codec", ctypes.c_int32),
     ]
 
 
@@ -50,6 +51,7 @@ class StateView(ctypes.Structure):
         ("max_u", ctypes.c_int32),
         ("on_device", ctypes.c_int32),
         ("step", ctypes.c_int64),
+        ("vc", ctypes.c_void_p * 3),
     ]
 
 

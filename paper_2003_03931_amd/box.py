@@ -15,6 +15,8 @@ CUBE_FP32 = 0
 CUBE_MIXED_BF16 = 1
 CUBE_MIXED_FP16 = 2
 PRECISIONS = {"fp32": CUBE_FP32, "bf16": CUBE_MIXED_BF16, "fp16": CUBE_MIXED_FP16}
+CUBE_VEL_LINEAR = 0
+CUBE_VEL_CELL_MEAN = 1
 
 
 def desc_from(spec, with_ids=False, tiles_per_batch=0, precision=CUBE_FP32):
@@ -23,7 +25,7 @@ def desc_from(spec, with_ids=False, tiles_per_batch=0, precision=CUBE_FP32):
     return BoxDesc(int(spec.n_side), int(spec.tiles_per_dim), int(spec.fine_per_spacing),
                    int(spec.coarse_ratio), int(spec.buffer_fine), int(spec.r_cut_fine),
                    float(spec.dt), float(spec.v_headroom), int(precision), 1 if with_ids else 0,
-                   int(tiles_per_batch), int(getattr(spec, "fd_order", 2)))
+                   int(tiles_per_batch), int(getattr(spec, "fd_order", 2)), int(getattr(spec, "vel_codec", 0)))
 
 
 def footprint(spec, tiles_per_batch=0, precision=CUBE_FP32, with_ids=False):
@@ -76,7 +78,8 @@ class TorchAllocator:
 class CubeBox:
     """One box: owns a cube_ctx.  `spec` carries the geometry fields of
     cube_box_desc (n_side, tiles_per_dim, fine_per_spacing, coarse_ratio,
-    buffer_fine, r_cut_fine, dt, v_headroom, and optionally fd_order)."""
+    buffer_fine, r_cut_fine, dt, v_headroom, and optionally fd_order and
+    vel_codec)."""
 
     def __init__(self, spec, with_ids=False, tiles_per_batch=0, device=0, precision=CUBE_FP32,
                  allocator="torch"):
@@ -103,6 +106,7 @@ class CubeBox:
         self.n_cells = nc ** 3
         T = n * spec.fine_per_spacing // spec.tiles_per_dim
         self.F = T if spec.tiles_per_dim == 1 else T + 2 * spec.buffer_fine
+        self.vel_codec = int(getattr(spec, "vel_codec", 0))
 
     # ------------------------------------------------------------ lifetime
     def close(self):
@@ -156,24 +160,29 @@ class CubeBox:
 
     # --------------------------------------------------------------- state
     def get_state(self):
-        """Host copy: dict(counts int32[N_c^3], m uint8[3,N], u int8[3,N], ids, s, M, step)."""
+        """Host copy: dict(counts int32[N_c^3], m uint8[3,N], u int8[3,N], ids, s, M, step,
+        vc float32[3, N_c^3] with the cell-mean velocity codec, else None)."""
         m = np.empty((3, self.n), dtype=np.uint8)
         u = np.empty((3, self.n), dtype=np.int8)
         counts = np.empty(self.n_cells, dtype=np.int32)
         ids = np.empty(self.n, dtype=np.uint32) if self.with_ids else None
+        vc = np.empty((3, self.n_cells), dtype=np.float32) if self.vel_codec else None
         v = StateView()
         v.n_particles = self.n
         v.n_cells = self.n_cells
         for k in range(3):
             v.m[k] = m[k].ctypes.data
             v.u[k] = u[k].ctypes.data
+            v.vc[k] = vc[k].ctypes.data if vc is not None else None
         v.counts = counts.ctypes.data
         v.ids = ids.ctypes.data if ids is not None else None
         v.on_device = 0
         check(self.lib.cube_get_state(self.ctx, ctypes.byref(v)))
-        return {"counts": counts, "m": m, "u": u, "ids": ids, "s": v.s_v, "M": v.max_u, "step": v.step}
+        return {"counts": counts, "m": m, "u": u, "ids": ids, "s": v.s_v, "M": v.max_u, "step": v.step,
+                "vc": vc}
 
-    def set_state(self, counts, m, u, s, M, ids=None, step=0):
+    def set_state(self, counts, m, u, s, M, ids=None, step=0, vc=None):
+        """vc: float32 (3, N_c^3) cell means, required with the cell-mean codec."""
         counts = np.ascontiguousarray(counts, dtype=np.int32)
         m = np.ascontiguousarray(m, dtype=np.uint8)
         u = np.ascontiguousarray(u, dtype=np.int8)
@@ -191,6 +200,11 @@ class CubeBox:
             v.ids = ids.ctypes.data
         else:
             v.ids = None
+        if vc is not None:
+            vc = np.ascontiguousarray(vc, dtype=np.float32)
+            keep.append(vc)
+            for k in range(3):
+                v.vc[k] = vc[k].ctypes.data
         v.s_v = float(s)
         v.max_u = int(M)
         v.on_device = 0

@@ -59,11 +59,11 @@ int ilog2(int v) {
 
 enum Stage {
     ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_R2C, ST_FFT_ZG, ST_FFT_C2R,
-    ST_GATHER, ST_SCAN, ST_COMPACT, NSTAGES
+    ST_GATHER, ST_SCAN, ST_COMPACT, ST_VENC, NSTAGES
 };
 const char* const kStageNames[NSTAGES] = {
     "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_r2c_xy", "fine_z_green",
-    "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact"};
+    "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact", "velocity_encode"};
 
 // HIP events around every launch of a stage, resolved at the next sync.
 struct Profiler {
@@ -182,6 +182,7 @@ struct cube_ctx {
     std::vector<std::pair<void*, size_t>> allocs;
 
     Planes A{}, B{};
+    VelCells vcell{};                 // cell-mean velocity codec: means and tan table
     uint8_t* dir = nullptr;
     uint32_t* far_key = nullptr;
     int32_t* counts = nullptr;
@@ -240,6 +241,9 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (d->fd_order != 0 && d->fd_order != 2 && d->fd_order != 4)
         return fail(CUBE_INVALID, "fd_order must be 2 or 4 (0 means 2)");
     g.fdr = d->fd_order == 4 ? 2 : 1;
+    if (d->vel_codec != CUBE_VEL_LINEAR && d->vel_codec != CUBE_VEL_CELL_MEAN)
+        return fail(CUBE_INVALID, "unknown vel_codec");
+    g.vcodec = d->vel_codec;
     if (!is_pow2(g.f) || !is_pow2(g.r) || g.r < 2 || g.r > 16 || g.r < g.f)
         return fail(CUBE_INVALID, "fine_per_spacing and coarse_ratio must be powers of two, 2 <= r <= 16, r >= f");
     const int64_t nfine = (int64_t)g.ns * g.f;
@@ -330,6 +334,11 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
     add(8 * (int64_t)g.F);
     add(8 * 64);
     add(8 * partial_len(g, batch));
+    if (g.vcodec) {
+        add(24 * n);                   // FP32 working velocities, two sets of planes
+        add(12 * g.ncells);            // cell means
+        add(8 * 255);                  // tan table
+    }
     auto r = [](int64_t bytes) { return (int64_t)round256((size_t)bytes); };
     const int64_t sortw = r((int64_t)sort_workspace_bytes(n));
     const int64_t t_green = r((int64_t)fine_green_workspace_bytes(g));
@@ -447,6 +456,7 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     a.fine_real = c->fine_real;
     a.coarse = c->coarse;
     a.sc = c->sc;
+    a.vcell = c->vcell;
     a.dt = c->desc.dt;
     a.tile0 = t0;
     a.ntiles = nt;
@@ -486,10 +496,14 @@ cube_status run_step(cube_ctx* c) {
     if (P.on) P.flush();
     if (c->sc_host->overflow)
         return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range: use CUBE_MIXED_BF16 or CUBE_FP32");
+    // with the cell-mean codec the kicked FP32 velocities move instead of codes
+    Planes src = c->B, dst = c->A;
+    if (g.vcodec)
+        for (int k = 0; k < 3; ++k) src.u[k] = dst.u[k] = nullptr;
     // the fast compaction's 16-bit counts and prefixes bound the old and new cell counts
     if (c->sc_host->far_count == 0 && c->max_count <= 65535 && c->sc_host->max_count <= 65535) {
         hipEvent_t ec = P.on ? P.mark(s) : nullptr;
-        launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, c->B, c->A, s);
+        launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, src, dst, s);
         // 6 B + move code read, 6 B written, old and new offsets read
         if (P.on) P.add(ST_COMPACT, ec, P.mark(s), 13.0 * (double)g.n + 8.0 * (double)g.ncells);
     } else {
@@ -503,11 +517,18 @@ cube_status run_step(cube_ctx* c) {
             return fail(CUBE_OOM, "general compaction: out of memory");
         launch_general_keys(g, c->offsets, c->dir, c->far_key, key, idx, s);
         stable_sort_pairs(key, idx, kt, it, g.n, ilog2((int)std::min<int64_t>(g.ncells, 1 << 30)) + 1, ws, s);
-        launch_permute_planes(idx, c->B, c->A, g.n, s);
+        launch_permute_planes(idx, src, dst, g.n, s);
         st = sync(c);
         if (st != CUBE_OK) return st;
     }
     launch_step_epilogue(c->sc, s);
+    if (g.vcodec) {
+        // re-encode against the new cells (sets sigma, max |u|, saturations)
+        hipEvent_t ev = P.on ? P.mark(s) : nullptr;
+        launch_vc_encode(g, c->offsets_new, c->A, c->vcell, c->sc, c->partial, s);
+        // FP32 velocities read twice, codes written, cell means written
+        if (P.on) P.add(ST_VENC, ev, P.mark(s), 27.0 * (double)g.n + 16.0 * (double)g.ncells);
+    }
     c->max_count = c->sc_host->max_count;
     c->max_block8 = c->sc_host->max_block8;
     std::swap(c->counts, c->counts_new);
@@ -574,6 +595,22 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
         CUBE_TRY(c->alloc_n(&c->A.ids, n));
         CUBE_TRY(c->alloc_n(&c->B.ids, n));
     }
+    double vtab_host[255];
+    if (g.vcodec) {
+        float* vp = nullptr;
+        CUBE_TRY(c->alloc_n(&vp, 6 * n));
+        float* vcp = nullptr;
+        CUBE_TRY(c->alloc_n(&vcp, 3 * g.ncells));
+        double* tab = nullptr;
+        CUBE_TRY(c->alloc_n(&tab, 255));
+        for (int k = 0; k < 3; ++k) {
+            c->A.v[k] = vp + k * n;
+            c->B.v[k] = vp + (3 + k) * n;
+            c->vcell.vc[k] = vcp + k * g.ncells;
+        }
+        c->vcell.tab = tab;
+        vc_table_host(vtab_host);
+    }
     CUBE_TRY(c->alloc_n(&c->dir, n));
     CUBE_TRY(c->alloc_n(&c->far_key, n));
     CUBE_TRY(c->alloc_n(&c->counts, g.ncells + 16));
@@ -615,6 +652,14 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s) != hipSuccess) {
         delete c;
         return fail(CUBE_DEVICE, "initial scalar copy failed");
+    }
+    if (g.vcodec) {
+        launch_fill_i32(reinterpret_cast<int32_t*>(c->vcell.vc[0]), 0, 3 * g.ncells, s);   // zero means
+        if (hipMemcpyAsync(const_cast<double*>(c->vcell.tab), vtab_host, sizeof(vtab_host), hipMemcpyHostToDevice,
+                           s) != hipSuccess) {
+            delete c;
+            return fail(CUBE_DEVICE, "velocity table copy failed");
+        }
     }
     build_coarse_green(g, c->coarse_green, s);
     build_fine_green(g, c->fine_green, gws, s);
@@ -691,6 +736,7 @@ cube_status cube_compress(cube_ctx* c, const float* pos, const float* vel, int64
     exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
     launch_max_block8(g, c->counts, &c->sc->max_block8, s);
     launch_scatter_compressed(g, idx, qp, dvel, s0, c->A, c->counts, c->sc, n, s);
+    if (g.vcodec) launch_vc_encode(g, c->offsets, c->A, c->vcell, c->sc, c->partial, s);
     hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s);
     st = sync(c);
     if (st != CUBE_OK) return st;
@@ -711,7 +757,7 @@ cube_status cube_decompress(cube_ctx* c, float* pos, float* vel, int64_t n, int3
     const size_t fb = (size_t)n * 3 * sizeof(float);
     Temp tmp(c->mem);
     if (!on_device && (!tmp.get(&dp, fb) || !tmp.get(&dv, fb))) return fail(CUBE_OOM, "decompress staging");
-    launch_decode(g, c->offsets, c->A, c->sc, dp, dv, s);
+    launch_decode(g, c->offsets, c->A, c->sc, c->vcell, dp, dv, s);
     if (!on_device) {
         hipMemcpyAsync(pos, dp, fb, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(vel, dv, fb, hipMemcpyDeviceToHost, s);
@@ -775,6 +821,9 @@ cube_status cube_get_state(cube_ctx* c, cube_state_view* v) {
     }
     if (v->counts) CUBE_HIP(hipMemcpyAsync(v->counts, c->counts, g.ncells * sizeof(int32_t), kind, s));
     if (v->ids && c->A.ids) CUBE_HIP(hipMemcpyAsync(v->ids, c->A.ids, g.n * sizeof(uint32_t), kind, s));
+    if (g.vcodec)
+        for (int k = 0; k < 3; ++k)
+            if (v->vc[k]) CUBE_HIP(hipMemcpyAsync(v->vc[k], c->vcell.vc[k], g.ncells * sizeof(float), kind, s));
     CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
     st = sync(c);
     if (st != CUBE_OK) return st;
@@ -791,8 +840,10 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
     if (!v || v->n_particles != g.n || v->n_cells != g.ncells || !v->counts)
         return fail(CUBE_INVALID, "state view size mismatch");
     if (!(v->s_v > 0.0) || v->max_u < 0 || v->max_u > 127) return fail(CUBE_INVALID, "bad velocity scale or max_u");
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k) {
         if (!v->m[k] || !v->u[k]) return fail(CUBE_INVALID, "missing planes");
+        if (g.vcodec && !v->vc[k]) return fail(CUBE_INVALID, "the cell-mean codec needs the cell means vc");
+    }
     hipStream_t s = c->stream;
     const hipMemcpyKind kind = v->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     for (int k = 0; k < 3; ++k) {
@@ -800,6 +851,9 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
         CUBE_HIP(hipMemcpyAsync(c->A.u[k], v->u[k], g.n, kind, s));
     }
     CUBE_HIP(hipMemcpyAsync(c->counts, v->counts, g.ncells * sizeof(int32_t), kind, s));
+    if (g.vcodec)
+        for (int k = 0; k < 3; ++k)
+            CUBE_HIP(hipMemcpyAsync(c->vcell.vc[k], v->vc[k], g.ncells * sizeof(float), kind, s));
     if (c->A.ids) {
         if (v->ids) CUBE_HIP(hipMemcpyAsync(c->A.ids, v->ids, g.n * sizeof(uint32_t), kind, s));
         else CUBE_HIP(hipMemsetAsync(c->A.ids, 0, g.n * sizeof(uint32_t), s));
@@ -840,7 +894,7 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
     hipStream_t s = c->stream;
     const int chunks = (int)(g.ncells / g.Tc);
     std::memset(out, 0, sizeof(*out));
-    launch_moments(g, c->offsets, c->A, c->sc, c->partial, chunks, s);
+    launch_moments(g, c->offsets, c->A, c->sc, c->vcell, c->partial, chunks, s);
     launch_reduce_partials(c->partial, chunks, 4, c->reduced, s);
     double mom[4];
     CUBE_HIP(hipMemcpyAsync(mom, c->reduced, sizeof(mom), hipMemcpyDeviceToHost, s));

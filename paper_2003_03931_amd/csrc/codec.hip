@@ -3,7 +3,9 @@
 // Positions: per axis the global quantum Q = floor(x * 256 / H) mod 256 N_c,
 // stored as the byte m = Q mod 256 in canonical cell order; decoding gives the
 // bin centre (Q + 1/2) H / 256, exact in FP32.  Velocities: one signed byte
-// per axis, u = clamp(rint(v / s), -127, 127) with a power-of-two scale s.
+// per axis, u = clamp(rint(v / s), -127, 127) with a power-of-two scale s, or
+// (cell-mean codec) the FP32 velocities are placed in cell order here and
+// encoded by vcodec.hip.
 #include "common.h"
 
 namespace cube {
@@ -53,17 +55,23 @@ __global__ void k_scatter_compressed(Geom g, const uint32_t* __restrict__ perm,
         out.m[0][j] = (uint8_t)(qp & 255);
         out.m[1][j] = (uint8_t)((qp >> 8) & 255);
         out.m[2][j] = (uint8_t)((qp >> 16) & 255);
+        if (out.v[0]) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double w = rint((double)vel[3 * (int64_t)src + k] / s_v);
-            sat += fabs(w) > 127.0;
-            w = fmin(fmax(w, -127.0), 127.0);
-            int u = (int)w;
-            umax = max(umax, abs(u));
-            out.u[k][j] = (int8_t)u;
+            for (int k = 0; k < 3; ++k) out.v[k][j] = vel[3 * (int64_t)src + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double w = rint((double)vel[3 * (int64_t)src + k] / s_v);
+                sat += fabs(w) > 127.0;
+                w = fmin(fmax(w, -127.0), 127.0);
+                int u = (int)w;
+                umax = max(umax, abs(u));
+                out.u[k][j] = (int8_t)u;
+            }
         }
         if (out.ids) out.ids[j] = src;
     }
+    if (out.v[0]) return;                    // codes are written by the cell-mean encoder
     sat = wave_sum(sat);
     umax = wave_max(umax);
     if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -74,7 +82,7 @@ __global__ void k_scatter_compressed(Geom g, const uint32_t* __restrict__ perm,
 
 // One block per chunk (x-row of cells in a tile).
 __global__ __launch_bounds__(256) void k_decode(Geom g, const int32_t* __restrict__ offsets, Planes in,
-                                                const StepScalars* __restrict__ sc,
+                                                const StepScalars* __restrict__ sc, VelCells vcell,
                                                 float* __restrict__ pos, float* __restrict__ vel) {
     extern __shared__ int offs[];
     const Chunk ch = chunk_of(g, blockIdx.x);
@@ -89,7 +97,9 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const int32_t* __restric
         for (int k = 0; k < 3; ++k) {
             const int q = c[k] * 256 + in.m[k][p];
             pos[3 * (int64_t)p + k] = ((float)q + 0.5f) * H256;
-            vel[3 * (int64_t)p + k] = (float)in.u[k][p] * s;
+            vel[3 * (int64_t)p + k] = g.vcodec
+                                          ? (float)vc_decode(vcell.vc[k][ch.c0 + j], sc->s, vcell.tab, in.u[k][p])
+                                          : (float)in.u[k][p] * s;
         }
     }
 }
@@ -118,11 +128,11 @@ void launch_scatter_compressed(const Geom& g, const uint32_t* perm, const uint32
                        s_v, out, sc, n);
 }
 
-void launch_decode(const Geom& g, const int32_t* offsets, Planes in, const StepScalars* sc, float* pos,
-                   float* vel, hipStream_t s) {
+void launch_decode(const Geom& g, const int32_t* offsets, Planes in, const StepScalars* sc,
+                   const VelCells& vcell, float* pos, float* vel, hipStream_t s) {
     const int64_t chunks = g.ncells / g.Tc;
     hipLaunchKernelGGL(k_decode, dim3((unsigned)chunks), dim3(256), (g.Tc + 1) * sizeof(int), s, g, offsets,
-                       in, sc, pos, vel);
+                       in, sc, vcell, pos, vel);
 }
 
 }  // namespace cube

@@ -168,3 +168,14 @@ __device__ __forceinline__ int64_t xcd_logical_block() {
 }
 
 }  // namespace cube
+
+namespace cube {
+
+// Eq. (3) decode of the cell-mean velocity codec: v_c + sigma tan(u pi / 255)
+// (table entry u + 127), in FP64 and in that order.  The byte -128, which no
+// encoder writes, reads as -127.
+__device__ __forceinline__ double vc_decode(float vc, double sigma, const double* tab, int u) {
+    return (double)vc + sigma * tab[max(u, -127) + 127];
+}
+
+}  // namespace cube

@@ -329,7 +329,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 dst.m[a][o] = src.m[a][p];
-                dst.u[a][o] = src.u[a][p];
+                if (src.u[0]) dst.u[a][o] = src.u[a][p];
+                if (src.v[0]) dst.v[a][o] = src.v[a][p];
             }
             if (dst.ids) dst.ids[o] = src.ids[p];
         }
@@ -414,9 +415,11 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     // copy run by run: consecutive slots are consecutive outputs
     const int total = s_run[nrow];
     constexpr int U = 4;
+    const bool cp_u = src.u[0] != nullptr, cp_v = src.v[0] != nullptr;
     for (int base = 0; base < total; base += kCThreads * U) {
         uint8_t mv[U][3];
         int8_t uv[U][3];
+        float vv[U][3];
         uint32_t idv[U];
         int ov[U];
 #pragma unroll
@@ -439,7 +442,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         mv[u][a] = src.m[a][p];
-                        uv[u][a] = src.u[a][p];
+                        if (cp_u) uv[u][a] = src.u[a][p];
+                        if (cp_v) vv[u][a] = src.v[a][p];
                     }
                     if (dst.ids) idv[u] = src.ids[p];
                 }
@@ -452,7 +456,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 dst.m[a][o] = mv[u][a];
-                dst.u[a][o] = uv[u][a];
+                if (cp_u) dst.u[a][o] = uv[u][a];
+                if (cp_v) dst.v[a][o] = vv[u][a];
             }
             if (dst.ids) dst.ids[o] = idv[u];
         }
@@ -491,7 +496,8 @@ __global__ void k_permute(const uint32_t* __restrict__ perm, Planes src, Planes 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         dst.m[a][j] = src.m[a][p];
-        dst.u[a][j] = src.u[a][p];
+        if (src.u[0]) dst.u[a][j] = src.u[a][p];
+        if (src.v[0]) dst.v[a][j] = src.v[a][p];
     }
     if (dst.ids) dst.ids[j] = src.ids[p];
 }

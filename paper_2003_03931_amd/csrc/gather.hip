@@ -117,7 +117,9 @@ __device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3
 // first wanted float has the parity of H (the buffer and the brick origin
 // are even), so odd H stages one extra float on the left and possibly one
 // past the row's end (the mesh allocation is padded for the last row).
-template <int MODE, int H, bool PER>
+// VC (step mode only): velocities in the cell-mean codec (Eq. (3)); the
+// kicked velocity is written to the FP32 working planes instead of codes.
+template <int MODE, int H, bool PER, bool VC = false>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     constexpr int kLX = Halo<H>::LX, kLY = Halo<H>::LY, kLZ = Halo<H>::LZ;
     constexpr int kSlack = H & 1;                  // floats staged before the wanted ones
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     __shared__ int s_hist[kMaxHist];
     __shared__ int s_scan[kGatherThreads / kWave + 1];
     __shared__ double s_red[kGatherThreads / kWave];
+    __shared__ float s_vc[3][VC ? kMaxRows * kMaxRowLen : 1];   // cell means of the brick's cells
 
     const Geom& g = A.g;
     const int r = g.r;
@@ -234,6 +237,14 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const int HX = BXc + 2, HY = BYc + 2, HZ = BZc + 2;
     if (MODE == GATHER_STEP)
         for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) s_hist[e] = 0;
+    if constexpr (VC) {
+        const int nbc = BXc * BYc * BZc;
+        for (int e = threadIdx.x; e < 3 * nbc; e += kGatherThreads) {
+            const int k3 = e / nbc, cl = e - k3 * nbc;
+            const int lx = cl % BXc, ly = (cl / BXc) % BYc, lz = cl / (BXc * BYc);
+            s_vc[k3][cl] = A.vcell.vc[k3][canon(g, gc[0] + lx, gc[1] + ly, gc[2] + lz)];
+        }
+    }
     __syncthreads();
     {
         const int row = threadIdx.x;
@@ -323,8 +334,24 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             for (int a = 0; a < 3; ++a) A.acc[3 * (int64_t)p + a] = acc[a];
             continue;
         }
-        // kick (FP64) and requantise; drift in cell-local quanta (exact FP64)
         int un[3], carry[3];
+        if constexpr (VC) {
+            // decode v_c + sigma tan(u pi / 255), kick in FP64 (one rounding per
+            // operation), hold in FP32, drift by it (exact FP64)
+            const int cl = (lcell[2] * BYc + lcell[1]) * BXc + lcell[0];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double v = vc_decode(s_vc[a][cl], s, A.vcell.tab, uo[a]);
+                const float v32 = (float)__dadd_rn(v, __dmul_rn((double)acc[a], dt));
+                A.out.v[a][p] = v32;
+                const double X = ((double)m[a] + 0.5) + ((double)v32 * q256H) * dt;
+                const int qq = (int)floor(X);
+                carry[a] = qq >> 8;
+                A.out.m[a][p] = (uint8_t)(qq & 255);
+                cmax = max(cmax, abs(carry[a]));
+            }
+        } else {
+        // kick (FP64) and requantise; drift in cell-local quanta (exact FP64)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double v = (double)uo[a] * s + (double)acc[a] * dt;
@@ -339,6 +366,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             A.out.m[a][p] = (uint8_t)(qq & 255);
             A.out.u[a][p] = (int8_t)un[a];
             cmax = max(cmax, abs(carry[a]));
+        }
         }
         if (A.out.ids) A.out.ids[p] = A.in.ids[p];
         const bool near = abs(carry[0]) <= 1 && abs(carry[1]) <= 1 && abs(carry[2]) <= 1;
@@ -421,7 +449,9 @@ bool gather_supported(const Geom& g) {
 
 template <int H, bool PER>
 void launch_gather_halo(const GatherArgs& a, const dim3& grid, hipStream_t s) {
-    if (a.mode == GATHER_STEP)
+    if (a.mode == GATHER_STEP && a.g.vcodec)
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER, true>), grid, dim3(kGatherThreads), 0, s, a);
+    else if (a.mode == GATHER_STEP)
         hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
     else if (a.mode == GATHER_FORCE)
         hipLaunchKernelGGL((k_gather<GATHER_FORCE, H, PER>), grid, dim3(kGatherThreads), 0, s, a);

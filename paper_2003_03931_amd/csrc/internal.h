@@ -29,6 +29,7 @@ struct Geom {
     int log2D;     // log2(512 / r): fine-coordinate fraction bits
     int periodic;  // 1 when the single tile is the periodic box
     int fdr;       // reach of the gradient stencil: 1 (2-point) or 2 (4-point)
+    int vcodec;    // velocity storage: 0 linear bytes, 1 cell means + Eq. (3) bytes
     int64_t ncells;   // Nc^3
     int64_t n;        // ns^3 particles
     int ntiles;       // nt^3
@@ -72,11 +73,21 @@ struct StepScalars {
     int32_t cmax_slot[64];
 };
 
-// Particle planes: m[3] uint8 then u[3] int8, each of capacity n.
+// Particle planes: m[3] uint8 then u[3] int8, each of capacity n; with the
+// cell-mean velocity codec also FP32 working velocities v[3] (else null).
+// Copies (compaction, permutation) move every non-null plane.
 struct Planes {
     uint8_t* m[3];
     int8_t* u[3];
     uint32_t* ids;   // may be null
+    float* v[3];     // may be null
+};
+
+// Cell-mean velocity codec state: FP32 mean velocity per axis and coarse cell
+// (canonical order) and the FP64 table tan(u pi / 255), u = -127..127.
+struct VelCells {
+    float* vc[3];
+    const double* tab;
 };
 
 // ---- scan.hip -----------------------------------------------------------
@@ -100,8 +111,17 @@ void launch_scatter_compressed(const Geom& g, const uint32_t* perm, const uint32
                                const float* vel, double s_v, Planes out, int32_t* counts,
                                StepScalars* sc, int64_t n, hipStream_t st);
 void launch_decode(const Geom& g, const int32_t* offsets, Planes in, const StepScalars* sc,
-                   float* pos, float* vel, hipStream_t s);
+                   const VelCells& vcell, float* pos, float* vel, hipStream_t s);
 void launch_count_keys(const uint32_t* key, int64_t n, int32_t* counts, hipStream_t s);
+
+// ---- vcodec.hip ---------------------------------------------------------
+// Cell-mean velocity codec (Eq. (3), Eq. (4)) on the FP32 velocities p.v of
+// a cell-ordered state: cell means into vcell.vc, sigma into sc->s, codes
+// into p.u; saturated components are added to sc->saturations and max |u|
+// replaces sc->max_u.  partial: ncells / Tc doubles of workspace.
+void vc_table_host(double* tab255);
+void launch_vc_encode(const Geom& g, const int32_t* offsets, Planes p, const VelCells& vcell,
+                      StepScalars* sc, double* partial, hipStream_t s);
 
 // ---- deposit.hip --------------------------------------------------------
 void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
@@ -165,6 +185,7 @@ struct GatherArgs {
     const float* fine_real;    // fine potentials of the batch: ntiles real F^3 meshes
     const float2* coarse;      // coarse potential (real part)
     StepScalars* sc;
+    VelCells vcell;         // GATHER_STEP with the cell-mean codec
     float* acc;             // GATHER_FORCE: [n][3]
     double* partial;        // GATHER_POTENTIAL: per-block partial sums
     float dt;
@@ -189,7 +210,7 @@ void launch_step_prologue(StepScalars* sc, float v_headroom, hipStream_t s);
 void launch_step_epilogue(StepScalars* sc, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,
-                    double* partial, int nblocks, hipStream_t s);
+                    const VelCells& vcell, double* partial, int nblocks, hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblocks, int width, double* out,
                             hipStream_t s);
 void launch_power_bins(const float2* dk, int n, int nbins, double* partial, int nparts,

@@ -51,18 +51,24 @@ __global__ void k_fill(int32_t* p, int32_t v, int64_t n) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-// per chunk: sum v_x, v_y, v_z, v^2 (v = u s) in FP64
+// per chunk: sum v_x, v_y, v_z, v^2 in FP64 (v = u s, or the cell-mean
+// decode v_c + sigma tan(u pi / 255))
 __global__ __launch_bounds__(256) void k_moments(Geom g, const int32_t* __restrict__ offsets, Planes p,
-                                                 const StepScalars* __restrict__ sc, double* __restrict__ partial) {
+                                                 const StepScalars* __restrict__ sc, VelCells vcell,
+                                                 double* __restrict__ partial) {
+    extern __shared__ int offs[];
     __shared__ double red[4][256 / kWave];
     const int64_t c0 = (int64_t)blockIdx.x * g.Tc;
-    const int lo = offsets[c0], hi = offsets[c0 + g.Tc];
+    for (int j = threadIdx.x; j <= g.Tc; j += blockDim.x) offs[j] = offsets[c0 + j];
+    __syncthreads();
+    const int lo = offs[0], hi = offs[g.Tc];
     const double s = sc->s;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const int64_t c = g.vcodec ? c0 + find_cell(offs, g.Tc, i) : 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double v = (double)p.u[k][i] * s;
+            const double v = g.vcodec ? vc_decode(vcell.vc[k][c], s, vcell.tab, p.u[k][i]) : (double)p.u[k][i] * s;
             a[k] += v;
             a[3] += v * v;
         }
@@ -144,9 +150,10 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, v, n);
 }
 
-void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc, double* partial,
-                    int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_moments, dim3(nblocks), dim3(256), 0, s, g, offsets, p, sc, partial);
+void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,
+                    const VelCells& vcell, double* partial, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, dim3(nblocks), dim3(256), (g.Tc + 1) * sizeof(int), s, g, offsets, p, sc, vcell,
+                       partial);
 }
 
 void launch_reduce_partials(const double* partial, int nblocks, int width, double* out, hipStream_t s) {

@@ -56,6 +56,9 @@ def test_invalid_descriptor_is_rejected_without_a_gpu():
     bad4 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 0, 0, 0, 3)     # fd_order 3
     assert lib.cube_init(ctypes.byref(bad4), None, None, ctypes.byref(ctx)) == 1
     assert b"fd_order" in lib.cube_last_error()
+    bad5 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 0, 0, 0, 2, 2)  # vel_codec 2
+    assert lib.cube_init(ctypes.byref(bad5), None, None, ctypes.byref(ctx)) == 1
+    assert b"vel_codec" in lib.cube_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
@@ -91,6 +94,11 @@ def test_footprint_is_host_only_and_grows_with_the_batch():
     bad = BoxDesc(32, 1, 2, 3, 0, 12, 0.05, 2.0, 0, 0, 0, 0)
     a, b = ctypes.c_int64(), ctypes.c_int64()
     assert lib.cube_footprint(ctypes.byref(bad), ctypes.byref(a), ctypes.byref(b)) == 1
+    # the cell-mean velocity codec adds 24 B per particle of working planes,
+    # 12 B per coarse cell and the table
+    p_vc, _ = footprint(spec.with_(vel_codec=1), tiles_per_batch=1)
+    n_cells = (64 * 2 // 4) ** 3
+    assert p_vc - p1 >= 24 * n + 12 * n_cells
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
