@@ -148,6 +148,8 @@ def main():
                     help="bytes of a plain device copy to run first (counter calibration)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed steps of each mixed-precision run (0 skips them)")
+    ap.add_argument("--vcodec-steps", type=int, default=10,
+                    help="timed steps with the cell-mean velocity codec (0 skips them)")
     ap.add_argument("--serving", type=int, default=40, help="requests of the serving run (0 skips it)")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--batched", type=int, default=0,
@@ -226,6 +228,29 @@ def main():
         mixed[prec] = {"value": n * args.mixed_steps / el, "ms_per_step": 1e3 * el / args.mixed_steps,
                        "steps": args.mixed_steps}
         log(f"{prec}: {1e3 * el / args.mixed_steps:.1f} ms/step")
+
+    # the same input with Eq. (3)'s cell-mean velocity codec (FP32 meshes)
+    vcodec = None
+    if args.vcodec_steps > 0:
+        vb = CubeBox(spec.with_(vel_codec=1), tiles_per_batch=args.tiles_per_batch, allocator=args.allocator)
+        vb.compress(pos, vel)
+        vb.step(1)
+        vb.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        vb.step(args.vcodec_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        vst = {st["name"]: st["total_ms"] / args.vcodec_steps for st in vb.profile_read() if st["launches"]}
+        vdiag = vb.diagnostics()
+        vb.close()
+        del vb
+        torch.cuda.empty_cache()
+        vcodec = {"value": n * args.vcodec_steps / el, "ms_per_step": 1e3 * el / args.vcodec_steps,
+                  "steps": args.vcodec_steps, "velocity_encode_ms": vst.get("velocity_encode"),
+                  "compact_ms": vst.get("compact"), "gather_kick_drift_ms": vst.get("gather_kick_drift"),
+                  "sigma": vdiag["s"], "saturations": vdiag["saturations"]}
+        log(f"cell-mean velocity codec: {1e3 * el / args.vcodec_steps:.1f} ms/step")
     del pos, vel
 
     serving = None
@@ -302,6 +327,7 @@ def main():
         },
         "cpu_baseline": base,
         "mixed": mixed,
+        "vel_codec_cell_mean": vcodec,
         "serving": serving,
         "batched": batched,
         "diagnostics": {"mass": diag["mass"], "max_carry": diag["max_carry"], "max_u": diag["max_u"],

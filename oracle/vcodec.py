@@ -13,7 +13,7 @@ form of the map only through its reference):
       storage order, divided by the count, and kept as FP32 (one value per
       axis and coarse cell); an empty cell has v_c = 0.
 * V2  deviation dv = v - v_c.  Decode: dv = sigma tan(u pi / 255) for
-      u in [-127, 127].  Encode: u = clamp(rint(atan~(dv / sigma) 255 / pi)),
+      u in [-127, 127].  Encode: u = clamp(rint(atan~(dv / sigma) * (255 / pi))),
       atan~ the Eq. (4) approximation; |atan~ - atan| <= 0.0038 rad is below
       half a code's angle pi / 510, so every code decodes and re-encodes to
       itself.  Eq. (4) stays below pi / 2, so the code never leaves the
@@ -39,6 +39,7 @@ import numpy as np
 from .codec import pow2ceil
 
 ANGLE = np.pi / 255.0          # angle of one code step
+CODES_PER_RADIAN = 255.0 / np.pi
 CODE_MAX = 127
 
 
@@ -67,7 +68,7 @@ def encode_deviation(dv, sigma: float):
     last code's value."""
     dv = np.asarray(dv, dtype=np.float64)
     t = fast_atan(dv / sigma)
-    w = np.rint(t / ANGLE)
+    w = np.rint(t * CODES_PER_RADIAN)
     sat = int(np.count_nonzero(np.abs(dv) > sigma * np.tan(CODE_MAX * ANGLE)))
     return np.clip(w, -CODE_MAX, CODE_MAX).astype(np.int8), sat
 

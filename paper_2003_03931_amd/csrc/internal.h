@@ -118,8 +118,9 @@ void launch_count_keys(const uint32_t* key, int64_t n, int32_t* counts, hipStrea
 // Cell-mean velocity codec (Eq. (3), Eq. (4)) on the FP32 velocities p.v of
 // a cell-ordered state: cell means into vcell.vc, sigma into sc->s, codes
 // into p.u; saturated components are added to sc->saturations and max |u|
-// replaces sc->max_u.  partial: ncells / Tc doubles of workspace.
+// replaces sc->max_u.  partial: vc_partials(g) doubles of workspace.
 void vc_table_host(double* tab255);
+int vc_partials(const Geom& g);
 void launch_vc_encode(const Geom& g, const int32_t* offsets, Planes p, const VelCells& vcell,
                       StepScalars* sc, double* partial, hipStream_t s);
 
