@@ -291,6 +291,28 @@ def main():
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     value = n * args.steps / elapsed
+    # whole-step HBM figures: algorithmic bytes (library profiler), measured
+    # bytes (calibrated rocprofv3 counters from profiles/, when they match the
+    # kernels) and the floor of the method (every fine and coarse half spectrum
+    # crossing HBM four times in FP32, the 12 bytes of each particle's state
+    # read and written once)
+    step_s = elapsed / args.steps
+    alg_gb = sum(s["bytes"] for s in stages) / args.steps / 1e9
+    traffic = {s["name"]: lookup_traffic(s["name"], spec.name) for s in stages if s["launches"]}
+    meas_gb = None
+    if traffic and all(v is not None for v in traffic.values()):
+        meas_gb = sum(traffic[s["name"]] * s["launches"] / args.steps for s in stages if s["launches"]) / 1e9
+    ntiles = spec.tiles_per_dim ** 3
+    floor_gb = (ntiles * 4 * 8 * F * F * (F // 2 + 1) + 4 * 8 * n_coarse ** 2 * (n_coarse // 2 + 1) + 12 * n) / 1e9
+    hbm = {
+        "peak_gbs": HBM_PEAK_GBS,
+        "algorithmic_gb_per_step": alg_gb,
+        "algorithmic_frac": alg_gb / step_s / HBM_PEAK_GBS,
+        "measured_gb_per_step": meas_gb,
+        "measured_frac": None if meas_gb is None else meas_gb / step_s / HBM_PEAK_GBS,
+        "floor_gb_per_step": floor_gb,
+        "effective_frac": floor_gb / step_s / HBM_PEAK_GBS,
+    }
     out = {
         "metric": METRIC,
         "value": value,
@@ -325,6 +347,7 @@ def main():
             "avg_launch_ms": avg_ms,
             "bytes_per_launch": bytes_per_launch,
         },
+        "hbm_step": hbm,
         "cpu_baseline": base,
         "mixed": mixed,
         "vel_codec_cell_mean": vcodec,
