@@ -85,12 +85,14 @@ def test_fp16_falls_back_to_fp32_for_dense_cells():
 
 
 # ------------------------------------------------------------ allocator
-def test_allocator_holds_exactly_the_footprint():
-    from paper_2003_03931_amd import footprint
-    spec = config("t4")
+@pytest.mark.parametrize("vel_codec", [0, 1])
+def test_allocator_holds_exactly_the_footprint(vel_codec):
+    from paper_2003_03931_amd import CubeBox, footprint
+    _need_gpu()
+    spec = config("t4").with_(vel_codec=vel_codec)
     pers, trans = footprint(spec, tiles_per_batch=5)
     pos, vel = ics("t4")
-    with _box("t4", tiles_per_batch=5) as g:
+    with CubeBox(spec, tiles_per_batch=5) as g:
         al = g.allocator
         assert al.live_bytes() == pers
         g.compress(pos, vel)
