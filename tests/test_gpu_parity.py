@@ -292,3 +292,30 @@ def test_diagnostics_match_oracle(name):
     assert np.max(np.abs(d["momentum"] - mo["momentum"])) <= 1e-12 * scale * np.sqrt(ref.n)
     assert abs(d["kinetic"] / mo["kinetic"] - 1.0) <= 1e-13
     assert abs(d["potential"] / w - 1.0) <= 1e-5
+
+
+def test_saturating_kick_matches_oracle():
+    """A state at rest with a tiny velocity scale (M = 0 keeps it): the first
+    kick overflows most codes, which clamp to +-127 and are counted (R6, R7,
+    R17) exactly as in the oracle."""
+    from oracle import codec, pm, step
+    box, ref = oracle_state("t4")
+    rest = codec.State(box, ref.counts.copy(), ref.m.copy(), np.zeros_like(ref.u), 2.0 ** -14, 0,
+                       ref.ids.copy(), 0, 0)
+    o, info = step.step(pm.Solver(box), rest, workers=1, return_info=True)
+    assert info["saturations"] > ref.n                  # most components clamp
+    with gpu_box("t4") as g:
+        load_state(g, rest)
+        g.step(1)
+        st = g.get_state()
+        dg = g.diagnostics()
+    assert st["s"] == o.s == 2.0 ** -14
+    assert abs(dg["saturations"] - info["saturations"]) <= 1e-4 * info["saturations"]
+    ug = np.empty((ref.n, 3), np.int64)
+    ug[st["ids"]] = st["u"].T
+    uo = np.empty((ref.n, 3), np.int64)
+    uo[o.ids] = o.u.T
+    assert np.mean(ug == uo) >= 0.999
+    assert np.abs(ug).max() == 127 and dg["max_u"] == 127
+    d = _compare_by_id(box, st, o)
+    assert np.mean(d == 0) >= 0.999 and d.max() <= 1
