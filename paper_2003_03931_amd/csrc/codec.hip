@@ -76,7 +76,9 @@ __global__ void k_scatter_compressed(Geom g, const uint32_t* __restrict__ perm,
     umax = wave_max(umax);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         if (sat) atomicAdd((unsigned long long*)&sc->saturations, (unsigned long long)sat);
-        atomicMax(&sc->max_u, umax);
+        // one address for the whole grid: skip the atomic when the (monotone)
+        // maximum already covers this wave
+        if (umax > *(volatile int32_t*)&sc->max_u) atomicMax(&sc->max_u, umax);
     }
 }
 

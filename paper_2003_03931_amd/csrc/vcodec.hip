@@ -146,7 +146,9 @@ __global__ __launch_bounds__(kCells) void k_vc_encode(Geom g, const int32_t* __r
     umax = wave_max(umax);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         if (sat) atomicAdd((unsigned long long*)&sc->saturations, (unsigned long long)sat);
-        if (umax) atomicMax(&sc->max_u, umax);
+        // the maximum only grows: skip the atomic (one address for the whole
+        // grid) when the value already there is at least this wave's
+        if (umax > *(volatile int32_t*)&sc->max_u) atomicMax(&sc->max_u, umax);
     }
 }
 
