@@ -158,6 +158,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     // potential with halo, row offsets) is issued before the first wait: one
     // memory latency per block instead of one per round.
     const int CX = BXc + 2 * H, CY = BYc + 2 * H, CZ = BZc + 2 * H;
+    // the coarse grid is laid out with the strides of the largest brick
+    // (r = kMinR), constants the LDS reads fold into their offsets
+    constexpr int kCSX = kBX / kMinR + 2 * H, kCSXY = kCSX * (kBY / kMinR + 2 * H);
     const float* cmesh = reinterpret_cast<const float*>(A.coarse);
     const int Nc = g.Nc, cx0 = gc[0] - H, cy0 = gc[1] - H, cz0 = gc[2] - H;
     const int ncoarse = CX * CY * CZ, nrowoff = nrows * (BXc + 1);
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     using FV = typename std::conditional<PER, float, f2>::type;
     FV fv[UF];
     float cv[UC];
+    int cl[UC];
     int rv[UR];
     const int ox_al = ox - kSlack;                 // even
     const int a_off = PER ? 0 : kSlack;            // first wanted float within the staged row
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         if (e < ncoarse) {
             const int ez = (int)(((float)e + 0.5f) * inv_cxy), rem = e - ez * (CX * CY);
             const int ey = (int)(((float)rem + 0.5f) * inv_cx), ex = rem - ey * CX;
+            cl[u] = ez * kCSXY + ey * kCSX + ex;
             int cx = cx0 + ex, cy = cy0 + ey, cz = cz0 + ez;
             cx = cx < 0 ? cx + Nc : (cx >= Nc ? cx - Nc : cx);
             cy = cy < 0 ? cy + Nc : (cy >= Nc ? cy - Nc : cy);
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
         const int e = threadIdx.x + u * kGatherThreads;
-        if (e < ncoarse) s_coarse[e] = cv[u];
+        if (e < ncoarse) s_coarse[cl[u]] = cv[u];
     }
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     __syncthreads();
 
     const LdsGrid fphi{s_fine + a_off, kSX, kSX * kLY};
-    const LdsGrid cphi{s_coarse, CX, CX * CY};
+    const LdsGrid cphi{s_coarse, kCSX, kCSXY};
     const int D = 1 << g.log2D, halfD = D >> 1;
     const float invD = 1.0f / (float)D;
     constexpr int R = H - 1;                                 // difference reach

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __res
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
     if (max_out) {
         mx = wave_max(mx);
-        if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_out, mx);
+        // one address for the whole grid: skip atomics the maximum already covers
+        if ((threadIdx.x & (kWave - 1)) == 0 && mx > *(volatile int32_t*)max_out) atomicMax(max_out, mx);
     }
 }
 
@@ -110,7 +111,8 @@ __global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __re
     if (threadIdx.x == 0) out[n] = total;
     if (max_out) {
         mx = wave_max(mx);
-        if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_out, mx);
+        // one address for the whole grid: skip atomics the maximum already covers
+        if ((threadIdx.x & (kWave - 1)) == 0 && mx > *(volatile int32_t*)max_out) atomicMax(max_out, mx);
     }
 }
 
