@@ -40,6 +40,10 @@ class BoxSpec:
     steps: int
     fd_order: int = 2      # 2- or 4-point central-difference gradients
     vel_codec: int = 0     # 0 linear velocity bytes, 1 cell means + companded bytes
+    comoving: int = 0      # 1: expanding background; dt is then the step in the scale factor
+    omega_m: float = 1.0   # matter density parameter (comoving runs)
+    omega_l: float = 0.0   # cosmological-constant density parameter (comoving runs)
+    a_start: float = 1.0   # scale factor of the initial state (comoving runs)
 
     def with_(self, **kw):
         return replace(self, **kw)

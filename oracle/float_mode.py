@@ -67,3 +67,17 @@ def leapfrog(solver, pos, vel_half, dt: float, nsteps: int, callback=None):
         if callback is not None:
             callback(i + 1, x, v)
     return x, v
+
+
+def leapfrog_comoving(solver, pos, p_half, box, nsteps: int, step0: int = 0):
+    """KD leapfrog in the scale factor (cosmo.py C3) from (x at a_step0,
+    p at a_step0 - da/2); returns the final (x, p)."""
+    from . import cosmo
+    L = float(solver.box.n_side)
+    x = np.array(pos, dtype=np.float64)
+    p = np.array(p_half, dtype=np.float64)
+    for i in range(step0, step0 + nsteps):
+        K, D = cosmo.step_factors(box, i)
+        p = p + solver.forces(x) * K
+        x = np.mod(x + p * D, L)
+    return x, p

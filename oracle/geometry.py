@@ -26,13 +26,19 @@ class Box:
     v_headroom: float = 2.0
     fd_order: int = 2                 # R13: 2- or 4-point gradient on both meshes
     vel_codec: int = 0                # 0: linear bytes (R6); 1: cell means + Eq. (3) bytes (V1-V4)
+    comoving: int = 0                 # 1: expanding background, dt is the step in a (C1-C4)
+    omega_m: float = 1.0
+    omega_l: float = 0.0
+    a_start: float = 1.0
 
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.n_side, spec.tiles_per_dim, spec.fine_per_spacing,
                    spec.coarse_ratio, spec.buffer_fine, spec.r_cut_fine,
                    float(spec.dt), float(spec.v_headroom), int(getattr(spec, "fd_order", 2)),
-                   int(getattr(spec, "vel_codec", 0)))
+                   int(getattr(spec, "vel_codec", 0)), int(getattr(spec, "comoving", 0)),
+                   float(getattr(spec, "omega_m", 1.0)), float(getattr(spec, "omega_l", 0.0)),
+                   float(getattr(spec, "a_start", 1.0)))
 
     # ---- derived sizes -------------------------------------------------
     @property
@@ -82,6 +88,9 @@ class Box:
         assert self.T % r == 0 and b % r == 0
         assert self.fd_order in (2, 4)
         assert self.vel_codec in (0, 1)
+        assert self.comoving in (0, 1)
+        if self.comoving:
+            assert self.omega_m > 0.0 and self.a_start > 0.0
         if self.tiles_per_dim == 1:
             assert b == 0 and 2 * a < self.F
         else:

@@ -24,6 +24,9 @@ FP32; the drift moves by that velocity (X = m + 1/2 + v' (256 / H) dt, exact
 in FP64), and after the stable reordering the velocities are re-encoded
 against the new cells' means.
 
+In a comoving box (cosmo.py) the same steps run with the kick multiplier
+K_n and the FP32 drift multiplier D_n of the step in place of dt.
+
 Pins: the dynamics tests (Zel'dovich plane wave, leapfrog order) exercise the
 same kick/drift through the float-state twin in float_mode.py; the compaction
 is pinned by brute force (tests/test_oracle_step.py).
@@ -31,13 +34,21 @@ is pinned by brute force (tests/test_oracle_step.py).
 
 import numpy as np
 
-from . import codec
+from . import codec, cosmo
 from .pm import Solver
+
+
+def factors(box, state):
+    """(kick, drift) multipliers of a step: dt and dt in a static box; the
+    comoving K_n and FP32 D_n otherwise (cosmo.py, C3-C4)."""
+    if box.comoving:
+        return cosmo.step_factors(box, state.step)
+    return box.dt, box.dt
 
 
 def kick(box, state, acc):
     s_new = codec.next_velocity_scale(box, state.s, state.M)
-    v = state.u.T.astype(np.float64) * state.s + acc * box.dt
+    v = state.u.T.astype(np.float64) * state.s + acc * factors(box, state)[0]
     w = np.rint(v / s_new)
     sat = int(np.count_nonzero(np.abs(w) > 127.0))
     u_new = np.clip(w, -127.0, 127.0).astype(np.int64)       # (N, 3)
@@ -48,7 +59,7 @@ def kick(box, state, acc):
 def drift(box, state, u_new, s_new):
     """New global quanta (N, 3) and the per-particle carries."""
     m = state.m.T.astype(np.float64)                          # (N, 3)
-    D = (u_new.astype(np.float64) * s_new) * (256.0 / box.H) * box.dt
+    D = (u_new.astype(np.float64) * s_new) * (256.0 / box.H) * factors(box, state)[1]
     X = (m + 0.5) + D
     q = np.floor(X).astype(np.int64)
     carry = np.floor_divide(q, 256)
@@ -61,13 +72,13 @@ def drift(box, state, u_new, s_new):
 
 def kick_cell_mean(box, state, acc):
     """V4: decoded velocity plus a dt, held in FP32 (N, 3)."""
-    return (state.velocities() + acc * box.dt).astype(np.float32)
+    return (state.velocities() + acc * factors(box, state)[0]).astype(np.float32)
 
 
 def drift_velocity(box, state, v32):
     """Drift by FP32 velocities in cell-local quanta (exact in FP64)."""
     m = state.m.T.astype(np.float64)
-    X = (m + 0.5) + v32.astype(np.float64) * (256.0 / box.H) * box.dt
+    X = (m + 0.5) + v32.astype(np.float64) * (256.0 / box.H) * factors(box, state)[1]
     q = np.floor(X).astype(np.int64)
     carry = np.floor_divide(q, 256)
     cell_new = np.mod(state.quanta() // 256 + carry, box.n_coarse)
