@@ -110,6 +110,17 @@ typedef enum {
  *                     (8 (phi(c+1) - phi(c-1)) - (phi(c+2) - phi(c-2))) / 12h;
  *                     0 means 2, anything else is CUBE_INVALID.
  *   vel_codec         cube_vel_codec (0 = linear bytes, the default).
+ *   comoving          0: static background, dt is the time step.  1: expanding
+ *                     background (the paper's LambdaCDM setting, Sec. IV):
+ *                     positions comoving, velocities the canonical momentum
+ *                     p = a^2 dx/dt (time in 1/H0), dt the step in the scale
+ *                     factor a, step n at a = a_start + n dt.  A step kicks by
+ *                     the force times (3/2) omega_m int da / (a^2 H) over
+ *                     [a - dt/2, a + dt/2] and drifts by p times
+ *                     int da / (a^3 H) over [a, a + dt] (rounded to FP32),
+ *                     H = sqrt(omega_m a^-3 + (1 - omega_m - omega_l) a^-2 + omega_l).
+ *   omega_m, omega_l  density parameters (comoving only; omega_m > 0).
+ *   a_start           scale factor of the state at step 0 (comoving only; > 0).
  * Derived: coarse cells per side N_c = n_side f / r, tile side T = n_side f / n_t
  * fine cells, tile FFT box F = T + 2b; every FFT side must factor into 2,3,5,7.
  */
@@ -127,6 +138,10 @@ typedef struct {
     int32_t tiles_per_batch;
     int32_t fd_order;
     int32_t vel_codec;
+    int32_t comoving;
+    float omega_m;
+    float omega_l;
+    float a_start;
 } cube_box_desc;
 
 typedef struct cube_ctx cube_ctx;

@@ -36,6 +36,10 @@ class BoxDesc(ctypes.Structure):
         ("tiles_per_batch", ctypes.c_int32),
         ("fd_order", ctypes.c_int32),
         ("vel_codec", ctypes.c_int32),
+        ("comoving", ctypes.c_int32),
+        ("omega_m", ctypes.c_float),
+        ("omega_l", ctypes.c_float),
+        ("a_start", ctypes.c_float),
     ]
 
 

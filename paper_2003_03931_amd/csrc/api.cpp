@@ -51,6 +51,55 @@ namespace {
     } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// 32-point Gauss-Legendre rule on [-1, 1]: Newton's method on the Legendre
+// polynomial from the usual cosine guesses.
+struct GaussLegendre32 {
+    double x[32], w[32];
+    GaussLegendre32() {
+        const int n = 32;
+        for (int i = 0; i < n / 2; ++i) {
+            double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+            for (int it = 0; it < 100; ++it) {
+                double p1 = 1.0, p0 = 0.0;
+                for (int j = 1; j <= n; ++j) {
+                    const double pm = p0;
+                    p0 = p1;
+                    p1 = ((2.0 * j - 1.0) * z * p0 - (j - 1.0) * pm) / j;
+                }
+                dp = n * (z * p1 - p0) / (z * z - 1.0);
+                const double dz = p1 / dp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-16) break;
+            }
+            x[i] = -z;
+            x[n - 1 - i] = z;
+            w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+};
+
+// Expanding background: H(a) in units of H0, and the step's kick multiplier
+// (3/2) Omega_m int da / (a^2 H) over [a - da/2, a + da/2] and drift
+// multiplier int da / (a^3 H) over [a, a + da], rounded to FP32.
+double hubble(double a, double om, double ol) { return std::sqrt(om / (a * a * a) + (1.0 - om - ol) / (a * a) + ol); }
+
+void comoving_factors(const cube_box_desc& d, int64_t step, double* kick, float* drift) {
+    static const GaussLegendre32 gl;
+    const double om = d.omega_m, ol = d.omega_l, da = d.dt;
+    const double a = (double)d.a_start + (double)step * da;
+    auto integrate = [&](double a1, double a2, int power) {
+        const double half = 0.5 * (a2 - a1), mid = 0.5 * (a2 + a1);
+        double sum = 0.0;
+        for (int i = 0; i < 32; ++i) {
+            const double t = mid + half * gl.x[i];
+            sum += gl.w[i] / (std::pow(t, power) * hubble(t, om, ol));
+        }
+        return half * sum;
+    };
+    *kick = 1.5 * om * integrate(a - 0.5 * da, a + 0.5 * da, 2);
+    *drift = (float)integrate(a, a + da, 3);
+}
 int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
@@ -244,6 +293,10 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (d->vel_codec != CUBE_VEL_LINEAR && d->vel_codec != CUBE_VEL_CELL_MEAN)
         return fail(CUBE_INVALID, "unknown vel_codec");
     g.vcodec = d->vel_codec;
+    if (d->comoving != 0 && d->comoving != 1) return fail(CUBE_INVALID, "comoving must be 0 or 1");
+    if (d->comoving && !(d->omega_m > 0.0f && d->omega_l >= 0.0f && d->a_start > 0.0f &&
+                         hubble(d->a_start, d->omega_m, d->omega_l) > 0.0))
+        return fail(CUBE_INVALID, "comoving needs omega_m > 0, omega_l >= 0, a_start > 0 and H(a_start) > 0");
     if (!is_pow2(g.f) || !is_pow2(g.r) || g.r < 2 || g.r > 16 || g.r < g.f)
         return fail(CUBE_INVALID, "fine_per_spacing and coarse_ratio must be powers of two, 2 <= r <= 16, r >= f");
     const int64_t nfine = (int64_t)g.ns * g.f;
@@ -457,7 +510,9 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     a.coarse = c->coarse;
     a.sc = c->sc;
     a.vcell = c->vcell;
-    a.dt = c->desc.dt;
+    a.kick = (double)c->desc.dt;
+    a.drift = c->desc.dt;
+    if (c->desc.comoving) comoving_factors(c->desc, c->step, &a.kick, &a.drift);
     a.tile0 = t0;
     a.ntiles = nt;
     a.mode = mode;

@@ -12,13 +12,15 @@
 //   * a = CIC-gather of -grad phi_f + CIC-gather of -grad phi_c, gradients by
 //     2- or 4-point central differences taken on the fly from the LDS
 //     potentials;
-//   * kick in FP64:  u' = clamp(rint((u s + a dt) / s'), -127, 127);
+//   * kick in FP64:  u' = clamp(rint((u s + a K) / s'), -127, 127);
 //   * drift in cell-local quanta, exactly in FP64:
-//       X = m + 1/2 + ((u' s') (256/H)) dt,  q = floor(X),
+//       X = m + 1/2 + ((u' s') (256/H)) D,  q = floor(X),
 //       carry = floor(q / 256), m' = q mod 256, cell' = cell + carry (periodic);
 //   * write (m', u') at the same index of the second particle buffer and a
 //     move code for the compaction; new-cell counts go to an LDS histogram
 //     over the brick's cells plus one cell, flushed once per brick.
+// K and D are the step's kick and drift multipliers: dt and dt in a static
+// box, the comoving integrals (D rounded to FP32) in an expanding one.
 #include <type_traits>
 
 #include "common.h"
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         inv_s_next = 1.0 / s_next;                           // exact: s' is a power of two
     }
     const double q256H = 256.0 * g.f / r;                    // 256 / H
-    const double dt = (double)A.dt;
+    const double kick = A.kick, drift = (double)A.drift;
 
     int umax = 0, sat = 0, cmax = 0, nfar = 0;
     double esum = 0.0;
@@ -347,9 +349,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double v = vc_decode(s_vc[a][cl], s, A.vcell.tab, uo[a]);
-                const float v32 = (float)__dadd_rn(v, __dmul_rn((double)acc[a], dt));
+                const float v32 = (float)__dadd_rn(v, __dmul_rn((double)acc[a], kick));
                 A.out.v[a][p] = v32;
-                const double X = ((double)m[a] + 0.5) + ((double)v32 * q256H) * dt;
+                const double X = ((double)m[a] + 0.5) + ((double)v32 * q256H) * drift;
                 const int qq = (int)floor(X);
                 carry[a] = qq >> 8;
                 A.out.m[a][p] = (uint8_t)(qq & 255);
@@ -359,13 +361,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         // kick (FP64) and requantise; drift in cell-local quanta (exact FP64)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double v = (double)uo[a] * s + (double)acc[a] * dt;
+            const double v = (double)uo[a] * s + (double)acc[a] * kick;
             double w = rint(v * inv_s_next);
             sat += fabs(w) > 127.0;
             w = fmin(fmax(w, -127.0), 127.0);
             un[a] = (int)w;
             umax = max(umax, abs(un[a]));
-            const double X = ((double)m[a] + 0.5) + (((double)un[a] * s_next) * q256H) * dt;
+            const double X = ((double)m[a] + 0.5) + (((double)un[a] * s_next) * q256H) * drift;
             const int qq = (int)floor(X);
             carry[a] = qq >> 8;                  // floor division by 256
             A.out.m[a][p] = (uint8_t)(qq & 255);

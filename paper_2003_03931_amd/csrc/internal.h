@@ -189,7 +189,8 @@ struct GatherArgs {
     VelCells vcell;         // GATHER_STEP with the cell-mean codec
     float* acc;             // GATHER_FORCE: [n][3]
     double* partial;        // GATHER_POTENTIAL: per-block partial sums
-    float dt;
+    double kick;            // GATHER_STEP: force multiplier of the kick (dt, or K_n comoving)
+    float drift;            // GATHER_STEP: velocity multiplier of the drift (dt, or FP32 D_n)
     int tile0;
     int ntiles;
     int mode;

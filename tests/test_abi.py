@@ -59,6 +59,13 @@ def test_invalid_descriptor_is_rejected_without_a_gpu():
     bad5 = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 0, 0, 0, 2, 2)  # vel_codec 2
     assert lib.cube_init(ctypes.byref(bad5), None, None, ctypes.byref(ctx)) == 1
     assert b"vel_codec" in lib.cube_last_error()
+    p, t = ctypes.c_int64(), ctypes.c_int64()
+    for om, ol, a0, ok in ((0.3, 0.7, 0.01, True), (0.0, 0.7, 0.01, False), (0.3, 0.7, 0.0, False),
+                           (0.3, -0.1, 0.5, False)):
+        d = BoxDesc(32, 1, 2, 4, 0, 12, 0.001, 2.0, 0, 0, 0, 2, 0, 1, om, ol, a0)
+        assert (lib.cube_footprint(ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)) == 0) == ok, (om, ol, a0)
+        if not ok:
+            assert b"comoving" in lib.cube_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
