@@ -35,9 +35,11 @@ def test_lcdm_factors_against_adaptive_quadrature(om, ol):
 def test_step_factors_round_the_drift_to_fp32():
     box = Box.from_spec(config("t4").with_(comoving=1, omega_m=0.3, omega_l=0.7, a_start=0.05, dt=0.0025))
     K, D = cosmo.step_factors(box, 3)
-    a = 0.05 + 3 * box.dt
-    assert D == float(np.float32(cosmo.drift_factor(a, a + box.dt, 0.3, 0.7)))
-    assert K == cosmo.kick_factor(a - box.dt / 2, a + box.dt / 2, 0.3, 0.7)
+    om, ol = box.omega_m, box.omega_l
+    assert (om, ol, box.a_start) == tuple(float(np.float32(v)) for v in (0.3, 0.7, 0.05))   # R9
+    a = box.a_start + 3 * box.dt
+    assert D == float(np.float32(cosmo.drift_factor(a, a + box.dt, om, ol)))
+    assert K == cosmo.kick_factor(a - box.dt / 2, a + box.dt / 2, om, ol)
 
 
 def _amplitude(q, x):
