@@ -159,7 +159,7 @@ def main():
                     help="device memory of the boxes: torch's caching allocator or the library's hipMalloc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

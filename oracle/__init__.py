@@ -17,9 +17,9 @@ Simulations" (arXiv:2003.03931):
   optionally velocities as cell means plus companded bytes (Eq. (3)) with the
   fast arctangent of Eq. (4).
 
-Where the paper is silent the oracle follows the numbered readings R1-R22
-listed in the design doc (units, codec details, CIC, Green's functions, integrator,
-drift, compaction order).  Every floating-point step runs in float64.
+Where the paper is silent the oracle follows numbered readings R1-R22 (units,
+codec details, CIC, Green's functions, integrator, drift, compaction order);
+each module's header states the ones it takes.  Every floating-point step runs in float64.
 
 Parity status of each function is stated in its module header; the pins live
 in ``tests/test_oracle_*.py``.

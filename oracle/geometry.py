@@ -4,7 +4,7 @@ Sec. II (two-level decomposition): the volume is cut into cubic tiles; the
 short-range PM of a tile runs on a mesh enlarged by the cut-off radius on every
 face.  Sec. III-A: particles are stored cell-ordered on the coarse mesh.
 
-Readings (DESIGN.md): R1 units (lengths in particle spacings), R3 cell-centred
+Readings: R1 units (lengths in particle spacings), R3 cell-centred
 meshes aligned at the origin, R5 canonical order = tile-major (tile index x
 fastest), then cells x-fastest inside the tile, R11 tile box F = T + 2b.
 """
@@ -37,8 +37,10 @@ class Box:
                    spec.coarse_ratio, spec.buffer_fine, spec.r_cut_fine,
                    float(spec.dt), float(spec.v_headroom), int(getattr(spec, "fd_order", 2)),
                    int(getattr(spec, "vel_codec", 0)), int(getattr(spec, "comoving", 0)),
-                   float(getattr(spec, "omega_m", 1.0)), float(getattr(spec, "omega_l", 0.0)),
-                   float(getattr(spec, "a_start", 1.0)))
+                   # R9: the descriptor carries these as FP32
+                   float(np.float32(getattr(spec, "omega_m", 1.0))),
+                   float(np.float32(getattr(spec, "omega_l", 0.0))),
+                   float(np.float32(getattr(spec, "a_start", 1.0))))
 
     # ---- derived sizes -------------------------------------------------
     @property

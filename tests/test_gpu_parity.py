@@ -2,7 +2,7 @@
 identical seeded inputs.
 
 Bit-exact: codec, counts, cell order, compaction, density meshes.
-FP32 tolerances (derived in the design doc): force relative L2 <= 1e-5; positions
+FP32 tolerances (from the rounding of the FP32 force path): force relative L2 <= 1e-5; positions
 within one quantum for >= 99.9% of particles (compared by particle id).
 """
 
