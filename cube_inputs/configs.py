@@ -44,6 +44,7 @@ class BoxSpec:
     omega_m: float = 1.0   # matter density parameter (comoving runs)
     omega_l: float = 0.0   # cosmological-constant density parameter (comoving runs)
     a_start: float = 1.0   # scale factor of the initial state (comoving runs)
+    pp_range: int = 0      # >0: extended PP force within that many fine cells
 
     def with_(self, **kw):
         return replace(self, **kw)

@@ -26,7 +26,7 @@ in ``tests/test_oracle_*.py``.
 """
 
 from .geometry import Box
-from . import codec, cic, green, pm, step, diag, ewald, float_mode, vcodec, cosmo
+from . import codec, cic, green, pm, pp, step, diag, ewald, float_mode, vcodec, cosmo
 
 __all__ = ["Box", "codec", "cic", "green", "pm", "step", "diag", "ewald",
            "float_mode", "vcodec", "cosmo"]

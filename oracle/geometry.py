@@ -30,6 +30,7 @@ class Box:
     omega_m: float = 1.0
     omega_l: float = 0.0
     a_start: float = 1.0
+    pp_range: int = 0                 # >0: extended PP force within that many fine cells (P1-P4)
 
     @classmethod
     def from_spec(cls, spec):
@@ -40,7 +41,8 @@ class Box:
                    # R9: the descriptor carries these as FP32
                    float(np.float32(getattr(spec, "omega_m", 1.0))),
                    float(np.float32(getattr(spec, "omega_l", 0.0))),
-                   float(np.float32(getattr(spec, "a_start", 1.0))))
+                   float(np.float32(getattr(spec, "a_start", 1.0))),
+                   int(getattr(spec, "pp_range", 0)))
 
     # ---- derived sizes -------------------------------------------------
     @property
@@ -93,6 +95,9 @@ class Box:
         assert self.comoving in (0, 1)
         if self.comoving:
             assert self.omega_m > 0.0 and self.a_start > 0.0
+        # P1: partners within one coarse cell, three distinct neighbours per axis
+        assert 0 <= self.pp_range <= r and self.pp_range < a
+        assert self.pp_range == 0 or self.n_coarse >= 3
         if self.tiles_per_dim == 1:
             assert b == 0 and 2 * a < self.F
         else:

@@ -15,6 +15,9 @@ like point masses once their centres are a_len apart, so
   k = 0; its real-space kernel vanishes beyond a_len in the continuum.  On a
   tile box of F cells the kernel is K_f = IDFT_F[G_s], truncated to the
   minimum-image sphere |d| <= a, and G_f = DFT_F[K_f] (real and even).
+  With the extended PP force on (Box.pp_range, readings P1-P4 in pp.py) the
+  fine kernel leaves out what the pair force carries:
+  G_s(k) = -(S_pp^2 - S^2) / k^2, S_pp the S2 transform at diameter r_pp.
 
 Units (R1, R14): Poisson's equation is lap(phi) = rho - 1 (4 pi G = 1), the
 potential is phi = IDFT(G * DFT(rho)) with rho the density (mass per unit
@@ -71,14 +74,16 @@ def coarse_green(box: Box) -> np.ndarray:
     return G
 
 
-def short_range_green_continuum(n: int, cell: float, a_len: float, half_last=False):
-    """G_s(k) = -(1 - S^2)/k^2 sampled on an n^3 mesh of the given cell size."""
+def short_range_green_continuum(n: int, cell: float, a_len: float, half_last=False, pp_len: float = 0.0):
+    """G_s(k) = -(1 - S^2)/k^2 sampled on an n^3 mesh of the given cell size;
+    with an extended PP range pp_len > 0 the part inside it is left to the
+    pair force: -(S_pp^2 - S^2)/k^2, limit -(a_len^2 - pp_len^2)/30 (P2)."""
     k2 = _k2_grid(n, cell, half_last)
-    xi = np.sqrt(k2) * a_len / 2.0
-    S = s2_window(xi)
+    S = s2_window(np.sqrt(k2) * a_len / 2.0)
+    inner = s2_window(np.sqrt(k2) * pp_len / 2.0) ** 2 if pp_len > 0.0 else 1.0
     with np.errstate(divide="ignore", invalid="ignore"):
-        G = -(1.0 - S * S) / k2
-    G[0, 0, 0] = -a_len ** 2 / 30.0
+        G = -(inner - S * S) / k2
+    G[0, 0, 0] = -(a_len ** 2 - pp_len ** 2) / 30.0
     return G
 
 
@@ -86,7 +91,7 @@ def fine_kernel(box: Box, F: int = None) -> np.ndarray:
     """Truncated real-space short-range kernel K_f on the F^3 tile box."""
     F = box.F if F is None else F
     a = box.r_cut_fine
-    Gs = short_range_green_continuum(F, box.h, a * box.h, half_last=False)
+    Gs = short_range_green_continuum(F, box.h, a * box.h, half_last=False, pp_len=box.pp_range * box.h)
     K = np.fft.ifftn(Gs).real
     d = np.fft.fftfreq(F, d=1.0 / F)           # minimum-image offsets in cells
     d2 = d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2

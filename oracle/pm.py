@@ -34,7 +34,7 @@ import multiprocessing as mp
 
 import numpy as np
 
-from . import cic, green
+from . import cic, green, pp
 from .geometry import Box
 
 
@@ -232,6 +232,8 @@ class Solver:
         a_c = cic.gather(fd_gradient(phi_c, box.H, box.fd_order), Xc, periodic=True).T
         a_f, p_f = _fine_all(box, Q, counts, offsets, self.Gf, want_phi, workers)
         a = a_f + a_c
+        if box.pp_range:
+            a = a + pp.pp_accel(box, state)
         extra = ()
         if want_phi:
             extra = (p_f + cic.gather(phi_c, Xc, periodic=True),)
