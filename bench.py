@@ -150,6 +150,9 @@ def main():
                     help="timed steps of each mixed-precision run (0 skips them)")
     ap.add_argument("--vcodec-steps", type=int, default=10,
                     help="timed steps with the cell-mean velocity codec (0 skips them)")
+    ap.add_argument("--pp-steps", type=int, default=5,
+                    help="timed steps with the extended PP force on (0 skips them)")
+    ap.add_argument("--pp-range", type=int, default=4, help="PP range in fine cells of that run")
     ap.add_argument("--serving", type=int, default=40, help="requests of the serving run (0 skips it)")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--batched", type=int, default=0,
@@ -251,6 +254,30 @@ def main():
                   "compact_ms": vst.get("compact"), "gather_kick_drift_ms": vst.get("gather_kick_drift"),
                   "sigma": vdiag["s"], "saturations": vdiag["saturations"]}
         log(f"cell-mean velocity codec: {1e3 * el / args.vcodec_steps:.1f} ms/step")
+
+    # the same input with the extended PP force (pairs within pp_range fine cells)
+    ppr = None
+    if args.pp_steps > 0:
+        pb = CubeBox(spec.with_(pp_range=args.pp_range), tiles_per_batch=args.tiles_per_batch,
+                     allocator=args.allocator)
+        pb.compress(pos, vel)
+        pb.step(1)
+        pb.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pb.step(args.pp_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        pst = {st["name"]: st["total_ms"] / args.pp_steps for st in pb.profile_read() if st["launches"]}
+        pdiag = pb.diagnostics()
+        pb.close()
+        del pb
+        torch.cuda.empty_cache()
+        ppr = {"pp_range": args.pp_range, "value": n * args.pp_steps / el, "ms_per_step": 1e3 * el / args.pp_steps,
+               "steps": args.pp_steps, "pp_force_ms": pst.get("pp_force"),
+               "saturations": pdiag["saturations"], "max_u": pdiag["max_u"]}
+        log(f"extended PP (range {args.pp_range}): {1e3 * el / args.pp_steps:.1f} ms/step, "
+            f"pair kernel {pst.get('pp_force', 0.0):.1f} ms")
     del pos, vel
 
     serving = None
@@ -351,6 +378,7 @@ def main():
         "cpu_baseline": base,
         "mixed": mixed,
         "vel_codec_cell_mean": vcodec,
+        "extended_pp": ppr,
         "serving": serving,
         "batched": batched,
         "diagnostics": {"mass": diag["mass"], "max_carry": diag["max_carry"], "max_u": diag["max_u"],

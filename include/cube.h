@@ -121,6 +121,16 @@ typedef enum {
  *                     H = sqrt(omega_m a^-3 + (1 - omega_m - omega_l) a^-2 + omega_l).
  *   omega_m, omega_l  density parameters (comoving only; omega_m > 0).
  *   a_start           scale factor of the state at step 0 (comoving only; > 0).
+ *   pp_range          extended PP force (Sec. II, optional module): 0 = off;
+ *                     n_pp in [1, coarse_ratio] and below r_cut_fine: pairs
+ *                     closer than r_pp = n_pp fine cells attract explicitly by
+ *                     F_G(r) - F_S2(r; r_pp) (F_S2 the attraction of two S2
+ *                     clouds of diameter r_pp, zero net beyond r_pp), and the
+ *                     fine kernel leaves that part out:
+ *                     -(S_pp^2 - S^2) / k^2.  Pair distances come from the
+ *                     integer positions (exact squared separations in
+ *                     position quanta).  Costs 12 bytes per particle of
+ *                     device memory.  Anything else is CUBE_INVALID.
  * Derived: coarse cells per side N_c = n_side f / r, tile side T = n_side f / n_t
  * fine cells, tile FFT box F = T + 2b; every FFT side must factor into 2,3,5,7.
  */
@@ -142,6 +152,7 @@ typedef struct {
     float omega_m;
     float omega_l;
     float a_start;
+    int32_t pp_range;
 } cube_box_desc;
 
 typedef struct cube_ctx cube_ctx;

@@ -40,6 +40,7 @@ class BoxDesc(ctypes.Structure):
         ("omega_m", ctypes.c_float),
         ("omega_l", ctypes.c_float),
         ("a_start", ctypes.c_float),
+        ("pp_range", ctypes.c_int32),
     ]
 
 

@@ -27,7 +27,8 @@ def desc_from(spec, with_ids=False, tiles_per_batch=0, precision=CUBE_FP32):
                    float(spec.dt), float(spec.v_headroom), int(precision), 1 if with_ids else 0,
                    int(tiles_per_batch), int(getattr(spec, "fd_order", 2)), int(getattr(spec, "vel_codec", 0)),
                    int(getattr(spec, "comoving", 0)), float(getattr(spec, "omega_m", 1.0)),
-                   float(getattr(spec, "omega_l", 0.0)), float(getattr(spec, "a_start", 1.0)))
+                   float(getattr(spec, "omega_l", 0.0)), float(getattr(spec, "a_start", 1.0)),
+                   int(getattr(spec, "pp_range", 0)))
 
 
 def footprint(spec, tiles_per_batch=0, precision=CUBE_FP32, with_ids=False):
@@ -81,7 +82,8 @@ class CubeBox:
     """One box: owns a cube_ctx.  `spec` carries the geometry fields of
     cube_box_desc (n_side, tiles_per_dim, fine_per_spacing, coarse_ratio,
     buffer_fine, r_cut_fine, dt, v_headroom, and optionally fd_order,
-    vel_codec and the comoving fields comoving, omega_m, omega_l, a_start)."""
+    vel_codec, the comoving fields comoving, omega_m, omega_l, a_start, and
+    pp_range)."""
 
     def __init__(self, spec, with_ids=False, tiles_per_batch=0, device=0, precision=CUBE_FP32,
                  allocator="torch"):

@@ -108,11 +108,11 @@ int ilog2(int v) {
 
 enum Stage {
     ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_R2C, ST_FFT_ZG, ST_FFT_C2R,
-    ST_GATHER, ST_SCAN, ST_COMPACT, ST_VENC, NSTAGES
+    ST_GATHER, ST_SCAN, ST_COMPACT, ST_VENC, ST_PP, NSTAGES
 };
 const char* const kStageNames[NSTAGES] = {
     "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_r2c_xy", "fine_z_green",
-    "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact", "velocity_encode"};
+    "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact", "velocity_encode", "pp_force"};
 
 // HIP events around every launch of a stage, resolved at the next sync.
 struct Profiler {
@@ -251,6 +251,7 @@ struct cube_ctx {
     void* scan_ws = nullptr;
     double* partial = nullptr;
     double* reduced = nullptr;
+    float* pp[3] = {nullptr, nullptr, nullptr};   // extended PP accelerations, [3][n]
     int batch = 1;
 
     int64_t step = 0;
@@ -293,6 +294,10 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (d->vel_codec != CUBE_VEL_LINEAR && d->vel_codec != CUBE_VEL_CELL_MEAN)
         return fail(CUBE_INVALID, "unknown vel_codec");
     g.vcodec = d->vel_codec;
+    // the pair search reaches one coarse cell each way (r_pp <= H)
+    if (d->pp_range < 0 || d->pp_range > d->coarse_ratio || d->pp_range >= d->r_cut_fine)
+        return fail(CUBE_INVALID, "pp_range must be in [0, coarse_ratio] and below r_cut_fine");
+    g.npp = d->pp_range;
     if (d->comoving != 0 && d->comoving != 1) return fail(CUBE_INVALID, "comoving must be 0 or 1");
     if (d->comoving && !(d->omega_m > 0.0f && d->omega_l >= 0.0f && d->a_start > 0.0f &&
                          hubble(d->a_start, d->omega_m, d->omega_l) > 0.0))
@@ -392,6 +397,7 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
         add(12 * g.ncells);            // cell means
         add(8 * 255);                  // tan table
     }
+    if (g.npp) add(12 * n);            // PP accelerations
     auto r = [](int64_t bytes) { return (int64_t)round256((size_t)bytes); };
     const int64_t sortw = r((int64_t)sort_workspace_bytes(n));
     const int64_t t_green = r((int64_t)fine_green_workspace_bytes(g));
@@ -497,6 +503,17 @@ void fine_potential(cube_ctx* c, int t0, int nt, bool full = false) {
     P.add(ST_FFT_C2R, ev[2], ev[3], nt * (8.0 * h3 * wf + 4.0 * w3));
 }
 
+// extended PP accelerations of the current state (nothing when off)
+void pp_forces(cube_ctx* c) {
+    const Geom& g = c->g;
+    if (!g.npp) return;
+    Profiler& P = c->prof;
+    hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
+    launch_pp(g, c->offsets, c->A, c->pp, c->stream);
+    // own positions and offsets, the neighbour cells' bytes (L2-resident), 12 B out
+    if (P.on) P.add(ST_PP, e0, P.mark(c->stream), 15.0 * (double)g.n + 4.0 * (double)g.ncells);
+}
+
 GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     GatherArgs a{};
     a.g = c->g;
@@ -510,6 +527,7 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     a.coarse = c->coarse;
     a.sc = c->sc;
     a.vcell = c->vcell;
+    for (int k = 0; k < 3; ++k) a.pp[k] = c->pp[k];
     a.kick = (double)c->desc.dt;
     a.drift = c->desc.dt;
     if (c->desc.comoving) comoving_factors(c->desc, c->step, &a.kick, &a.drift);
@@ -526,6 +544,7 @@ cube_status run_step(cube_ctx* c) {
     launch_fill_i32(c->counts_new, 0, g.ncells, s);
     coarse_potential(c);
     Profiler& P = c->prof;
+    pp_forces(c);
     for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
         const int nt = std::min(c->batch, g.ntiles - t0);
         fine_potential(c, t0, nt);
@@ -649,6 +668,11 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     if (desc->with_ids) {
         CUBE_TRY(c->alloc_n(&c->A.ids, n));
         CUBE_TRY(c->alloc_n(&c->B.ids, n));
+    }
+    if (g.npp) {
+        float* pa = nullptr;
+        CUBE_TRY(c->alloc_n(&pa, 3 * n));
+        for (int k = 0; k < 3; ++k) c->pp[k] = pa + k * n;
     }
     double vtab_host[255];
     if (g.vcodec) {
@@ -848,6 +872,7 @@ cube_status cube_forces(cube_ctx* c, float* acc, int32_t on_device) {
     if (!on_device && !tmp.get(&dacc, bytes)) return fail(CUBE_OOM, "forces staging");
     launch_fill_i32(&c->sc->overflow, 0, 1, s);
     coarse_potential(c);
+    pp_forces(c);
     for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
         const int nt = std::min(c->batch, g.ntiles - t0);
         fine_potential(c, t0, nt);

@@ -335,7 +335,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         float af[3], ac[3];
         gather_force<R>(fphi, fi, ft, scale_f, af);
         gather_force<R>(cphi, ci, ct, scale_c, ac);
-        const float acc[3] = {af[0] + ac[0], af[1] + ac[1], af[2] + ac[2]};
+        float acc[3] = {af[0] + ac[0], af[1] + ac[1], af[2] + ac[2]};
+        if (A.pp[0]) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[a] += A.pp[a][p];
+        }
         if (MODE == GATHER_FORCE) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) A.acc[3 * (int64_t)p + a] = acc[a];

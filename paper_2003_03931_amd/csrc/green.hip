@@ -6,6 +6,8 @@
 //   coarse   G_c = -S^2 / k^2 (k != 0), 0 at k = 0            (FP64 table)
 //   fine     K_f = IDFT_F[-(1 - S^2)/k^2] truncated to |d| <= a,
 //            G_f = DFT_F[K_f]                                   (FP32 table)
+//            (1 becomes S_pp^2 with the extended PP force of range pp_len:
+//            the pair force then carries the part inside it, pp.hip)
 // Both are real, even in every axis and symmetric under axis permutations, so
 // one octant (n/2+1)^3 is stored; both already carry the 1/n^3 of the inverse
 // transform.  Everything is built on the device in FP64.  The fine kernel
@@ -55,8 +57,10 @@ __global__ void k_coarse_green(int Nc, double L, double a_len, double* __restric
     out[i] = g / ((double)Nc * Nc * Nc);
 }
 
-// short-range continuum kernel on the fine octant, k = 2 pi m / (F h)
-__global__ void k_short_green(int F, double h, double a_len, double* __restrict__ out) {
+// short-range continuum kernel on the fine octant, k = 2 pi m / (F h); with
+// the extended PP force (pp_len > 0) the part inside pp_len is the pair
+// force's: -(S_pp^2 - S^2) / k^2, k = 0 value -(a_len^2 - pp_len^2) / 30
+__global__ void k_short_green(int F, double h, double a_len, double pp_len, double* __restrict__ out) {
     const int M = F / 2 + 1;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)M * M * M) return;
@@ -66,9 +70,14 @@ __global__ void k_short_green(int F, double h, double a_len, double* __restrict_
     double g;
     if (k2 > 0.0) {
         const double S = s2_window(sqrt(k2) * a_len / 2.0);
-        g = -(1.0 - S * S) / k2;
+        double inner = 1.0;
+        if (pp_len > 0.0) {
+            const double Sp = s2_window(sqrt(k2) * pp_len / 2.0);
+            inner = Sp * Sp;
+        }
+        g = -(inner - S * S) / k2;
     } else {
-        g = -a_len * a_len / 30.0;
+        g = -(a_len * a_len - pp_len * pp_len) / 30.0;
     }
     out[i] = g;
 }
@@ -137,7 +146,8 @@ void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s) {
     double* b0 = static_cast<double*>(ws);
     double* b1 = b0 + (int64_t)M * M * M;
     // G_s on the octant
-    hipLaunchKernelGGL(k_short_green, dim3(blocks_for((int64_t)M * M * M)), dim3(256), 0, s, F, h, a_len, b0);
+    hipLaunchKernelGGL(k_short_green, dim3(blocks_for((int64_t)M * M * M)), dim3(256), 0, s, F, h, a_len,
+                       (double)g.npp / g.f, b0);
     // K(d) = (1/F^3) sum_m G_s(m) cos(2 pi m.d / F), d in [0, a]^3
     hipLaunchKernelGGL(k_cos_axis, dim3(blocks_for((int64_t)A * M * M)), dim3(256), 0, s, b0, b1, M, M, M, 0, M, A,
                        F, 1);

@@ -30,6 +30,7 @@ struct Geom {
     int periodic;  // 1 when the single tile is the periodic box
     int fdr;       // reach of the gradient stencil: 1 (2-point) or 2 (4-point)
     int vcodec;    // velocity storage: 0 linear bytes, 1 cell means + Eq. (3) bytes
+    int npp;       // extended PP range in fine cells (0: off)
     int64_t ncells;   // Nc^3
     int64_t n;        // ns^3 particles
     int ntiles;       // nt^3
@@ -187,6 +188,7 @@ struct GatherArgs {
     const float2* coarse;      // coarse potential (real part)
     StepScalars* sc;
     VelCells vcell;         // GATHER_STEP with the cell-mean codec
+    const float* pp[3];     // GATHER_STEP / GATHER_FORCE: PP accelerations to add (null: none)
     float* acc;             // GATHER_FORCE: [n][3]
     double* partial;        // GATHER_POTENTIAL: per-block partial sums
     double kick;            // GATHER_STEP: force multiplier of the kick (dt, or K_n comoving)
@@ -198,6 +200,10 @@ struct GatherArgs {
 void launch_gather(const GatherArgs& a, hipStream_t s);
 int gather_blocks_per_tile(const Geom& g);
 bool gather_supported(const Geom& g);
+
+// ---- pp.hip -------------------------------------------------------------
+// PP accelerations of every particle of the state, [3][n] FP32 planes.
+void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const acc[3], hipStream_t s);
 
 // ---- compact.hip --------------------------------------------------------
 bool compact_supported(const Geom& g);

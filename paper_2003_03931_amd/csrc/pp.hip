@@ -1,0 +1,124 @@
+// Extended PP force (Sec. II, optional PP module; Sec. III-B, pair distances
+// from the compressed integer positions).
+//
+// Every pair of particles closer than r_pp = n_pp fine cells attracts by
+//     F_pp(r) = F_G(r) - F_l(r; r_pp),
+// F_l(r; D) the attraction of two S2 clouds of diameter D (Hockney &
+// Eastwood's reference force), which equals F_G from r = D on; the fine
+// mesh's kernel leaves this part out (green.hip).  With xi = 2 r / D:
+//     4 pi D^2 F_l = (224 xi - 224 xi^3 + 70 xi^4 + 48 xi^5 - 21 xi^6) / 35,  xi <= 1
+//                  = (12/xi^2 - 224 + 896 xi - 840 xi^2 + 224 xi^3 + 70 xi^4
+//                     - 48 xi^5 + 7 xi^6) / 35,                            1 <= xi <= 2.
+// r_pp <= H, so a particle's partners lie in its own or the adjacent coarse
+// cells.  Positions stay in the fixed-point format: per axis the separation
+// is 256 (cell' - cell) + m' - m quanta (|.| < 512), the squared distance is
+// an exact integer from a packed 16-bit dot product (the CDNA analogue of
+// the paper's 8-bit VNNI distances), and only pairs inside r_pp reach the
+// FP32 force polynomial.  Coincident particles (and a particle with itself)
+// exert nothing.
+//
+// One workgroup per x-row of Tc coarse cells of a tile (a contiguous run of
+// the canonical order); per axis a thread visits its own cell and the
+// neighbour on the side its r_pp sphere reaches.  The accelerations go to
+// three FP32 planes in canonical order, which the gather adds to the mesh
+// force before the kick.
+#include <cmath>
+
+#include "common.h"
+
+namespace cube {
+
+namespace {
+
+typedef short v2i16 __attribute__((ext_vector_type(2)));
+
+constexpr int kPPThreads = 256;
+
+struct PPParams {
+    int reach;        // r_pp in position quanta: 256 n_pp / r
+    int reach2;       // its square
+    float two_over;   // 2 / reach: xi per quantum
+    float k35;        // 1 / (35 reach^2)
+    float amp;        // (256 / H)^2 / (4 pi): quanta to spacings, 4 pi G = 1
+};
+
+// (F_pp / r) in units of amp per quantum of separation, for 0 < u < reach
+__device__ __forceinline__ float pp_weight(int r2, const PPParams& P) {
+    const float u2 = (float)r2;                   // exact: r2 < 2^24
+    const float inv_u = rsqrtf(u2);
+    const float u = u2 * inv_u;
+    const float x = u * P.two_over;
+    float poly;
+    if (x <= 1.0f) {
+        const float x2 = x * x;
+        poly = x * (224.0f + x2 * (-224.0f + x * (70.0f + x * (48.0f - 21.0f * x))));
+    } else {
+        poly = 12.0f / (x * x) - 224.0f +
+               x * (896.0f + x * (-840.0f + x * (224.0f + x * (70.0f + x * (-48.0f + 7.0f * x)))));
+    }
+    return (inv_u * inv_u - poly * P.k35) * inv_u;
+}
+
+__global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __restrict__ offsets, Planes in,
+                                                  float* __restrict__ ax_out, float* __restrict__ ay_out,
+                                                  float* __restrict__ az_out, PPParams P) {
+    extern __shared__ int offs[];
+    const Chunk ch = chunk_of(g, blockIdx.x);
+    for (int j = threadIdx.x; j <= g.Tc; j += blockDim.x) offs[j] = offsets[ch.c0 + j];
+    __syncthreads();
+    const int Nc = g.Nc;
+    for (int p = offs[0] + threadIdx.x; p < offs[g.Tc]; p += blockDim.x) {
+        const int j = find_cell(offs, g.Tc, p);
+        const int c[3] = {ch.cx0 + j, ch.cy, ch.cz};
+        int m[3], lo[3], hi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            m[k] = in.m[k][p];
+            lo[k] = m[k] < P.reach ? -1 : 0;            // the sphere crosses the lower face
+            hi[k] = m[k] + P.reach > 255 ? 1 : 0;       // ... the upper face
+        }
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int dz = lo[2]; dz <= hi[2]; ++dz) {
+            const int z = wrapi(c[2] + dz, Nc);
+            for (int dy = lo[1]; dy <= hi[1]; ++dy) {
+                const int y = wrapi(c[1] + dy, Nc);
+                for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+                    const int64_t cn = canon(g, wrapi(c[0] + dx, Nc), y, z);
+                    const int q1 = offsets[cn + 1];
+                    for (int q = offsets[cn]; q < q1; ++q) {
+                        const int sx = 256 * dx + (int)in.m[0][q] - m[0];
+                        const int sy = 256 * dy + (int)in.m[1][q] - m[1];
+                        const int sz = 256 * dz + (int)in.m[2][q] - m[2];
+                        const v2i16 xy = {(short)sx, (short)sy};
+                        const int r2 = __builtin_amdgcn_sdot2(xy, xy, sz * sz, false);
+                        if (r2 == 0 || r2 >= P.reach2) continue;
+                        const float w = pp_weight(r2, P);
+                        a0 += w * (float)sx;
+                        a1 += w * (float)sy;
+                        a2 += w * (float)sz;
+                    }
+                }
+            }
+        }
+        ax_out[p] = a0 * P.amp;
+        ay_out[p] = a1 * P.amp;
+        az_out[p] = a2 * P.amp;
+    }
+}
+
+}  // namespace
+
+void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const acc[3], hipStream_t s) {
+    PPParams P;
+    P.reach = 256 * g.npp / g.r;
+    P.reach2 = P.reach * P.reach;
+    P.two_over = 2.0f / (float)P.reach;
+    P.k35 = (float)(1.0 / (35.0 * (double)P.reach * (double)P.reach));
+    const double q_per_spacing = 256.0 * g.f / g.r;          // 256 / H
+    P.amp = (float)(q_per_spacing * q_per_spacing / (4.0 * M_PI));
+    const int64_t chunks = g.ncells / g.Tc;
+    hipLaunchKernelGGL(k_pp, dim3((unsigned)chunks), dim3(kPPThreads), (g.Tc + 1) * sizeof(int), s, g, offsets,
+                       in, acc[0], acc[1], acc[2], P);
+}
+
+}  // namespace cube

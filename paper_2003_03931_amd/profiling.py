@@ -37,6 +37,7 @@ STAGE_KERNEL = {
     "gather_kick_drift": "k_gather<0,",
     "scan_counts": "k_tile_scan",
     "compact": "k_compact_fast",
+    "pp_force": "k_pp",
 }
 COPY_KERNELS = ("elementwise", "copyBuffer")
 

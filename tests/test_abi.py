@@ -135,3 +135,21 @@ def test_server_rejects_bad_requests_without_a_gpu():
         assert lib.cube_poll(srv, ctypes.c_uint64(12345), ctypes.byref(r)) == 1
     finally:
         lib.cube_server_destroy(srv)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
+def test_pp_range_validation_and_footprint():
+    """pp_range in [0, coarse_ratio] and below r_cut_fine; the PP planes add
+    12 bytes per particle to the persistent footprint."""
+    from paper_2003_03931_amd._lib import BoxDesc, load
+    lib = load()
+    p, t = ctypes.c_int64(), ctypes.c_int64()
+    sizes = {}
+    for npp, ok in ((0, True), (1, True), (4, True), (5, False), (-1, False)):
+        d = BoxDesc(32, 1, 2, 4, 0, 12, 0.05, 2.0, 0, 0, 0, 2, 0, 0, 1.0, 0.0, 1.0, npp)
+        assert (lib.cube_footprint(ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)) == 0) == ok, npp
+        if ok:
+            sizes[npp] = p.value
+        else:
+            assert b"pp_range" in lib.cube_last_error()
+    assert sizes[1] == sizes[4] and 12 * 32 ** 3 <= sizes[1] - sizes[0] <= 12 * 32 ** 3 + 256
