@@ -38,25 +38,27 @@ struct PPParams {
     int reach;        // r_pp in position quanta: 256 n_pp / r
     int reach2;       // its square
     float two_over;   // 2 / reach: xi per quantum
-    float k35;        // 1 / (35 reach^2)
-    float amp;        // (256 / H)^2 / (4 pi): quanta to spacings, 4 pi G = 1
+    float amp;        // (256 / H)^2 / (4 pi) / 140: quanta to spacings, 4 pi G = 1
 };
 
-// (F_pp / r) in units of amp per quantum of separation, for 0 < u < reach
+// F_pp / r per quantum of separation, in units of amp, for 0 < u < reach:
+// F_pp = F_G R(xi) / 140 with R = 140 - 35 xi^2 (4 pi D^2 F_l), i.e.
+//     R = 140 - xi^3 (224 - 224 xi^2 + 70 xi^3 + 48 xi^4 - 21 xi^5)   (xi <= 1)
+//     R = t^5 (168 - 182 t + 64 t^2 - 7 t^3),  t = 2 - xi           (1 <= xi < 2)
+// The second line is the outer branch rewritten about xi = 2, where the pair
+// force vanishes to fifth order: evaluated in t it has no FP32 cancellation.
 __device__ __forceinline__ float pp_weight(int r2, const PPParams& P) {
     const float u2 = (float)r2;                   // exact: r2 < 2^24
     const float inv_u = rsqrtf(u2);
-    const float u = u2 * inv_u;
-    const float x = u * P.two_over;
-    float poly;
+    const float x = u2 * inv_u * P.two_over;
+    float R;
     if (x <= 1.0f) {
-        const float x2 = x * x;
-        poly = x * (224.0f + x2 * (-224.0f + x * (70.0f + x * (48.0f - 21.0f * x))));
+        R = 140.0f - x * x * x * (224.0f + x * x * (-224.0f + x * (70.0f + x * (48.0f - 21.0f * x))));
     } else {
-        poly = 12.0f / (x * x) - 224.0f +
-               x * (896.0f + x * (-840.0f + x * (224.0f + x * (70.0f + x * (-48.0f + 7.0f * x)))));
+        const float t = 2.0f - x, t2 = t * t;
+        R = t2 * t2 * t * (168.0f + t * (-182.0f + t * (64.0f - 7.0f * t)));
     }
-    return (inv_u * inv_u - poly * P.k35) * inv_u;
+    return R * inv_u * inv_u * inv_u;
 }
 
 __global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __restrict__ offsets, Planes in,
@@ -113,9 +115,8 @@ void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const ac
     P.reach = 256 * g.npp / g.r;
     P.reach2 = P.reach * P.reach;
     P.two_over = 2.0f / (float)P.reach;
-    P.k35 = (float)(1.0 / (35.0 * (double)P.reach * (double)P.reach));
     const double q_per_spacing = 256.0 * g.f / g.r;          // 256 / H
-    P.amp = (float)(q_per_spacing * q_per_spacing / (4.0 * M_PI));
+    P.amp = (float)(q_per_spacing * q_per_spacing / (4.0 * M_PI * 140.0));
     const int64_t chunks = g.ncells / g.Tc;
     hipLaunchKernelGGL(k_pp, dim3((unsigned)chunks), dim3(kPPThreads), (g.Tc + 1) * sizeof(int), s, g, offsets,
                        in, acc[0], acc[1], acc[2], P);
