@@ -42,10 +42,19 @@ STAGE_KERNEL = {
 COPY_KERNELS = ("elementwise", "copyBuffer")
 
 
+# sources whose kernels the profiled plain step never launches: the
+# extended PP force (pp_range > 0), the cell-mean velocity codec
+# (vel_codec = 1) and the request server
+NOT_IN_STEP = ("pp.hip", "vcodec.hip", "server.cpp")
+
+
 def source_digest():
-    """Digest of the kernel sources: a traffic summary is valid only for them."""
+    """Digest of the sources of the profiled step's kernels: a traffic summary
+    is valid only for them."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if os.path.basename(f) in NOT_IN_STEP:
+            continue
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
