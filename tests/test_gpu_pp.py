@@ -95,6 +95,37 @@ def test_pp_forces_on_clumps_with_coincident_particles(npp):
     assert np.all(np.isfinite(a))
 
 
+def test_pp_forces_where_neighbourhoods_exceed_the_lds_stage():
+    """A quarter of the 32^3 box's particles in one tight clump: the rows
+    around it hold more than the 4096 neighbour particles a workgroup stages
+    in LDS, so those workgroups read their partners from global memory while
+    the others use the staged copy; both against the oracle."""
+    _need_gpu()
+    import oracle
+    from oracle import codec, pm, pp
+    spec = config("c1").with_(pp_range=4)
+    box = oracle.Box.from_spec(spec).validate()
+    rng = np.random.default_rng(22)
+    n, L = box.n_side ** 3, float(box.n_side)
+    pos = rng.uniform(0, L, (n, 3))
+    pos[:n // 4] = np.mod(np.array([9.3, 20.1, 4.7]) + 0.5 * rng.standard_normal((n // 4, 3)), L)
+    u = rng.integers(-20, 21, (n, 3)).astype(np.int8)
+    st = codec.build_state(box, codec.encode_positions(box, pos), u, 2.0 ** -6, 20, ids=np.arange(n))
+    # particles in the 3 x 3 rows of Tc + 2 cells around each row of cells
+    Nc, Tc = box.n_coarse, box.Tc
+    c = st.counts.reshape(Nc, Nc, Nc)                      # [z][y][x] for one periodic tile
+    rows = c.sum(axis=2) + c[:, :, -1] + c[:, :, 0]      # Tc = Nc: the end cells wrap onto the row
+    hood = sum(np.roll(np.roll(rows, dz, 0), dy, 1) for dz in (-1, 0, 1) for dy in (-1, 0, 1))
+    assert (hood > 4096).sum() > 0 and (hood <= 4096).sum() > 0
+    a_ref = pm.Solver(box).forces(st, workers=1)
+    a = _gpu_forces(spec, st)
+    err = rel_l2(a, a_ref)
+    share = np.linalg.norm(pp.pp_accel(box, st)) / np.linalg.norm(a_ref)
+    print(f"dense clump: {(hood > 4096).sum()} rows read from global memory, force relative L2 {err:.3e}, "
+          f"|PP| / |total| {share:.3f}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("name,npp,nsteps", [("c1", 4, 2), ("t4", 2, 2)])
 def test_pp_steps_match_oracle(name, npp, nsteps):
     _need_gpu()
