@@ -88,27 +88,8 @@ __device__ __forceinline__ void pp_cell(int q0, int q1, int dx, int dy, int dz, 
     }
 }
 
-// the same for staged partners: their separations from the row origin are
-// stored (x, y) as packed 16-bit integers and z as a 16-bit integer, so a
-// separation is one packed subtract and one subtract (modulo 2^16, exact:
-// every separation lies in (-512, 512))
-__device__ __forceinline__ void pp_staged(int q0, int q1, const uint32_t* s_xy, const short* s_z, v2i16 own_xy,
-                                          short own_z, const PPParams& P, float& a0, float& a1, float& a2) {
-    for (int q = q0; q < q1; ++q) {
-        const v2i16 sxy = __builtin_bit_cast(v2i16, s_xy[q]) - own_xy;
-        const int sz = (short)(s_z[q] - own_z);
-        const int r2 = __builtin_amdgcn_sdot2(sxy, sxy, sz * sz, false);
-        if (r2 == 0 || r2 >= P.reach2) continue;
-        const float w = pp_weight(r2, P);
-        a0 += w * (float)sxy.x;
-        a1 += w * (float)sxy.y;
-        a2 += w * (float)sz;
-    }
-}
-
 // Dynamic LDS: own row offsets [Tc + 1], per neighbour row the LDS ranges of
-// its Tc + 2 cells [9][Tc + 3], and up to kPPCap staged positions (packed
-// 16-bit (x, y) words, then 16-bit z values).
+// its Tc + 2 cells [9][Tc + 3], and up to kPPCap packed positions.
 __global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __restrict__ offsets, Planes in,
                                                   float* __restrict__ ax_out, float* __restrict__ ay_out,
                                                   float* __restrict__ az_out, PPParams P) {
@@ -116,8 +97,7 @@ __global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __rest
     const int Tc = g.Tc, RW = Tc + 3;
     int* offs = lds;
     int* s_off = offs + (Tc + 1);
-    uint32_t* s_xy = reinterpret_cast<uint32_t*>(s_off + 9 * RW);
-    short* s_z = reinterpret_cast<short*>(s_xy + kPPCap);
+    uint32_t* s_pos = reinterpret_cast<uint32_t*>(s_off + 9 * RW);
     // per neighbour row (dy, dz) = (r % 3 - 1, r / 3 - 1): its first middle
     // cell and the global particle ranges of the middle cells and of the
     // cells just left and right of them
@@ -166,23 +146,12 @@ __global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __rest
                 v = s_base[r + 1];
             s_off[e] = v;
         }
-    }
-    __syncthreads();
-    if (staged) {
-        // a staged particle of row r, cell i (0: left of the row, Tc + 1:
-        // right) lies at (256 (i - 1) + m0, 256 dy + m1, 256 dz + m2) quanta
-        // from the origin of the workgroup's first cell
         for (int r = 0; r < 9; ++r) {
             const int nl = s_rng[r][3] - s_rng[r][2], nm = s_rng[r][1] - s_rng[r][0];
             const int n = s_base[r + 1] - s_base[r];
-            const int dy = r % 3 - 1, dz = r / 3 - 1;
             for (int k = threadIdx.x; k < n; k += blockDim.x) {
                 const int q = k < nl ? s_rng[r][2] + k : k < nl + nm ? s_rng[r][0] + (k - nl) : s_rng[r][4] + (k - nl - nm);
-                const int e = s_base[r] + k;
-                const int i = find_cell(s_off + r * RW, Tc + 2, e);
-                const int x = 256 * (i - 1) + (int)in.m[0][q], y = 256 * dy + (int)in.m[1][q];
-                s_xy[e] = ((uint32_t)x & 0xffffu) | ((uint32_t)y << 16);
-                s_z[e] = (short)(256 * dz + (int)in.m[2][q]);
+                s_pos[s_base[r] + k] = (uint32_t)in.m[0][q] | ((uint32_t)in.m[1][q] << 8) | ((uint32_t)in.m[2][q] << 16);
             }
         }
     }
@@ -198,15 +167,20 @@ __global__ __launch_bounds__(kPPThreads) void k_pp(Geom g, const int32_t* __rest
             hi[k] = m[k] + P.reach > 255 ? 1 : 0;       // ... the upper face
         }
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        const v2i16 own_xy = {(short)(256 * j + m[0]), (short)m[1]};
-        const short own_z = (short)m[2];
         for (int dz = lo[2]; dz <= hi[2]; ++dz) {
             for (int dy = lo[1]; dy <= hi[1]; ++dy) {
                 const int r = (dz + 1) * 3 + (dy + 1);
                 for (int dx = lo[0]; dx <= hi[0]; ++dx) {
                     if (staged) {
                         const int i = r * RW + j + 1 + dx;
-                        pp_staged(s_off[i], s_off[i + 1], s_xy, s_z, own_xy, own_z, P, a0, a1, a2);
+                        pp_cell(s_off[i], s_off[i + 1], dx, dy, dz, m, P,
+                                [&](int q, int* mq) {
+                                    const uint32_t w = s_pos[q];
+                                    mq[0] = (int)(w & 255u);
+                                    mq[1] = (int)((w >> 8) & 255u);
+                                    mq[2] = (int)(w >> 16);
+                                },
+                                a0, a1, a2);
                     } else {
                         const int64_t cn = canon(g, wrapi(c[0] + dx, Nc), wrapi(c[1] + dy, Nc), wrapi(c[2] + dz, Nc));
                         pp_cell(offsets[cn], offsets[cn + 1], dx, dy, dz, m, P,
@@ -236,7 +210,7 @@ void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const ac
     const double q_per_spacing = 256.0 * g.f / g.r;          // 256 / H
     P.amp = (float)(q_per_spacing * q_per_spacing / (4.0 * M_PI * 140.0));
     const int64_t chunks = g.ncells / g.Tc;
-    const size_t lds = sizeof(int) * ((size_t)(g.Tc + 1) + 9 * (size_t)(g.Tc + 3) + kPPCap) + sizeof(short) * kPPCap;
+    const size_t lds = sizeof(int) * ((size_t)(g.Tc + 1) + 9 * (size_t)(g.Tc + 3) + kPPCap);
     hipLaunchKernelGGL(k_pp, dim3((unsigned)chunks), dim3(kPPThreads), lds, s, g, offsets, in, acc[0], acc[1], acc[2],
                        P);
 }
