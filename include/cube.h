@@ -262,7 +262,9 @@ cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
  * step (only the cumulative saturation counter may include the aborted step). */
 cube_status cube_pm_step(cube_ctx* ctx, int32_t nsteps);
 
-/* Acceleration of every particle at the current state, no update.
+/* Acceleration of every particle at the current state, no update: coarse
+ * plus fine mesh force (Sec. II, Eq. (1)), plus the pair force when
+ * pp_range > 0, in static units (the comoving kick factor is not applied).
  * acc[i*3+k], canonical order, float32.  Synchronises.  CUBE_OVERFLOW as for
  * cube_pm_step (the output is then not valid). */
 cube_status cube_forces(cube_ctx* ctx, float* acc, int32_t on_device);
