@@ -9,7 +9,8 @@ full cube_pm_step (deposits, both Poisson solves, gather, kick, drift,
 recount, compaction) with the state resident in HBM.
 
 Prints one JSON line: throughput in particle-steps/s (FP32 spectra; the
-BF16 and FP16 spectrum stores on the same input beside it), the dominant
+BF16 and FP16 spectrum stores, the cell-mean velocity codec and the extended
+PP force on the same input beside it), the dominant
 kernel's achieved bandwidth against the 8 TB/s HBM peak (HIP events on the
 library stream over the timed region), the FP64 oracle timed on the host
 cores on a bounded sample of the same tile geometry, and a served stream of
