@@ -125,8 +125,9 @@ typedef enum {
  *                     n_pp in [1, coarse_ratio] and below r_cut_fine: pairs
  *                     closer than r_pp = n_pp fine cells attract explicitly by
  *                     F_G(r) - F_S2(r; r_pp) (F_S2 the attraction of two S2
- *                     clouds of diameter r_pp, zero net beyond r_pp), and the
- *                     fine kernel leaves that part out:
+ *                     clouds of diameter r_pp, equal to F_G from r_pp on, so
+ *                     the pair force vanishes there), and the fine kernel
+ *                     leaves that part out:
  *                     -(S_pp^2 - S^2) / k^2.  Pair distances come from the
  *                     integer positions (exact squared separations in
  *                     position quanta).  Costs 12 bytes per particle of
