@@ -11,7 +11,8 @@ Simulations" (arXiv:2003.03931):
 
 * Sec. II: force split F_G = F_s + F_l, PM convolution Eq. (1), a global coarse
   mesh for the long-range force and per-tile fine meshes (tile plus buffer) for
-  the short-range force.
+  the short-range force; optionally the extended PP force between close pairs
+  with the fine kernel corrected to match (pp.py).
 * Sec. III-A: fixed-point compression -- positions as a 1-byte offset inside the
   parent coarse cell (Eq. (2)), cell-ordered storage with a per-cell count;
   optionally velocities as cell means plus companded bytes (Eq. (3)) with the
@@ -28,5 +29,5 @@ in ``tests/test_oracle_*.py``.
 from .geometry import Box
 from . import codec, cic, green, pm, pp, step, diag, ewald, float_mode, vcodec, cosmo
 
-__all__ = ["Box", "codec", "cic", "green", "pm", "step", "diag", "ewald",
+__all__ = ["Box", "codec", "cic", "green", "pm", "pp", "step", "diag", "ewald",
            "float_mode", "vcodec", "cosmo"]
