@@ -153,3 +153,38 @@ def test_pp_range_validation_and_footprint():
         else:
             assert b"pp_range" in lib.cube_last_error()
     assert sizes[1] == sizes[4] and 12 * 32 ** 3 <= sizes[1] - sizes[0] <= 12 * 32 ** 3 + 256
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror has the C struct's size and each of its fields the
+    C offset: a small C program built with the host compiler against
+    include/cube.h prints them."""
+    import shutil
+    import subprocess
+    from paper_2003_03931_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"cube_box_desc": _lib.BoxDesc, "cube_state_view": _lib.StateView, "cube_diag": _lib.Diag,
+             "cube_stage_stat": _lib.StageStat, "cube_allocator": _lib.Allocator,
+             "cube_server_desc": _lib.ServerDesc, "cube_request": _lib.Request, "cube_result": _lib.Result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cube.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'    printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, value = line.split()
+            got[cname, field] = int(value)
+    for cname, py in pairs.items():
+        assert got[cname, "sizeof"] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[cname, fname] == getattr(py, fname).offset, (cname, fname)
