@@ -13,8 +13,8 @@
  *   kick and requantise the 1-byte velocities, drift and requantise the
  *   1-byte positions, then recount and stably compact the particles by cell.
  *
- * Conventions (units, codec details, Green's functions, integrator, order)
- * are the readings listed with the library's design notes; in brief:
+ * Conventions where the paper is silent (units, codec details, Green's
+ * functions, integrator, order), in brief:
  * lengths in mean inter-particle spacings, particle mass 1, lap(phi) = rho - 1,
  * positions x = (256 n_c + m + 1/2) H / 256 (0-based n_c, H the coarse cell
  * size), velocities v = u * s with int8 u and a power-of-two scale s per box,
