@@ -35,30 +35,54 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample="c3cpu"):
-    """The FP64 oracle's step on a 256^3 box with the benchmark's tile
-    geometry, tile-parallel over the host cores (run before the GPU is
-    touched, so the worker processes fork from a clean process)."""
-    import numpy as np
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_step_rate(name, workers):
+    """Particle-steps/s of one full oracle step of workload `name` and its wall time."""
     from cube_inputs import config, zeldovich_ics
     import oracle
     from oracle import codec, pm, step
 
-    spec = config(sample)
+    spec = config(name)
     box = oracle.Box.from_spec(spec).validate()
     pos, vel = zeldovich_ics(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
     st = codec.compress(box, pos, vel)
     del pos, vel
-    workers = max(1, min(16, os.cpu_count() or 1))
     sol = pm.Solver(box)
     t0 = time.perf_counter()
     step.step(sol, st, workers=workers)
     dt = time.perf_counter() - t0
     n = spec.n_side ** 3
-    return {"value": n / dt, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"one full oracle step (coarse mesh, all {box.n_tiles} tiles, kick, drift, compaction) "
-                      f"of a {spec.n_side}^3 box with the same tile geometry (r=4, b=16, 160^3 tile box, "
-                      f"8 particles per coarse cell): {n} particle-steps in {dt:.2f} s"}
+    return n / dt, dt, n, box.n_tiles
+
+
+def cpu_baseline(sample="c3cpu", sample_one="c3s"):
+    """The FP64 oracle's step on a 256^3 box with the benchmark's tile
+    geometry, tile-parallel over the host cores, and on one core for a 128^3
+    box with the same tile geometry (run before the GPU is touched, so the
+    worker processes fork from a clean process)."""
+    workers = max(1, min(16, os.cpu_count() or 1))
+    v_all, t_all, n_all, nt_all = _oracle_step_rate(sample, workers)
+    v_one, t_one, n_one, nt_one = _oracle_step_rate(sample_one, 1)
+    geom = "r=4, b=16, 160^3 tile box, 8 particles per coarse cell"
+    return {"value": v_all, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"one full oracle step (coarse mesh, all {nt_all} tiles, kick, drift, compaction) "
+                      f"of a 256^3 box with the same tile geometry ({geom}): {n_all} particle-steps in "
+                      f"{t_all:.2f} s on {workers} worker processes",
+            "one_core": {"value": v_one, "unit": "particle-steps/s", "cores": 1,
+                         "sample": f"one full oracle step of a 128^3 box with the same tile geometry ({geom}, "
+                                   f"{nt_one} tiles): {n_one} particle-steps in {t_one:.2f} s"},
+            "cpu_count": os.cpu_count(), "cpu_model": _cpu_model(),
+            "note": "unoptimised FP64 numpy reference, not the paper's tuned CPU code"}
 
 
 def served_spec(n_side, spectral_index, seed, name):
@@ -171,7 +195,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         base = cpu_baseline()
-        log(f"cpu baseline {base['value']:.3e} particle-steps/s on {base['cores']} cores")
+        log(f"cpu baseline {base['value']:.3e} particle-steps/s on {base['cores']} cores, "
+            f"{base['one_core']['value']:.3e} on one core")
 
     import numpy as np
     import torch

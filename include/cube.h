@@ -222,7 +222,9 @@ typedef struct {
     void* user;
 } cube_allocator;
 
-/* Create a context for one box: validates the geometry, allocates the state,
+/* Create a context for one box (Sec. II: the box's global coarse mesh and its
+ * tiles of fine meshes with buffers; Sec. III-A: the coarse mesh is also the
+ * cell grid of the position codec): validates the geometry, allocates the state,
  * the meshes and the workspace on the current device (through `alloc`, or
  * hipMalloc when it is NULL), builds the FFT twiddles (FP64-derived) and the
  * Green's tables (FP64).  hip_stream is a hipStream_t (NULL = the default
@@ -251,12 +253,16 @@ void cube_destroy(cube_ctx* ctx);
 cube_status cube_compress(cube_ctx* ctx, const float* pos, const float* vel,
                           int64_t n, int32_t on_device);
 
-/* Decode the state to float positions/velocities in canonical order (exact:
- * bin centres and u * s).  Same layout as cube_compress.  Synchronises. */
+/* Decode the state to float positions/velocities in canonical order (Eq. (2)
+ * read back at the bin centres, exact; velocities u * s, or Eq. (3) with
+ * CUBE_VEL_CELL_MEAN).  Same layout as cube_compress.  Synchronises. */
 cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
                             int32_t on_device);
 
-/* Advance the state by nsteps kick-drift steps.  Enqueued on the context
+/* Advance the state by nsteps kick-drift steps of the two-level PM method
+ * (Sec. II: coarse plus per-tile fine mesh force, Eq. (1); Sec. III-A: the
+ * positions and velocities are requantised and the particles recounted and
+ * reordered by cell after each step).  Enqueued on the context
  * stream; returns after the last step's completion flag is read back (one
  * small device-to-host copy per step).  CUBE_OVERFLOW if a CUBE_MIXED_FP16
  * spectrum value left the FP16 range: the state is then the one before that
@@ -275,11 +281,14 @@ cube_status cube_forces(cube_ctx* ctx, float* acc, int32_t on_device);
 cube_status cube_get_state(cube_ctx* ctx, cube_state_view* view);
 cube_status cube_set_state(cube_ctx* ctx, const cube_state_view* view);
 
-/* FP64 diagnostics (mass, momentum, kinetic and potential energy, counters).
- * Synchronises. */
+/* FP64 diagnostics (mass, momentum, kinetic and potential energy, counters)
+ * of the current state: the conserved quantities against which a PM run is
+ * checked (Sec. IV-C compares the evolved matter field; mass is exact here
+ * because the deposit of Sec. II is integer).  Synchronises. */
 cube_status cube_diagnostics(cube_ctx* ctx, cube_diag* out);
 
-/* Matter power spectrum of the current state: CIC on a mesh of one cell per
+/* Matter power spectrum of the current state (Sec. IV-C: delta = rho/rho_bar
+ * - 1, P(k) and Delta^2(k) = k^3 P(k) / (2 pi^2)): CIC on a mesh of one cell per
  * spacing, delta = rho - 1, P = L^3 |DFT(delta)|^2 / N_cells^2 averaged over
  * shells j = round(|n|), 1 <= j < n_side/4.  Host arrays of nbins entries
  * (nbins must be n_side/4 - 1).  Synchronises. */

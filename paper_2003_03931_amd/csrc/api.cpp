@@ -15,6 +15,7 @@
 // compaction moves B back into A in the new order.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -944,21 +945,28 @@ cube_status cube_set_state(cube_ctx* c, const cube_state_view* v) {
     init.max_u = v->max_u;
     *c->sc_host = init;
     CUBE_HIP(hipMemcpyAsync(c->sc, c->sc_host, sizeof(StepScalars), hipMemcpyHostToDevice, s));
-    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
-    launch_max_block8(g, c->counts, &c->sc->max_block8, s);
-    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
-    int32_t total = -1;
-    CUBE_HIP(hipMemcpyAsync(&total, c->offsets + g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // the counts must be non-negative and sum to n (in 64 bits) before any
+    // offset derived from them indexes the particle planes
+    long long check[2] = {0, INT64_MAX};
+    long long* dcheck = reinterpret_cast<long long*>(c->reduced);
+    CUBE_HIP(hipMemcpyAsync(dcheck, check, sizeof(check), hipMemcpyHostToDevice, s));
+    launch_count_check(c->counts, g.ncells, dcheck, s);
+    CUBE_HIP(hipMemcpyAsync(check, dcheck, sizeof(check), hipMemcpyDeviceToHost, s));
     st = sync(c);
     if (st != CUBE_OK) return st;
-    if (total != g.n) {
+    if (check[1] < 0 || check[0] != (long long)g.n) {
         // never leave offsets that point past the particle arrays
         launch_fill_i32(c->counts, 0, g.ncells + 16, s);
         launch_fill_i32(c->offsets, 0, g.ncells + 16, s);
         c->has_state = false;
         sync(c);
-        return fail(CUBE_INVALID, "counts do not sum to n_particles");
+        return fail(CUBE_INVALID, check[1] < 0 ? "negative cell count" : "counts do not sum to n_particles");
     }
+    exclusive_scan_i32(c->counts, c->offsets, g.ncells, c->scan_ws, s, &c->sc->max_count);
+    launch_max_block8(g, c->counts, &c->sc->max_block8, s);
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
+    st = sync(c);
+    if (st != CUBE_OK) return st;
     c->max_count = c->sc_host->max_count;
     c->max_block8 = c->sc_host->max_block8;
     c->has_state = true;

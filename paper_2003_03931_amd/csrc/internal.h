@@ -97,6 +97,9 @@ struct VelCells {
 size_t scan_workspace_bytes(int64_t n);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
                         int32_t* max_out = nullptr);
+// out[0] += 64-bit sum of counts[0..n), out[1] = min(out[1], smallest count)
+// (out[0] = 0 and out[1] = INT64_MAX on entry)
+void launch_count_check(const int32_t* counts, int64_t n, long long* out, hipStream_t s);
 
 // ---- sort.hip -----------------------------------------------------------
 // Stable LSD sort of (key, value) pairs by the low `bits` key bits.

@@ -4,6 +4,8 @@
 // Three passes over tiles of 4096 values: per-tile totals, a (recursive) scan
 // of the totals, then a tile-local scan plus the tile's base.  Each thread
 // owns 16 consecutive values so the loads are 64-byte vectors.
+#include <algorithm>
+
 #include "common.h"
 
 namespace cube {
@@ -118,7 +120,34 @@ __global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __re
 
 inline int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
 
+// out[0] += sum of in (64-bit), out[1] = min(out[1], smallest value)
+__global__ __launch_bounds__(kScanThreads) void k_count_check(const int32_t* __restrict__ in, int64_t n,
+                                                               long long* __restrict__ out) {
+    long long sum = 0;
+    int mn = 0x7fffffff;
+    for (int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kScanThreads) {
+        const int v = in[i];
+        sum += v;
+        mn = min(mn, v);
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        sum += __shfl_xor(sum, d, kWave);
+        mn = min(mn, __shfl_xor(mn, d, kWave));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(&out[0]), (unsigned long long)sum);
+        atomicMin(&out[1], (long long)mn);
+    }
+}
+
 }  // namespace
+
+void launch_count_check(const int32_t* counts, int64_t n, long long* out, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kScanThreads - 1) / kScanThreads));
+    hipLaunchKernelGGL(k_count_check, dim3(blocks), dim3(kScanThreads), 0, s, counts, n, out);
+}
 
 size_t scan_workspace_bytes(int64_t n) {
     size_t bytes = 0;

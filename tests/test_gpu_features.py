@@ -65,7 +65,7 @@ def test_mixed_precision_steps(prec):
         load_state(g, ref)
         g.step(3)
         st = g.get_state()
-    d = _compare_by_id(box, st, o)
+    d = _compare_by_id(box, st, o, codes=0.0)    # 16-bit spectra: codes near a half-integer may flip
     print(f"{prec}: within 1 quantum {np.mean(d <= 1):.5f}, identical {np.mean(d == 0):.5f}")
     assert st["counts"].sum() == ref.n
     assert np.mean(d <= 1) >= 0.99

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from cube_inputs import config
-from tests.gpu_common import gpu_box, ics, load_state, oracle_state, rel_l2
+from tests.gpu_common import check_compaction, compare_by_id, gpu_box, ics, load_state, oracle_state, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -139,16 +139,11 @@ def test_forces_relative_l2(name):
 
 
 # ---------------------------------------------------------------- steps
-def _compare_by_id(box, gstate, ostate):
-    from oracle.codec import State
-    gs = State(box, gstate["counts"].astype(np.int64), gstate["m"], gstate["u"], gstate["s"], gstate["M"],
-               gstate["ids"])
-    qg = np.empty((ostate.n, 3), dtype=np.int64)
-    qo = np.empty_like(qg)
-    qg[gs.ids] = gs.quanta()
-    qo[ostate.ids] = ostate.quanta()
-    L = 256 * box.n_coarse
-    d = np.abs(np.mod(qg - qo + L // 2, L) - L // 2).max(axis=1)
+def _compare_by_id(box, gstate, ostate, codes=0.99):
+    """Periodic max |dQ| per id; also asserts that the ids are a permutation
+    and that at least `codes` of the particles carry the oracle's velocity codes."""
+    d, same_u = compare_by_id(box, gstate, ostate)
+    assert np.mean(same_u) >= codes, f"velocity codes identical for {np.mean(same_u):.5f}"
     return d
 
 
@@ -162,9 +157,12 @@ def test_steps_match_oracle(name, nsteps):
         o = step.step(sol, o, workers=1)
     with gpu_box(name, tiles_per_batch=5) as g:
         load_state(g, ref)
-        g.step(nsteps)
+        g.step(nsteps - 1)
+        before = g.get_state()
+        g.step(1)
         st = g.get_state()
         diag = g.diagnostics()
+    check_compaction(box, before, st)
     assert st["s"] == o.s
     assert st["counts"].sum() == ref.n and diag["mass"] == ref.n
     d = _compare_by_id(box, st, o)
@@ -185,11 +183,12 @@ def test_general_compaction_path_far_movers():
     assert info["max_carry"] >= 2
     with gpu_box("c1") as g:
         load_state(g, fast)
+        before = g.get_state()
         g.step(1)
         st = g.get_state()
         diag = g.diagnostics()
     assert diag["max_carry"] == info["max_carry"]
-    assert st["counts"].sum() == ref.n
+    check_compaction(box, before, st)
     d = _compare_by_id(box, st, o)
     assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
 
@@ -209,11 +208,12 @@ def test_many_one_cell_movers():
     assert info["max_carry"] == 1
     with gpu_box("t4") as g:
         load_state(g, fast)
+        before = g.get_state()
         g.step(1)
         st = g.get_state()
         diag = g.diagnostics()
     assert diag["max_carry"] == 1
-    assert st["counts"].sum() == ref.n
+    check_compaction(box, before, st)
     d = _compare_by_id(box, st, o)
     assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
 
@@ -250,10 +250,11 @@ def test_dense_cell_paths(n_dense):
     with gpu_box("t4") as g:
         load_state(g, ref)
         got = g.debug_mesh(2, tile).cpu().numpy()
+        before = g.get_state()
         g.step(1)
         st = g.get_state()
     assert np.array_equal(got, rho.transpose(2, 1, 0).astype(np.float32))
-    assert st["counts"].sum() == ref.n
+    check_compaction(box, before, st)
     d = _compare_by_id(box, st, o)
     assert np.mean(d <= 1) >= 0.999 and np.mean(d == 0) >= 0.99
 
@@ -306,10 +307,12 @@ def test_saturating_kick_matches_oracle():
     assert info["saturations"] > ref.n                  # most components clamp
     with gpu_box("t4") as g:
         load_state(g, rest)
+        before = g.get_state()
         g.step(1)
         st = g.get_state()
         dg = g.diagnostics()
     assert st["s"] == o.s == 2.0 ** -14
+    check_compaction(box, before, st)
     assert abs(dg["saturations"] - info["saturations"]) <= 1e-4 * info["saturations"]
     ug = np.empty((ref.n, 3), np.int64)
     ug[st["ids"]] = st["u"].T
@@ -319,3 +322,26 @@ def test_saturating_kick_matches_oracle():
     assert np.abs(ug).max() == 127 and dg["max_u"] == 127
     d = _compare_by_id(box, st, o)
     assert np.mean(d == 0) >= 0.999 and d.max() <= 1
+
+
+# ------------------------------------------------------------ state input
+def test_set_state_rejects_negative_counts():
+    """Counts that sum to n but hold a negative entry would give offsets that
+    run backwards: the library refuses them and keeps no state."""
+    from paper_2003_03931_amd._lib import CubeError
+    box, ref = oracle_state("t4")
+    bad = ref.counts.astype(np.int64).copy()
+    bad[0] += 100
+    bad[1] -= 100
+    assert bad.sum() == ref.n and bad[1] < 0
+    with gpu_box("t4") as g:
+        with pytest.raises(CubeError):
+            g.set_state(bad, ref.m, ref.u, ref.s, ref.M, ref.ids)
+        big = ref.counts.astype(np.int64).copy()
+        big[0] += 2 ** 31 - 1        # wraps to the right int32 total only with the negative entry
+        big[1] -= 2 ** 31 - 1
+        with pytest.raises(CubeError):
+            g.set_state(big.astype(np.int32), ref.m, ref.u, ref.s, ref.M, ref.ids)
+        load_state(g, ref)           # a valid state is still accepted afterwards
+        st = g.get_state()
+    assert np.array_equal(st["counts"], ref.counts.astype(np.int32))
