@@ -42,7 +42,7 @@ typedef enum {
     CUBE_OOM = 2,          /* device allocation failed; ctx unchanged                 */
     CUBE_DEVICE = 3,       /* HIP runtime error; ctx is poisoned (only destroy valid) */
     CUBE_NOT_READY = 4,    /* cube_poll: the request is queued or running             */
-    CUBE_OVERFLOW = 5,     /* a CUBE_MIXED_FP16 spectrum value left the FP16 range    */
+    CUBE_OVERFLOW = 5,     /* FP32 spectra still raised the FP16 range flag (not seen) */
     CUBE_UNSUPPORTED = 6   /* mesh side not factorable by the FFT radices             */
 } cube_status;
 
@@ -56,11 +56,10 @@ typedef enum {
  *   CUBE_MIXED_BF16  BF16 real and imaginary parts (4 bytes), rounded to
  *                    nearest even; about 2^-9 relative error per stored value.
  *   CUBE_MIXED_FP16  FP16 parts scaled by a power of two (4 bytes); about
- *                    2^-12 relative error per value.  Batches whose densities
- *                    could leave the FP16 range are run with FP32 storage;
- *                    a potential spectrum value beyond it makes cube_pm_step
- *                    return CUBE_OVERFLOW with the state left as before the
- *                    step.
+ *                    2^-12 relative error per value.  Steps whose densities
+ *                    could leave the FP16 range are run with FP32 storage,
+ *                    and so is again any step in which a potential spectrum
+ *                    value left it.
  */
 typedef enum {
     CUBE_FP32 = 0,
@@ -262,18 +261,25 @@ cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
 /* Advance the state by nsteps kick-drift steps of the two-level PM method
  * (Sec. II: coarse plus per-tile fine mesh force, Eq. (1); Sec. III-A: the
  * positions and velocities are requantised and the particles recounted and
- * reordered by cell after each step).  Enqueued on the context
- * stream; returns after the last step's completion flag is read back (one
- * small device-to-host copy per step).  CUBE_OVERFLOW if a CUBE_MIXED_FP16
- * spectrum value left the FP16 range: the state is then the one before that
- * step (only the cumulative saturation counter may include the aborted step). */
+ * reordered by cell after each step).  All steps are enqueued on the
+ * context stream with no host synchronisation and no allocation between
+ * them; every choice a step makes from its own data (the compaction path,
+ * accumulator widths, spectrum formats) is taken on the device, and a step
+ * that needs the host (the sorted compaction for a particle that moved more
+ * than one coarse cell, or a plan change) stops the later ones until the
+ * host resolves it after the one read-back at the end.  A CUBE_MIXED_FP16
+ * potential spectrum value outside the FP16 range makes that step run again
+ * with FP32 spectra.  Returns after the last step; errors CUBE_OOM (the
+ * sorted compaction's temporaries; the state is then the one before that
+ * step), CUBE_DEVICE. */
 cube_status cube_pm_step(cube_ctx* ctx, int32_t nsteps);
 
 /* Acceleration of every particle at the current state, no update: coarse
  * plus fine mesh force (Sec. II, Eq. (1)), plus the pair force when
  * pp_range > 0, in static units (the comoving kick factor is not applied).
- * acc[i*3+k], canonical order, float32.  Synchronises.  CUBE_OVERFLOW as for
- * cube_pm_step (the output is then not valid). */
+ * acc[i*3+k], canonical order, float32.  Synchronises.  A CUBE_MIXED_FP16
+ * potential spectrum value outside the FP16 range makes it evaluate again
+ * with FP32 spectra. */
 cube_status cube_forces(cube_ctx* ctx, float* acc, int32_t on_device);
 
 /* Copy the state out to / in from caller buffers (see cube_state_view).
@@ -300,6 +306,13 @@ cube_status cube_power_spectrum(cube_ctx* ctx, int32_t nbins, double* k,
  * 1 coarse potential (N_c^3), 2 fine density of tile `tile` (F^3),
  * 3 fine potential of tile `tile` (F^3).  Layout [z][y][x], x fastest. */
 cube_status cube_debug_mesh(cube_ctx* ctx, int32_t what, int32_t tile, float* out);
+
+/* Test hook: force a condition in the next `count` steps of cube_pm_step so
+ * that the host-side recovery runs on ordinary states.  what: 1 raise the
+ * FP16 range flag (the step runs again with FP32 spectra), 2 take the sorted
+ * general compaction (same order as the fast one), 3 stop the steps after
+ * this one for a new plan.  The results equal those of unforced steps. */
+cube_status cube_debug_force(cube_ctx* ctx, int32_t what, int32_t count);
 
 /* Utility: in-place unnormalised 3-D complex FFT of an n^3 interleaved
  * (re, im) float32 device array, [z][y][x] layout, sign -1 (inverse = 0) or

@@ -148,6 +148,7 @@ SIGNATURES = {
     "cube_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
     "cube_debug_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "cube_debug_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "cube_fft3d": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cube_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cube_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StageStat), ctypes.c_int32,

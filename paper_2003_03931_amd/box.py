@@ -243,6 +243,10 @@ class CubeBox:
         return [{"name": buf[i].name.decode(), "launches": buf[i].launches, "total_ms": buf[i].total_ms,
                  "bytes": buf[i].bytes} for i in range(n.value)]
 
+    def debug_force(self, what, count=1):
+        """Test hook: 1 FP16 range flag, 2 sorted compaction, 3 re-plan, for the next `count` steps."""
+        check(self.lib.cube_debug_force(self.ctx, int(what), int(count)))
+
     def debug_mesh(self, what, tile=0):
         t = self.torch
         side = self.n_coarse if what in (0, 1) else self.F

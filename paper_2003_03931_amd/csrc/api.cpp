@@ -259,6 +259,8 @@ struct cube_ctx {
     double last_step_ms = 0.0;
     int32_t max_count = 0;            // largest cell count of the current state
     int32_t max_block8 = 0;           // largest count of a 2x2x2 block of coarse cells
+    bool halted_recently = false;     // the last cube_pm_step met a halt: enqueue one step per sync
+    int dbg_force[4] = {0, 0, 0, 0};  // cube_debug_force: steps still to receive each forced condition
 
     ~cube_ctx() {
         if (sc_host) hipHostFree(sc_host);
@@ -450,35 +452,42 @@ void coarse_potential(cube_ctx* c) {
     }
 }
 
-// Storage format of the tile half spectra for the current state: the mixed
-// FP16 mode falls back to FP32 while a fine-cell density could exceed the
-// FP16 range (a fine cell gathers the particles of at most one 2x2x2 block
-// of coarse cells, density f^3 per particle; the plane transform's gain is
-// divided out).
-int spec_format(const cube_ctx* c) {
+// What the host fixes when it enqueues a step, from the state's counts as of
+// its last synchronisation: the fine-deposit accumulator width and the
+// storage format of the tile half spectra.  The mixed FP16 mode falls back to
+// FP32 while a fine-cell density could exceed the FP16 range (a fine cell
+// gathers the particles of at most one 2x2x2 block of coarse cells, density
+// f^3 per particle; the plane transform's gain is divided out), and after a
+// potential spectrum value left it (force_fp32).  The epilogue of every step
+// checks that the new state still fits the plan (halt 3 otherwise).
+struct StepPlan {
+    bool wide;
+    int fmt;
+};
+
+StepPlan plan_of(const cube_ctx* c, bool force_fp32 = false) {
+    StepPlan p;
+    p.wide = fine_deposit_needs_wide(c->g, c->max_block8);
     switch (c->desc.precision) {
-        case CUBE_MIXED_BF16: return 1;
-        case CUBE_MIXED_FP16: {
-            const double f3 = (double)c->g.f * c->g.f * c->g.f;
-            return f3 * (double)c->max_block8 + 1.0 < 32768.0 ? 2 : 0;
-        }
-        default: return 0;
+        case CUBE_MIXED_BF16: p.fmt = 1; break;
+        case CUBE_MIXED_FP16: p.fmt = (!force_fp32 && fp16_density_fits(c->g, c->max_block8)) ? 2 : 0; break;
+        default: p.fmt = 0;
     }
+    return p;
 }
 
 // fine potentials of tiles [t0, t0 + nt) into ctx->fine_real: over the
 // whole box when `full`, else over the tile plus the 1 + fdr cells the
 // gather's interpolation and differences reach (all of the box for a
 // periodic tile)
-void fine_potential(cube_ctx* c, int t0, int nt, bool full = false) {
+void fine_potential(cube_ctx* c, const StepPlan& plan, int t0, int nt, bool full = false) {
     const Geom& g = c->g;
     Profiler& P = c->prof;
-    const int fmt = spec_format(c);
+    const int fmt = plan.fmt;
     const bool whole = full || g.periodic;
     const int lo = whole ? 0 : g.b - 1 - g.fdr, hi = whole ? g.F : g.b + g.T + 1 + g.fdr;
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
-    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
-                        c->stream);
+    launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, plan.wide, c->stream);
     if (!P.on) {
         fft_tiles_convolve(c->fine_real, c->fine_spec, g.F, nt, c->tw_fine, c->fine_green, fmt, &c->sc->overflow,
                            lo, hi, c->stream);
@@ -515,7 +524,7 @@ void pp_forces(cube_ctx* c) {
     if (P.on) P.add(ST_PP, e0, P.mark(c->stream), 15.0 * (double)g.n + 4.0 * (double)g.ncells);
 }
 
-GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
+GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt, int64_t step_index) {
     GatherArgs a{};
     a.g = c->g;
     a.offsets = c->offsets;
@@ -531,25 +540,33 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt) {
     for (int k = 0; k < 3; ++k) a.pp[k] = c->pp[k];
     a.kick = (double)c->desc.dt;
     a.drift = c->desc.dt;
-    if (c->desc.comoving) comoving_factors(c->desc, c->step, &a.kick, &a.drift);
+    if (c->desc.comoving) comoving_factors(c->desc, step_index, &a.kick, &a.drift);
     a.tile0 = t0;
     a.ntiles = nt;
     a.mode = mode;
     return a;
 }
 
-cube_status run_step(cube_ctx* c) {
+// Enqueue one step (no host synchronisation, no allocation): `plan` fixes
+// the deposit width and spectrum format of this step and of the next one
+// (checked by the epilogue), `step_index` the comoving factors.
+void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
     const Geom& g = c->g;
     hipStream_t s = c->stream;
-    launch_step_prologue(c->sc, c->desc.v_headroom, s);
-    launch_fill_i32(c->counts_new, 0, g.ncells, s);
+    StepScalars* sc = c->sc;
+    launch_step_prologue(sc, c->desc.v_headroom, s);
+    launch_fill_i32(c->counts_new, 0, g.ncells, s, &sc->halt);
     coarse_potential(c);
     Profiler& P = c->prof;
     pp_forces(c);
     for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
         const int nt = std::min(c->batch, g.ntiles - t0);
-        fine_potential(c, t0, nt);
-        GatherArgs a = gather_args(c, GATHER_STEP, t0, nt);
+        fine_potential(c, plan, t0, nt);
+        if (t0 == 0 && c->dbg_force[1] > 0) {
+            --c->dbg_force[1];
+            launch_fill_i32(&sc->overflow, 1, 1, s, &sc->halt);
+        }
+        GatherArgs a = gather_args(c, GATHER_STEP, t0, nt, step_index);
         hipEvent_t e0 = P.on ? P.mark(s) : nullptr;
         launch_gather(a, s);
         if (P.on) {
@@ -561,55 +578,129 @@ cube_status run_step(cube_ctx* c) {
         }
     }
     hipEvent_t es = P.on ? P.mark(s) : nullptr;
-    launch_fill_i32(&c->sc->max_count, 0, 2, s);          // max_count and max_block8
-    exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &c->sc->max_count);
-    launch_max_block8(g, c->counts_new, &c->sc->max_block8, s);
+    launch_fill_i32(&sc->new_max_count, 0, 2, s, &sc->halt);     // new_max_count and new_max_block8
+    exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &sc->new_max_count, &sc->halt);
+    launch_max_block8(g, c->counts_new, &sc->new_max_block8, s, &sc->halt);
     if (P.on) P.add(ST_SCAN, es, P.mark(s), 8.0 * (double)g.ncells);
-    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, s));
-    cube_status st = sync(c);
-    if (st != CUBE_OK) return st;
-    if (P.on) P.flush();
-    if (c->sc_host->overflow)
-        return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range: use CUBE_MIXED_BF16 or CUBE_FP32");
+    // the fast compaction's 16-bit counts and prefixes bound the old and new cell counts
+    if (c->dbg_force[2] > 0) {
+        --c->dbg_force[2];
+        launch_fill_i32(&sc->far_count, 1, 1, s, &sc->halt);
+    }
+    launch_step_decide(sc, 65535, s);
     // with the cell-mean codec the kicked FP32 velocities move instead of codes
     Planes src = c->B, dst = c->A;
     if (g.vcodec)
         for (int k = 0; k < 3; ++k) src.u[k] = dst.u[k] = nullptr;
-    // the fast compaction's 16-bit counts and prefixes bound the old and new cell counts
-    if (c->sc_host->far_count == 0 && c->max_count <= 65535 && c->sc_host->max_count <= 65535) {
-        hipEvent_t ec = P.on ? P.mark(s) : nullptr;
-        launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, src, dst, s);
-        // 6 B + move code read, 6 B written, old and new offsets read
-        if (P.on) P.add(ST_COMPACT, ec, P.mark(s), 13.0 * (double)g.n + 8.0 * (double)g.ncells);
-    } else {
-        // general path: stable sort of the new keys (temporary buffers)
-        uint32_t *key = nullptr, *idx = nullptr, *kt = nullptr, *it = nullptr;
-        void* ws = nullptr;
-        Temp tmp(c->mem);
-        const size_t nb = (size_t)g.n * sizeof(uint32_t);
-        if (!tmp.get(&key, nb) || !tmp.get(&idx, nb) || !tmp.get(&kt, nb) || !tmp.get(&it, nb) ||
-            !tmp.get(&ws, sort_workspace_bytes(g.n)))
-            return fail(CUBE_OOM, "general compaction: out of memory");
-        launch_general_keys(g, c->offsets, c->dir, c->far_key, key, idx, s);
-        stable_sort_pairs(key, idx, kt, it, g.n, ilog2((int)std::min<int64_t>(g.ncells, 1 << 30)) + 1, ws, s);
-        launch_permute_planes(idx, src, dst, g.n, s);
-        st = sync(c);
-        if (st != CUBE_OK) return st;
-    }
-    launch_step_epilogue(c->sc, s);
+    hipEvent_t ec = P.on ? P.mark(s) : nullptr;
+    launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, src, dst, sc, s);
+    // 6 B + move code read, 6 B written, old and new offsets read
+    if (P.on) P.add(ST_COMPACT, ec, P.mark(s), 13.0 * (double)g.n + 8.0 * (double)g.ncells);
     if (g.vcodec) {
         // re-encode against the new cells (sets sigma, max |u|, saturations)
         hipEvent_t ev = P.on ? P.mark(s) : nullptr;
-        launch_vc_encode(g, c->offsets_new, c->A, c->vcell, c->sc, c->partial, s);
+        launch_vc_encode(g, c->offsets_new, c->A, c->vcell, sc, c->partial, s, true);
         // FP32 velocities read twice, codes written, cell means written
         if (P.on) P.add(ST_VENC, ev, P.mark(s), 27.0 * (double)g.n + 16.0 * (double)g.ncells);
     }
+    launch_commit_cells(c->counts_new, c->offsets_new, c->counts, c->offsets, g.ncells, sc, s);
+    launch_step_epilogue(sc, g, g.vcodec, plan.wide, plan.fmt == 2, s);
+    if (c->dbg_force[3] > 0) {
+        --c->dbg_force[3];
+        launch_fill_i32(&sc->halt, 3, 1, s, &sc->halt);
+    }
+}
+
+// Temporaries of the sorted general compaction: four key/index arrays of n
+// words and the sort's workspace, from the context's allocator or from a
+// caller-provided region.
+size_t general_scratch_bytes(int64_t n) {
+    return 4 * round256((size_t)n * sizeof(uint32_t)) + round256(sort_workspace_bytes(n));
+}
+
+// Finish a step that halted for the general compaction (halt 1): every
+// stage up to the compaction has run and its outputs (the updated planes,
+// move codes, far keys and new counts and offsets) are intact.  Sort the new
+// keys stably, permute, re-encode (cell-mean codec), commit.  `scratch`
+// (general_scratch_bytes) comes from the caller, or is allocated here.
+cube_status finish_general(cube_ctx* c, const StepPlan& next, void* scratch) {
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    launch_fill_i32(&c->sc->halt, 0, 1, s);
+    Temp tmp(c->mem);
+    char* base = static_cast<char*>(scratch);
+    if (!base && !tmp.get(&base, general_scratch_bytes(g.n)))
+        return fail(CUBE_OOM, "general compaction: out of memory");
+    const size_t nb = round256((size_t)g.n * sizeof(uint32_t));
+    uint32_t* key = reinterpret_cast<uint32_t*>(base);
+    uint32_t* idx = reinterpret_cast<uint32_t*>(base + nb);
+    uint32_t* kt = reinterpret_cast<uint32_t*>(base + 2 * nb);
+    uint32_t* it = reinterpret_cast<uint32_t*>(base + 3 * nb);
+    void* ws = base + 4 * nb;
+    Planes src = c->B, dst = c->A;
+    if (g.vcodec)
+        for (int k = 0; k < 3; ++k) src.u[k] = dst.u[k] = nullptr;
+    launch_general_keys(g, c->offsets, c->dir, c->far_key, key, idx, s);
+    stable_sort_pairs(key, idx, kt, it, g.n, ilog2((int)std::min<int64_t>(g.ncells, 1 << 30)) + 1, ws, s);
+    launch_permute_planes(idx, src, dst, g.n, s);
+    if (g.vcodec) launch_vc_encode(g, c->offsets_new, c->A, c->vcell, c->sc, c->partial, s, true);
+    launch_commit_cells(c->counts_new, c->offsets_new, c->counts, c->offsets, g.ncells, c->sc, s);
+    launch_step_epilogue(c->sc, g, g.vcodec, next.wide, next.fmt == 2, s);
+    return launch_status(c);
+}
+
+// Wait for the enqueued work and read the step scalars back.
+cube_status read_scalars(cube_ctx* c) {
+    CUBE_HIP(hipMemcpyAsync(c->sc_host, c->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, c->stream));
+    cube_status st = sync(c);
+    if (st != CUBE_OK) return st;
     c->max_count = c->sc_host->max_count;
     c->max_block8 = c->sc_host->max_block8;
-    std::swap(c->counts, c->counts_new);
-    std::swap(c->offsets, c->offsets_new);
-    c->step += 1;
-    return launch_status(c);
+    return CUBE_OK;
+}
+
+// nsteps steps: enqueue them all (one at a time after a recent halt), read
+// the scalars once, resolve a halt, and continue with the rest.  scratch:
+// optional region for the general compaction's temporaries.
+cube_status run_steps(cube_ctx* c, int32_t nsteps, void* scratch) {
+    int64_t done_total = 0;
+    bool force_fp32 = false;
+    bool met_halt = false;
+    while (done_total < nsteps) {
+        const StepPlan plan = plan_of(c, force_fp32);
+        const int64_t k = c->halted_recently || met_halt ? 1 : nsteps - done_total;
+        const int64_t base = c->sc_host->steps_done;
+        for (int64_t i = 0; i < k; ++i) enqueue_step(c, plan, c->step + i);
+        cube_status st = read_scalars(c);
+        if (st != CUBE_OK) return st;
+        if (c->prof.on) c->prof.flush();
+        const int64_t done = c->sc_host->steps_done - base;
+        c->step += done;
+        done_total += done;
+        const int halt = c->sc_host->halt;
+        if (halt == 0) continue;
+        met_halt = true;
+        if (halt == 1) {
+            st = finish_general(c, plan_of(c, force_fp32), scratch);
+            if (st == CUBE_OK) st = read_scalars(c);
+            if (st != CUBE_OK) {
+                launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+                sync(c);
+                return st;
+            }
+            if (c->sc_host->steps_done != base + done + 1) return fail(CUBE_DEVICE, "general compaction did not commit");
+            c->step += 1;
+            done_total += 1;
+            if (c->sc_host->halt == 3) launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+        } else {
+            // 2: FP16 overflow, the step is run again with FP32 spectra;
+            // 3: the committed state needs another plan for the next step
+            if (halt == 2) force_fp32 = true;
+            launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+        }
+    }
+    c->halted_recently = met_halt;
+    return CUBE_OK;
 }
 
 }  // namespace
@@ -850,14 +941,10 @@ cube_status cube_pm_step(cube_ctx* c, int32_t nsteps) {
     if (st != CUBE_OK) return st;
     if (nsteps < 0) return fail(CUBE_INVALID, "negative step count");
     auto t0 = std::chrono::steady_clock::now();
-    for (int i = 0; i < nsteps; ++i) {
-        st = run_step(c);
-        if (st != CUBE_OK) return st;
-    }
-    st = sync(c);
-    if (st == CUBE_OK && c->prof.on) c->prof.flush();
+    st = run_steps(c, nsteps, nullptr);
     auto t1 = std::chrono::steady_clock::now();
-    if (nsteps > 0) c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
+    if (st == CUBE_OK && nsteps > 0)
+        c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
     return st;
 }
 
@@ -871,21 +958,30 @@ cube_status cube_forces(cube_ctx* c, float* acc, int32_t on_device) {
     const size_t bytes = (size_t)g.n * 3 * sizeof(float);
     Temp tmp(c->mem);
     if (!on_device && !tmp.get(&dacc, bytes)) return fail(CUBE_OOM, "forces staging");
-    launch_fill_i32(&c->sc->overflow, 0, 1, s);
-    coarse_potential(c);
-    pp_forces(c);
-    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
-        const int nt = std::min(c->batch, g.ntiles - t0);
-        fine_potential(c, t0, nt);
-        GatherArgs a = gather_args(c, GATHER_FORCE, t0, nt);
-        a.acc = dacc;
-        launch_gather(a, s);
+    // a FP16 potential spectrum out of range: evaluate again with FP32 spectra
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const StepPlan plan = plan_of(c, attempt > 0);
+        launch_fill_i32(&c->sc->overflow, 0, 1, s);
+        coarse_potential(c);
+        pp_forces(c);
+        for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+            const int nt = std::min(c->batch, g.ntiles - t0);
+            fine_potential(c, plan, t0, nt);
+            GatherArgs a = gather_args(c, GATHER_FORCE, t0, nt, c->step);
+            a.acc = dacc;
+            launch_gather(a, s);
+        }
+        int32_t oflow = 0;
+        CUBE_HIP(hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        st = sync(c);
+        if (st != CUBE_OK) return st;
+        if (!oflow) break;
+        if (attempt > 0) return fail(CUBE_OVERFLOW, "FP32 spectra raised the FP16 range flag");
     }
-    if (!on_device) hipMemcpyAsync(acc, dacc, bytes, hipMemcpyDeviceToHost, s);
-    int32_t oflow = 0;
-    hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    st = sync(c);
-    if (st == CUBE_OK && oflow) return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range");
+    if (!on_device) {
+        CUBE_HIP(hipMemcpyAsync(acc, dacc, bytes, hipMemcpyDeviceToHost, s));
+        st = sync(c);
+    }
     return st;
 }
 
@@ -1002,29 +1098,35 @@ cube_status cube_diagnostics(cube_ctx* c, cube_diag* out) {
     out->s_v = c->sc_host->s;
     out->step = c->step;
     out->last_step_ms = c->last_step_ms;
-    // potential energy: 1/2 sum over particles of phi_f + phi_c at their positions
-    launch_fill_i32(&c->sc->overflow, 0, 1, s);
-    coarse_potential(c);
+    // potential energy: 1/2 sum over particles of phi_f + phi_c at their
+    // positions (again with FP32 spectra if a FP16 one left its range)
     double wsum = 0.0;
     std::vector<double> part;
-    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
-        const int nt = std::min(c->batch, g.ntiles - t0);
-        fine_potential(c, t0, nt);
-        GatherArgs a = gather_args(c, GATHER_POTENTIAL, t0, nt);
-        a.partial = c->partial;
-        launch_gather(a, s);
-        const int64_t np = (int64_t)gather_blocks_per_tile(g) * nt;
-        part.resize(np);
-        CUBE_HIP(hipMemcpyAsync(part.data(), c->partial, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const StepPlan plan = plan_of(c, attempt > 0);
+        launch_fill_i32(&c->sc->overflow, 0, 1, s);
+        coarse_potential(c);
+        wsum = 0.0;
+        for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+            const int nt = std::min(c->batch, g.ntiles - t0);
+            fine_potential(c, plan, t0, nt);
+            GatherArgs a = gather_args(c, GATHER_POTENTIAL, t0, nt, c->step);
+            a.partial = c->partial;
+            launch_gather(a, s);
+            const int64_t np = (int64_t)gather_blocks_per_tile(g) * nt;
+            part.resize(np);
+            CUBE_HIP(hipMemcpyAsync(part.data(), c->partial, np * sizeof(double), hipMemcpyDeviceToHost, s));
+            st = sync(c);
+            if (st != CUBE_OK) return st;
+            for (double v : part) wsum += v;
+        }
+        int32_t oflow = 0;
+        CUBE_HIP(hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         st = sync(c);
         if (st != CUBE_OK) return st;
-        for (double v : part) wsum += v;
+        if (!oflow) break;
+        if (attempt > 0) return fail(CUBE_OVERFLOW, "FP32 spectra raised the FP16 range flag");
     }
-    int32_t oflow = 0;
-    CUBE_HIP(hipMemcpyAsync(&oflow, &c->sc->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    st = sync(c);
-    if (st != CUBE_OK) return st;
-    if (oflow) return fail(CUBE_OVERFLOW, "FP16 spectrum value out of range");
     out->potential = 0.5 * wsum;
     return CUBE_OK;
 }
@@ -1084,12 +1186,20 @@ cube_status cube_debug_mesh(cube_ctx* c, int32_t what, int32_t tile, float* out)
         if (what == 2)
             launch_fine_deposit(g, c->offsets, c->A, tile, 1, c->fine_real, fine_deposit_needs_wide(g, c->max_block8),
                                 s);
-        else fine_potential(c, tile, 1, true);
+        else fine_potential(c, plan_of(c), tile, 1, true);
         CUBE_HIP(hipMemcpyAsync(out, c->fine_real, fcube * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
         return fail(CUBE_INVALID, "unknown mesh");
     }
     return sync(c);
+}
+
+cube_status cube_debug_force(cube_ctx* c, int32_t what, int32_t count) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (what < 1 || what > 3 || count < 0) return fail(CUBE_INVALID, "unknown forced condition");
+    c->dbg_force[what] = count;
+    return CUBE_OK;
 }
 
 cube_status cube_fft3d(int32_t n, float* data, int32_t inverse, void* hip_stream) {

@@ -45,7 +45,9 @@ struct CompactShape {
 template <int BX, int BYZ>
 __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_t* __restrict__ off_old,
                                                             const int32_t* __restrict__ off_new,
-                                                            const uint8_t* __restrict__ dir, Planes src, Planes dst) {
+                                                            const uint8_t* __restrict__ dir, Planes src, Planes dst,
+                                                            const StepScalars* sc) {
+    if (*(volatile const int32_t*)&sc->halt) return;
     constexpr int BY = BYZ, BZ = BYZ;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
     constexpr int nsrc = SX * SY * SZ, ndst = BX * BY * BZ, nrow = BY * BZ;
@@ -515,13 +517,13 @@ CompactShape compact_shape(const Geom& g) {
 
 template <int BYZ>
 void launch_compact_yz(int bx, dim3 grid, const Geom& g, const int32_t* off_old, const int32_t* off_new,
-                       const uint8_t* dir, Planes src, Planes dst, hipStream_t s) {
+                       const uint8_t* dir, Planes src, Planes dst, const StepScalars* sc, hipStream_t s) {
     switch (bx) {
-        case 16: hipLaunchKernelGGL((k_compact_fast<16, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
-        case 8: hipLaunchKernelGGL((k_compact_fast<8, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
-        case 4: hipLaunchKernelGGL((k_compact_fast<4, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
-        case 2: hipLaunchKernelGGL((k_compact_fast<2, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
-        default: hipLaunchKernelGGL((k_compact_fast<1, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst); break;
+        case 16: hipLaunchKernelGGL((k_compact_fast<16, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst, sc); break;
+        case 8: hipLaunchKernelGGL((k_compact_fast<8, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst, sc); break;
+        case 4: hipLaunchKernelGGL((k_compact_fast<4, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst, sc); break;
+        case 2: hipLaunchKernelGGL((k_compact_fast<2, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst, sc); break;
+        default: hipLaunchKernelGGL((k_compact_fast<1, BYZ>), grid, dim3(kCThreads), 0, s, g, off_old, off_new, dir, src, dst, sc); break;
     }
 }
 
@@ -533,12 +535,12 @@ bool compact_supported(const Geom& g) {
 }
 
 void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new, const uint8_t* dir,
-                         Planes src, Planes dst, hipStream_t s) {
+                         Planes src, Planes dst, const StepScalars* sc, hipStream_t s) {
     const CompactShape sh = compact_shape(g);
     const int64_t nb = (int64_t)(g.Nc / sh.BX) * (g.Nc / sh.BY) * (g.Nc / sh.BZ);
     const dim3 grid((unsigned)nb);
-    if (sh.BY == 2) launch_compact_yz<2>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, s);
-    else launch_compact_yz<1>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, s);
+    if (sh.BY == 2) launch_compact_yz<2>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, sc, s);
+    else launch_compact_yz<1>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, sc, s);
 }
 
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir, const uint32_t* far_key,

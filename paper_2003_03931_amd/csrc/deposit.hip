@@ -208,7 +208,8 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
 // Cells are visited in storage order (the +x, +y, +z neighbours are then
 // mostly 1, Tc and Tc^2 entries ahead); one atomic per workgroup.
 __global__ __launch_bounds__(256) void k_max_block8(Geom g, const int32_t* __restrict__ counts,
-                                                      int32_t* __restrict__ out) {
+                                                      int32_t* __restrict__ out, const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
     __shared__ int red[256 / kWave];
     const int64_t tc3 = (int64_t)g.Tc * g.Tc * g.Tc;
     int v = 0;
@@ -287,9 +288,16 @@ bool fine_deposit_needs_wide(const Geom& g, int max_block8) {
     return (double)max_block8 * std::ldexp(1.0, 3 * g.log2D) >= 4294967296.0;
 }
 
-void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s) {
+bool fp16_density_fits(const Geom& g, int max_block8) {
+    // a fine cell's density is at most f^3 times the particles of one 2 x 2 x 2
+    // block of coarse cells; the plane transform's gain is divided out
+    return (double)g.f * g.f * g.f * (double)max_block8 + 1.0 < 32768.0;
+}
+
+void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s, const int32_t* gate) {
     const int64_t want = (g.ncells + 255) / 256;
-    hipLaunchKernelGGL(k_max_block8, dim3((unsigned)std::min<int64_t>(want, 4096)), dim3(256), 0, s, g, counts, out);
+    hipLaunchKernelGGL(k_max_block8, dim3((unsigned)std::min<int64_t>(want, 4096)), dim3(256), 0, s, g, counts, out,
+                       gate);
 }
 
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, hipStream_t s) {

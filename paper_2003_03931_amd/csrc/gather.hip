@@ -137,6 +137,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     __shared__ double s_red[kGatherThreads / kWave];
     __shared__ float s_vc[3][VC ? kMaxRows * kMaxRowLen : 1];   // cell means of the brick's cells
 
+    // a halted step (see StepScalars) writes nothing
+    if (MODE == GATHER_STEP && *(volatile const int32_t*)&A.sc->halt) return;
     const Geom& g = A.g;
     const int r = g.r;
     const int BXc = kBX / r, BYc = kBY / r, BZc = kBZ / r;
@@ -435,7 +437,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             const int slot = (blockIdx.x + blockIdx.y * 7) & 63;
             if (bu) atomicMax(&A.sc->umax_slot[slot], bu);
             if (bc) atomicMax(&A.sc->cmax_slot[slot], bc);
-            if (bs) atomicAdd((unsigned long long*)&A.sc->saturations, (unsigned long long)bs);
+            if (bs) atomicAdd((unsigned long long*)&A.sc->sat_step, (unsigned long long)bs);
             if (bf) atomicAdd(&A.sc->far_count, bf);
         }
     } else if (MODE == GATHER_POTENTIAL) {

@@ -57,6 +57,16 @@ __host__ __device__ inline int wrapi(int x, int n) {
 }
 
 // Per-step scalars that live on the device so that nothing syncs mid-step.
+// A step's kernels that write the state or these scalars return at once
+// while `halt` is set; the host resolves a halt at its next synchronisation:
+//   1  the step needs the sorted general compaction (a particle moved more
+//      than one coarse cell, or a cell count exceeds the fast path's bound);
+//      everything up to the compaction is done and kept for it;
+//   2  a CUBE_MIXED_FP16 potential spectrum value left the FP16 range; the
+//      step is run again with FP32 spectra;
+//   3  the new state needs a wider fine-deposit accumulator or FP32 density
+//      spectra than the host planned for the next step; the step itself is
+//      complete, the following ones are enqueued again.
 struct StepScalars {
     double s;            // velocity scale of the state
     double s_next;       // scale after the coming kick
@@ -64,10 +74,15 @@ struct StepScalars {
     int32_t max_u_next;  // accumulated by the kick
     int32_t far_count;   // particles whose carry exceeds one cell
     int32_t max_carry;   // max |carry| of the step
-    int64_t saturations; // clamped velocity components (cumulative)
+    int64_t saturations; // clamped velocity components (cumulative, committed by the epilogue)
+    int64_t sat_step;    // clamped components of the running step
     int32_t overflow;    // a 16-bit spectrum value was out of range (cleared by the prologue)
-    int32_t max_count;   // largest cell count of the newest counts (set by the scan)
-    int32_t max_block8;  // largest count of a 2x2x2 block of coarse cells in the newest counts
+    int32_t max_count;   // largest cell count of the state
+    int32_t max_block8;  // largest count of a 2x2x2 block of coarse cells of the state
+    int32_t new_max_count;   // the same two of the step's new counts (set by the scan, adjacent)
+    int32_t new_max_block8;
+    int32_t halt;        // see above; 0 while steps run normally
+    int64_t steps_done;  // steps committed since the context was made
     // per-block maxima land in 64 slots (spreads atomic contention); the
     // epilogue folds them into max_u / max_carry
     int32_t umax_slot[64];
@@ -95,8 +110,9 @@ struct VelCells {
 // out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  If max_out
 // is given, atomicMax(max_out, max(in)) as well.
 size_t scan_workspace_bytes(int64_t n);
+// gate (optional): every kernel returns at once while *gate is nonzero.
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
-                        int32_t* max_out = nullptr);
+                        int32_t* max_out = nullptr, const int32_t* gate = nullptr);
 // out[0] += 64-bit sum of counts[0..n), out[1] = min(out[1], smallest count)
 // (out[0] = 0 and out[1] = INT64_MAX on entry)
 void launch_count_check(const int32_t* counts, int64_t n, long long* out, hipStream_t s);
@@ -126,7 +142,7 @@ void launch_count_keys(const uint32_t* key, int64_t n, int32_t* counts, hipStrea
 void vc_table_host(double* tab255);
 int vc_partials(const Geom& g);
 void launch_vc_encode(const Geom& g, const int32_t* offsets, Planes p, const VelCells& vcell,
-                      StepScalars* sc, double* partial, hipStream_t s);
+                      StepScalars* sc, double* partial, hipStream_t s, bool gated = false);
 
 // ---- deposit.hip --------------------------------------------------------
 void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
@@ -136,8 +152,10 @@ void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, floa
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
                          float* mesh, bool wide, hipStream_t s);
 bool fine_deposit_needs_wide(const Geom& g, int max_block8);
+bool fp16_density_fits(const Geom& g, int max_block8);
 // atomicMax(*out, largest count of a periodic 2 x 2 x 2 block of coarse cells)
-void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s);
+void launch_max_block8(const Geom& g, const int32_t* counts, int32_t* out, hipStream_t s,
+                       const int32_t* gate = nullptr);
 void launch_diag_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh,
                          hipStream_t s);
 
@@ -210,16 +228,30 @@ void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const ac
 
 // ---- compact.hip --------------------------------------------------------
 bool compact_supported(const Geom& g);
+// the fast path returns at once while sc->halt is set
 void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
-                         const uint8_t* dir, Planes src, Planes dst, hipStream_t s);
+                         const uint8_t* dir, Planes src, Planes dst, const StepScalars* sc, hipStream_t s);
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir,
                          const uint32_t* far_key, uint32_t* key, uint32_t* idx, hipStream_t s);
 void launch_permute_planes(const uint32_t* perm, Planes src, Planes dst, int64_t n, hipStream_t s);
 
 // ---- step.hip -----------------------------------------------------------
+// Prologue, decision, commit and epilogue of a step: all return at once while
+// sc->halt is set (the epilogue may set it, 3, after committing).
 void launch_step_prologue(StepScalars* sc, float v_headroom, hipStream_t s);
-void launch_step_epilogue(StepScalars* sc, hipStream_t s);
-void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// halt 2 on a spectrum overflow, else 1 when the fast compaction cannot run
+// (a far mover, or a cell count above fast_max_count in the old or new counts)
+void launch_step_decide(StepScalars* sc, int32_t fast_max_count, hipStream_t s);
+// counts <- counts_new, offsets <- offsets_new (ncells + 1 entries)
+void launch_commit_cells(const int32_t* counts_new, const int32_t* offsets_new, int32_t* counts, int32_t* offsets,
+                         int64_t ncells, const StepScalars* sc, hipStream_t s);
+// commit the scalars (s and max |u| only when vcodec == 0: the re-encode of
+// the cell-mean codec has set them); then halt 3 if the new state escapes the
+// plan of the next step (planned_wide: 64-bit fine-deposit accumulators;
+// planned_f16: FP16 density spectra)
+void launch_step_epilogue(StepScalars* sc, const Geom& g, int vcodec, bool planned_wide, bool planned_f16,
+                          hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s, const int32_t* gate = nullptr);
 void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,
                     const VelCells& vcell, double* partial, int nblocks, hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblocks, int width, double* out,

@@ -16,9 +16,12 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
+__device__ __forceinline__ bool gated(const int32_t* gate) { return gate && *(volatile const int32_t*)gate; }
+
 __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ in,
                                                              int64_t n, int32_t* __restrict__ sums,
-                                                             int32_t* __restrict__ max_out) {
+                                                             int32_t* __restrict__ max_out, const int32_t* gate) {
+    if (gated(gate)) return;
     __shared__ int lds[kScanThreads / kWave + 1];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int acc = 0, mx = 0;
@@ -49,7 +52,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __res
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in,
                                                              int64_t n, const int32_t* __restrict__ base_of_tile,
-                                                             int32_t* __restrict__ out) {
+                                                             int32_t* __restrict__ out, const int32_t* gate) {
+    if (gated(gate)) return;
     __shared__ int lds[kScanThreads / kWave + 1];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
@@ -93,7 +97,9 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __res
 
 // Single-block scan for short inputs (n <= kScanTile): out[0..n].
 __global__ __launch_bounds__(kScanThreads) void k_small_scan(const int32_t* __restrict__ in, int64_t n,
-                                                              int32_t* __restrict__ out, int32_t* __restrict__ max_out) {
+                                                              int32_t* __restrict__ out, int32_t* __restrict__ max_out,
+                                                              const int32_t* gate) {
+    if (gated(gate)) return;
     __shared__ int lds[kScanThreads / kWave + 1];
     const int64_t base = (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
@@ -160,9 +166,10 @@ size_t scan_workspace_bytes(int64_t n) {
     return bytes + 256;
 }
 
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s, int32_t* max_out) {
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s, int32_t* max_out,
+                        const int32_t* gate) {
     if (n <= kScanTile) {
-        hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kScanThreads), 0, s, in, n, out, max_out);
+        hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kScanThreads), 0, s, in, n, out, max_out, gate);
         return;
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -170,9 +177,9 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hi
     int32_t* sums = static_cast<int32_t*>(ws);
     int32_t* sums_scan = sums + round16(nb);
     void* rest = sums_scan + round16(nb + 1);
-    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums, max_out);
-    exclusive_scan_i32(sums, sums_scan, nb, rest, s);
-    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums_scan, out);
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums, max_out, gate);
+    exclusive_scan_i32(sums, sums_scan, nb, rest, s, nullptr, gate);
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums_scan, out, gate);
 }
 
 }  // namespace cube

@@ -6,6 +6,8 @@
 // Diagnostics: momentum and kinetic energy of the decoded velocities summed in
 // FP64 in a fixed order (per-chunk partials, then one ordered reduction);
 // power-spectrum shells binned in FP64.
+#include <cmath>
+
 #include "common.h"
 
 namespace cube {
@@ -18,8 +20,10 @@ __device__ double pow2ceil_d(double x) {
     return m == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
 }
 
+__device__ __forceinline__ bool halted(const StepScalars* sc) { return *(volatile const int32_t*)&sc->halt != 0; }
+
 __global__ void k_prologue(StepScalars* sc, float hv) {
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || halted(sc)) return;
     const int M = sc->max_u;
     const double s = sc->s;
     sc->s_next = (M == 0) ? s : pow2ceil_d(((double)hv * (double)M) * s / 127.0);
@@ -27,25 +31,61 @@ __global__ void k_prologue(StepScalars* sc, float hv) {
     sc->far_count = 0;
     sc->max_carry = 0;
     sc->overflow = 0;
+    sc->sat_step = 0;
     for (int i = 0; i < 64; ++i) {
         sc->umax_slot[i] = 0;
         sc->cmax_slot[i] = 0;
     }
 }
 
-__global__ void k_epilogue(StepScalars* sc) {
-    if (threadIdx.x != 0) return;
+__global__ void k_decide(StepScalars* sc, int32_t fast_max_count) {
+    if (threadIdx.x != 0 || halted(sc)) return;
+    if (sc->overflow) sc->halt = 2;
+    else if (sc->far_count > 0 || sc->max_count > fast_max_count || sc->new_max_count > fast_max_count) sc->halt = 1;
+}
+
+// counts <- counts_new and offsets <- offsets_new, 16 bytes at a time where aligned
+__global__ __launch_bounds__(256) void k_commit_cells(const int32_t* __restrict__ cn, const int32_t* __restrict__ on,
+                                                      int32_t* __restrict__ c, int32_t* __restrict__ o, int64_t ncells,
+                                                      const StepScalars* sc) {
+    if (halted(sc)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = ncells / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        reinterpret_cast<int4*>(c)[i] = reinterpret_cast<const int4*>(cn)[i];
+        reinterpret_cast<int4*>(o)[i] = reinterpret_cast<const int4*>(on)[i];
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= ncells; i += stride) {
+        if (i < ncells) c[i] = cn[i];
+        o[i] = on[i];
+    }
+}
+
+__global__ void k_epilogue(StepScalars* sc, int vcodec, int planned_wide, int planned_f16, double wide_cut,
+                           double f16_cut, double f3) {
+    if (threadIdx.x != 0 || halted(sc)) return;
     int um = sc->max_u_next, cm = sc->max_carry;
     for (int i = 0; i < 64; ++i) {
         um = max(um, sc->umax_slot[i]);
         cm = max(cm, sc->cmax_slot[i]);
     }
-    sc->s = sc->s_next;
-    sc->max_u = um;
+    if (!vcodec) {
+        sc->s = sc->s_next;
+        sc->max_u = um;
+    }
     sc->max_carry = cm;
+    sc->saturations += sc->sat_step;
+    sc->sat_step = 0;
+    sc->max_count = sc->new_max_count;
+    sc->max_block8 = sc->new_max_block8;
+    sc->steps_done += 1;
+    // the next step was enqueued for narrower accumulators or FP16 densities
+    const double b8 = (double)sc->max_block8;
+    if ((!planned_wide && b8 >= wide_cut) || (planned_f16 && f3 * b8 + 1.0 >= f16_cut)) sc->halt = 3;
 }
 
-__global__ void k_fill(int32_t* p, int32_t v, int64_t n) {
+__global__ void k_fill(int32_t* p, int32_t v, int64_t n, const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
@@ -140,14 +180,32 @@ void launch_step_prologue(StepScalars* sc, float v_headroom, hipStream_t s) {
     hipLaunchKernelGGL(k_prologue, dim3(1), dim3(64), 0, s, sc, v_headroom);
 }
 
-void launch_step_epilogue(StepScalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, sc);
+void launch_step_decide(StepScalars* sc, int32_t fast_max_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, sc, fast_max_count);
 }
 
-void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+void launch_commit_cells(const int32_t* counts_new, const int32_t* offsets_new, int32_t* counts, int32_t* offsets,
+                         int64_t ncells, const StepScalars* sc, hipStream_t s) {
+    unsigned blocks = grid1d(ncells / 4 + 1, 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_commit_cells, dim3(blocks), dim3(256), 0, s, counts_new, offsets_new, counts, offsets, ncells,
+                       sc);
+}
+
+void launch_step_epilogue(StepScalars* sc, const Geom& g, int vcodec, bool planned_wide, bool planned_f16,
+                          hipStream_t s) {
+    // 32-bit fine accumulators hold D^3 units per particle of a 2x2x2 block of
+    // coarse cells; FP16 density spectra hold f^3 per particle of such a block
+    const double wide_cut = std::ldexp(1.0, 32 - 3 * g.log2D);
+    const double f3 = (double)g.f * g.f * g.f;
+    hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, sc, vcodec, planned_wide ? 1 : 0, planned_f16 ? 1 : 0,
+                       wide_cut, 32768.0, f3);
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s, const int32_t* gate) {
     unsigned blocks = grid1d(n, 256);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, v, n, gate);
 }
 
 void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,

@@ -59,7 +59,8 @@ __device__ __forceinline__ int stage_offsets(const Geom& g, const int32_t* offse
 
 // cell means into vc; sum of squared deviations of the workgroup into partial
 __global__ __launch_bounds__(kCells) void k_vc_mean(Geom g, const int32_t* __restrict__ offsets, Planes p,
-                                                    VelCells vcell, double* __restrict__ partial) {
+                                                    VelCells vcell, double* __restrict__ partial, const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
     __shared__ int s_off[kCells + 1];
     __shared__ float s_v[3][kStage];
     __shared__ double red[kCells / kWave];
@@ -102,7 +103,8 @@ __global__ __launch_bounds__(kCells) void k_vc_mean(Geom g, const int32_t* __res
 
 // sigma from the per-workgroup sums (fixed order); max |u| restarts for the encode
 __global__ __launch_bounds__(kSigmaThreads) void k_vc_sigma(const double* __restrict__ partial, int nparts,
-                                                            int64_t ncomp, StepScalars* sc) {
+                                                            int64_t ncomp, StepScalars* sc, const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
     __shared__ double red[kSigmaThreads / kWave];
     double acc = 0.0;
     for (int b = threadIdx.x; b < nparts; b += kSigmaThreads) acc += partial[b];
@@ -121,7 +123,8 @@ __global__ __launch_bounds__(kSigmaThreads) void k_vc_sigma(const double* __rest
 }
 
 __global__ __launch_bounds__(kCells) void k_vc_encode(Geom g, const int32_t* __restrict__ offsets, Planes p,
-                                                      VelCells vcell, StepScalars* sc) {
+                                                      VelCells vcell, StepScalars* sc, const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
     __shared__ int s_off[kCells + 1];
     int64_t c0;
     const int nc = stage_offsets(g, offsets, s_off, c0);
@@ -161,11 +164,12 @@ void vc_table_host(double* tab) {
 int vc_partials(const Geom& g) { return (int)((g.ncells + kCells - 1) / kCells); }
 
 void launch_vc_encode(const Geom& g, const int32_t* offsets, Planes p, const VelCells& vcell, StepScalars* sc,
-                      double* partial, hipStream_t s) {
+                      double* partial, hipStream_t s, bool gated) {
+    const int32_t* gate = gated ? &sc->halt : nullptr;
     const int blocks = vc_partials(g);
-    hipLaunchKernelGGL(k_vc_mean, dim3((unsigned)blocks), dim3(kCells), 0, s, g, offsets, p, vcell, partial);
-    hipLaunchKernelGGL(k_vc_sigma, dim3(1), dim3(kSigmaThreads), 0, s, partial, blocks, 3 * g.n, sc);
-    hipLaunchKernelGGL(k_vc_encode, dim3((unsigned)blocks), dim3(kCells), 0, s, g, offsets, p, vcell, sc);
+    hipLaunchKernelGGL(k_vc_mean, dim3((unsigned)blocks), dim3(kCells), 0, s, g, offsets, p, vcell, partial, gate);
+    hipLaunchKernelGGL(k_vc_sigma, dim3(1), dim3(kSigmaThreads), 0, s, partial, blocks, 3 * g.n, sc, gate);
+    hipLaunchKernelGGL(k_vc_encode, dim3((unsigned)blocks), dim3(kCells), 0, s, g, offsets, p, vcell, sc, gate);
 }
 
 }  // namespace cube
