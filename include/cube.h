@@ -274,6 +274,20 @@ cube_status cube_decompress(cube_ctx* ctx, float* pos, float* vel, int64_t n,
  * step), CUBE_DEVICE. */
 cube_status cube_pm_step(cube_ctx* ctx, int32_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps as cube_pm_step, with the only temporaries a step can need (those
+ * of the sorted general compaction, 16 bytes per particle plus the sort's
+ * workspace) taken from a fixed region of 36 MiB that the library holds on
+ * each device for the life of the process, so no call allocates or frees.
+ * Boxes above 128^3 particles (more scratch than the region) are refused
+ * with CUBE_INVALID, as is a context with profiling on.  Every call on one
+ * device shares that region: calls that overlap on a device (two host
+ * threads, or contexts on different streams) race and must be serialised by
+ * the caller.  The region needs no clearing between calls (every word is
+ * written before it is read). */
+cube_status cube_pm_step_noalloc(cube_ctx* ctx, int32_t nsteps);
+
 /* Acceleration of every particle at the current state, no update: coarse
  * plus fine mesh force (Sec. II, Eq. (1)), plus the pair force when
  * pp_range > 0, in static units (the comoving kick factor is not applied).

@@ -141,6 +141,7 @@ SIGNATURES = {
     "cube_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_int32]),
     "cube_pm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cube_pm_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cube_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "cube_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StateView)]),
     "cube_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StateView)]),

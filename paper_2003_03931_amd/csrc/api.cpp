@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -261,6 +262,7 @@ struct cube_ctx {
     int32_t max_block8 = 0;           // largest count of a 2x2x2 block of coarse cells
     bool halted_recently = false;     // the last cube_pm_step met a halt: enqueue one step per sync
     int dbg_force[4] = {0, 0, 0, 0};  // cube_debug_force: steps still to receive each forced condition
+    void* noalloc_scratch = nullptr;  // this device's fixed scratch region (cube_pm_step_noalloc)
 
     ~cube_ctx() {
         if (sc_host) hipHostFree(sc_host);
@@ -703,6 +705,42 @@ cube_status run_steps(cube_ctx* c, int32_t nsteps, void* scratch) {
     return CUBE_OK;
 }
 
+// Fixed device region for the callers that cannot allocate
+// (cube_pm_step_noalloc): the temporaries of the sorted general compaction,
+// 16 bytes per particle plus the sort's workspace, for boxes up to 128^3
+// particles.  Each device holds its own copy for the life of the process;
+// host code reaches it only through the address resolved per device below.
+constexpr size_t kNoAllocScratchBytes = (size_t)36 << 20;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device
+// with that device current (nullptr if the runtime refused).
+void* noalloc_scratch_of_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_tried[dev]) {
+        g_scratch_tried[dev] = true;
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = ptr;
+        else (void)hipGetLastError();
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -739,6 +777,7 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     }
     const int64_t n = g.n;
     c->batch = batch_of(g, *desc);
+    c->noalloc_scratch = noalloc_scratch_of_current_device();
 
 #define CUBE_TRY(x)              \
     do {                         \
@@ -942,6 +981,24 @@ cube_status cube_pm_step(cube_ctx* c, int32_t nsteps) {
     if (nsteps < 0) return fail(CUBE_INVALID, "negative step count");
     auto t0 = std::chrono::steady_clock::now();
     st = run_steps(c, nsteps, nullptr);
+    auto t1 = std::chrono::steady_clock::now();
+    if (st == CUBE_OK && nsteps > 0)
+        c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
+    return st;
+}
+
+cube_status cube_pm_step_noalloc(cube_ctx* c, int32_t nsteps) {
+    cube_status st = check_ctx(c);
+    if (st != CUBE_OK) return st;
+    if (nsteps < 0) return fail(CUBE_INVALID, "negative step count");
+    if (general_scratch_bytes(c->g.n) > kNoAllocScratchBytes)
+        return fail(CUBE_INVALID, "cube_pm_step_noalloc: the box needs " + std::to_string(general_scratch_bytes(c->g.n)) +
+                                      " bytes of scratch, more than the fixed " +
+                                      std::to_string(kNoAllocScratchBytes) + " (boxes up to 128^3 particles)");
+    if (c->prof.on) return fail(CUBE_INVALID, "cube_pm_step_noalloc: profiling creates events; disable it");
+    if (!c->noalloc_scratch) return fail(CUBE_DEVICE, "cube_pm_step_noalloc: scratch address not resolved");
+    auto t0 = std::chrono::steady_clock::now();
+    st = run_steps(c, nsteps, c->noalloc_scratch);
     auto t1 = std::chrono::steady_clock::now();
     if (st == CUBE_OK && nsteps > 0)
         c->last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / nsteps;
