@@ -236,6 +236,8 @@ struct cube_ctx {
     VelCells vcell{};                 // cell-mean velocity codec: means and tan table
     uint8_t* dir = nullptr;
     uint32_t* far_key = nullptr;
+    uint4* ment = nullptr;            // mover records, one slot per particle
+    int4* mhdr = nullptr;             // per gather brick: row segments' record counts
     int32_t* counts = nullptr;
     int32_t* offsets = nullptr;
     int32_t* counts_new = nullptr;
@@ -385,6 +387,8 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
     }
     add(n);
     add(4 * n);
+    add(16 * n);                                           // mover records
+    add(16 * compact_bricks(g) * kGMaxRows);               // their brick headers
     for (int i = 0; i < 4; ++i) add(4 * cells);
     add(sizeof(StepScalars));
     add((int64_t)scan_workspace_bytes(cells));
@@ -534,6 +538,8 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt, int64_t step_index
     a.out = c->B;
     a.dir = c->dir;
     a.far_key = c->far_key;
+    a.ment = c->ment;
+    a.mhdr = c->mhdr;
     a.counts_new = c->counts_new;
     a.fine_real = c->fine_real;
     a.coarse = c->coarse;
@@ -584,18 +590,17 @@ void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
     exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &sc->new_max_count, &sc->halt);
     launch_max_block8(g, c->counts_new, &sc->new_max_block8, s, &sc->halt);
     if (P.on) P.add(ST_SCAN, es, P.mark(s), 8.0 * (double)g.ncells);
-    // the fast compaction's 16-bit counts and prefixes bound the old and new cell counts
     if (c->dbg_force[2] > 0) {
         --c->dbg_force[2];
         launch_fill_i32(&sc->far_count, 1, 1, s, &sc->halt);
     }
-    launch_step_decide(sc, 65535, s);
+    launch_step_decide(sc, INT_MAX, s);
     // with the cell-mean codec the kicked FP32 velocities move instead of codes
     Planes src = c->B, dst = c->A;
     if (g.vcodec)
         for (int k = 0; k < 3; ++k) src.u[k] = dst.u[k] = nullptr;
     hipEvent_t ec = P.on ? P.mark(s) : nullptr;
-    launch_compact_fast(g, c->offsets, c->offsets_new, c->dir, src, dst, sc, s);
+    launch_compact_bricks(g, c->offsets, c->offsets_new, c->dir, c->ment, c->mhdr, src, dst, sc, s);
     // 6 B + move code read, 6 B written, old and new offsets read
     if (P.on) P.add(ST_COMPACT, ec, P.mark(s), 13.0 * (double)g.n + 8.0 * (double)g.ncells);
     if (g.vcodec) {
@@ -823,6 +828,8 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     }
     CUBE_TRY(c->alloc_n(&c->dir, n));
     CUBE_TRY(c->alloc_n(&c->far_key, n));
+    CUBE_TRY(c->alloc_n(&c->ment, n));
+    CUBE_TRY(c->alloc_n(&c->mhdr, compact_bricks(g) * kGMaxRows));
     CUBE_TRY(c->alloc_n(&c->counts, g.ncells + 16));
     CUBE_TRY(c->alloc_n(&c->offsets, g.ncells + 16));
     CUBE_TRY(c->alloc_n(&c->counts_new, g.ncells + 16));

@@ -466,6 +466,224 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     }
 }
 
+// Brick compaction from the gather's mover records.  One workgroup per
+// gather brick D (tile-major numbering, XCD-aware).  The old storage order is
+// the canonical cell order, so for a destination cell c the stable counting
+// sort puts, in order of old index p: the particles arriving from cells
+// stored before c, then c's own stayers, then the arrivals from cells stored
+// after c.  Hence, with every arrival's old index p known,
+//   stayer of c, k-th among them:  new_offset[c] + #(arrivals with p < off_old[c]) + k
+//   arrival into c:                new_offset[c] + #(arrivals into c with smaller p)
+//                                  + (p >= off_old[c] ? stayers of c : 0)
+// with no distinction between tile faces, periodic wraps and interior cells.
+// The arrivals are D's own stay-in-brick records and the leaving records of
+// the 26 neighbour bricks whose move class points at D; stayers are D's own
+// particles with move code 13, ranked by a block scan per 256-particle chunk.
+// Bricks with more arrivals than the LDS list holds rank them from the
+// records in memory (slower, same result).
+constexpr int kKThreads = 256;
+constexpr int kInCap = 1024;
+
+template <int R>
+__global__ __launch_bounds__(kKThreads) void k_compact_brick(Geom g, const int32_t* __restrict__ off_old,
+                                                             const int32_t* __restrict__ off_new,
+                                                             const uint8_t* __restrict__ dir,
+                                                             const uint4* __restrict__ ment,
+                                                             const int4* __restrict__ mhdr, Planes src, Planes dst,
+                                                             const StepScalars* sc) {
+    if (*(volatile const int32_t*)&sc->halt) return;
+    constexpr int BXc = kGBX / R, BYc = kGBY / R, BZc = kGBZ / R;
+    constexpr int NROW = BYc * BZc, NCELL = BXc * NROW, NLIST = 27 * NROW;
+    static_assert(NROW <= kGMaxRows && NCELL <= 64, "brick shape");
+    __shared__ int s_oo[NROW][BXc + 1], s_on[NROW][BXc + 1];
+    __shared__ int s_rowpref[NROW + 1];
+    __shared__ int s_abefore[NCELL], s_stay[NCELL];
+    __shared__ int s_lbase[NLIST], s_lpref[NLIST + 1];
+    __shared__ uint8_t s_lcls[NLIST];
+    __shared__ uint4 s_in[kInCap];
+    __shared__ int s_nin;
+    __shared__ int s_incl[kKThreads];
+    __shared__ int s_scan[kKThreads / kWave + 1];
+
+    const int64_t lin = xcd_logical_block();
+    const int nbx = g.T / kGBX, nby = g.T / kGBY, nbz = g.T / kGBZ, bpt = nbx * nby * nbz;
+    const int tile = (int)(lin / bpt), b = (int)(lin - (int64_t)tile * bpt);
+    const int tx = tile % g.nt, ty = (tile / g.nt) % g.nt, tz = tile / (g.nt * g.nt);
+    // global brick coordinates and the brick's first coarse cell
+    const int gb[3] = {tx * nbx + b % nbx, ty * nby + (b / nbx) % nby, tz * nbz + b / (nbx * nby)};
+    const int c0[3] = {gb[0] * BXc, gb[1] * BYc, gb[2] * BZc};
+    const int NB[3] = {g.nt * nbx, g.nt * nby, g.nt * nbz};
+
+    for (int t = threadIdx.x; t < NROW * (BXc + 1); t += kKThreads) {
+        const int r = t / (BXc + 1), j = t - r * (BXc + 1);
+        const int64_t c = canon(g, c0[0], c0[1] + r % BYc, c0[2] + r / BYc) + j;
+        s_oo[r][j] = off_old[c];
+        s_on[r][j] = off_new[c];
+    }
+    // the 27 x NROW candidate lists: the own brick's stay-in-brick records
+    // (offset 13) and each neighbour's leaving records of the class pointing here
+    int lcount = 0;
+    if ((int)threadIdx.x < NLIST) {
+        const int o = threadIdx.x / NROW, r = threadIdx.x - o * NROW;
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        int sb[3] = {gb[0] + ox, gb[1] + oy, gb[2] + oz};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sb[k] = sb[k] < 0 ? sb[k] + NB[k] : (sb[k] >= NB[k] ? sb[k] - NB[k] : sb[k]);
+        const int stile = sb[0] / nbx + g.nt * (sb[1] / nby + g.nt * (sb[2] / nbz));
+        const int sbl = sb[0] % nbx + nbx * (sb[1] % nby + nby * (sb[2] % nbz));
+        const int4 h = mhdr[((int64_t)stile * bpt + sbl) * kGMaxRows + r];
+        if (o == 13) {
+            s_lbase[threadIdx.x] = h.x;
+            lcount = h.y;
+        } else {
+            s_lbase[threadIdx.x] = h.z - h.w;
+            lcount = h.w;
+        }
+        s_lcls[threadIdx.x] = (uint8_t)(26 - o);
+    }
+    {
+        int tot;
+        const int pre = block_exclusive_scan(lcount, s_scan, &tot);
+        if ((int)threadIdx.x < NLIST) s_lpref[threadIdx.x] = pre;
+        if (threadIdx.x == 0) {
+            s_lpref[NLIST] = tot;
+            s_nin = 0;
+        }
+    }
+    if ((int)threadIdx.x < NCELL) {
+        s_abefore[threadIdx.x] = 0;
+        s_stay[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_rowpref[0] = 0;
+        for (int r = 0; r < NROW; ++r) s_rowpref[r + 1] = s_rowpref[r] + (s_oo[r][BXc] - s_oo[r][0]);
+    }
+    // candidate records -> arrivals (those of the class pointing at this brick)
+    const int ncand = s_lpref[NLIST];
+    auto cand = [&](int i, uint4& rec) -> bool {
+        const int l = find_cell_fixed<(NLIST > 128 ? 8 : 7)>(s_lpref, NLIST, i);
+        rec = ment[s_lbase[l] + (i - s_lpref[l])];
+        return (int)((rec.y >> 8) & 31) == (int)s_lcls[l];
+    };
+    for (int i = threadIdx.x; i < ncand; i += kKThreads) {
+        uint4 rec;
+        if (cand(i, rec)) {
+            const int k = atomicAdd(&s_nin, 1);
+            if (k < kInCap) s_in[k] = rec;
+        }
+    }
+    __syncthreads();
+    const int nin = s_nin;
+    const bool listed = nin <= kInCap;
+    // oo / on of a brick cell d (row-major in the brick)
+    auto oo_of = [&](int d) { return s_oo[d / BXc][d % BXc]; };
+    // arrivals from cells stored before each destination cell
+    if (listed) {
+        for (int i = threadIdx.x; i < nin; i += kKThreads) {
+            const int d = (int)(s_in[i].y & 255);
+            if ((int)s_in[i].x < oo_of(d)) atomicAdd(&s_abefore[d], 1);
+        }
+    } else {
+        for (int i = threadIdx.x; i < ncand; i += kKThreads) {
+            uint4 rec;
+            if (cand(i, rec)) {
+                const int d = (int)(rec.y & 255);
+                if ((int)rec.x < oo_of(d)) atomicAdd(&s_abefore[d], 1);
+            }
+        }
+    }
+    __syncthreads();
+
+    // own particles, 256 at a time in storage order: stayers keep their
+    // order within their cell and are written straight to their new slot
+    const int nown = s_rowpref[NROW];
+    const bool cp_u = src.u[0] != nullptr, cp_v = src.v[0] != nullptr, cp_id = dst.ids != nullptr;
+    for (int base = 0; base < nown; base += kKThreads) {
+        const int e = base + (int)threadIdx.x;
+        int row = 0, x = 0, p = -1, stay = 0, first = 0, cl = 0;
+        if (e < nown) {
+            row = find_cell_fixed<3>(s_rowpref, NROW, e);
+            p = s_oo[row][0] + (e - s_rowpref[row]);
+            x = find_cell_fixed<3>(s_oo[row], BXc, p);
+            cl = x + BXc * row;
+            stay = dir[p] == 13 ? 1 : 0;
+            // first chunk position of this particle's cell
+            const int cell_e = s_rowpref[row] + (s_oo[row][x] - s_oo[row][0]);
+            first = max(cell_e, base) - base;
+        }
+        int tot;
+        const int excl = block_exclusive_scan(stay, s_scan, &tot);
+        s_incl[threadIdx.x] = excl + stay;
+        __syncthreads();
+        if (e < nown && stay) {
+            const int before = first > 0 ? s_incl[first - 1] : 0;
+            const int k = s_stay[cl] + (excl - before);
+            const int o = s_on[row][x] + s_abefore[cl] + k;
+            if (o >= 0 && o < g.n)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dst.m[a][o] = src.m[a][p];
+                if (cp_u) dst.u[a][o] = src.u[a][p];
+                if (cp_v) dst.v[a][o] = src.v[a][p];
+            }
+            if (cp_id && o >= 0 && o < g.n) dst.ids[o] = src.ids[p];
+        }
+        __syncthreads();
+        // the last particle of each cell's run in this chunk carries the count on
+        if (e < nown) {
+            const int cell_end_e = s_rowpref[row] + (s_oo[row][x + 1] - s_oo[row][0]);
+            const bool last = e == nown - 1 || e == base + kKThreads - 1 || e + 1 == cell_end_e;
+            if (last) s_stay[cl] += s_incl[threadIdx.x] - (first > 0 ? s_incl[first - 1] : 0);
+        }
+        __syncthreads();
+    }
+
+    // arrivals: rank among the arrivals into the same cell by old index
+    auto place = [&](const uint4& rec, int rank) {
+        const int d = (int)(rec.y & 255), p = (int)rec.x;
+        const int row = d / BXc, x = d - row * BXc;
+        const int o = s_on[row][x] + rank + (p >= s_oo[row][x] ? s_stay[d] : 0);
+        if (o < 0 || o >= g.n || p < 0 || p >= g.n) return;
+        dst.m[0][o] = (uint8_t)(rec.z & 255);
+        dst.m[1][o] = (uint8_t)((rec.z >> 8) & 255);
+        dst.m[2][o] = (uint8_t)((rec.z >> 16) & 255);
+        if (cp_u) {
+            dst.u[0][o] = (int8_t)(rec.w & 255);
+            dst.u[1][o] = (int8_t)((rec.w >> 8) & 255);
+            dst.u[2][o] = (int8_t)((rec.w >> 16) & 255);
+        }
+        if (cp_v)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dst.v[a][o] = src.v[a][p];
+        if (cp_id) dst.ids[o] = src.ids[p];
+    };
+    if (listed) {
+        for (int i = threadIdx.x; i < nin; i += kKThreads) {
+            const uint4 rec = s_in[i];
+            const int d = (int)(rec.y & 255);
+            int rank = 0;
+            for (int j = 0; j < nin; ++j) {
+                const uint4 q = s_in[j];
+                rank += ((int)(q.y & 255) == d && q.x < rec.x) ? 1 : 0;
+            }
+            place(rec, rank);
+        }
+    } else {
+        for (int i = threadIdx.x; i < ncand; i += kKThreads) {
+            uint4 rec;
+            if (!cand(i, rec)) continue;
+            const int d = (int)(rec.y & 255);
+            int rank = 0;
+            for (int j = 0; j < ncand; ++j) {
+                uint4 q;
+                if (cand(j, q)) rank += ((int)(q.y & 255) == d && q.x < rec.x) ? 1 : 0;
+            }
+            place(rec, rank);
+        }
+    }
+}
+
 // keys of the general path: new canonical cell of every particle, old order
 __global__ __launch_bounds__(256) void k_general_keys(Geom g, const int32_t* __restrict__ offsets,
                                                        const uint8_t* __restrict__ dir,
@@ -541,6 +759,22 @@ void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_
     const dim3 grid((unsigned)nb);
     if (sh.BY == 2) launch_compact_yz<2>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, sc, s);
     else launch_compact_yz<1>(sh.BX, grid, g, offsets_old, offsets_new, dir, src, dst, sc, s);
+}
+
+int64_t compact_bricks(const Geom& g) {
+    return (int64_t)g.ntiles * (g.T / kGBX) * (g.T / kGBY) * (g.T / kGBZ);
+}
+
+void launch_compact_bricks(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
+                           const uint8_t* dir, const uint4* ment, const int4* mhdr, Planes src, Planes dst,
+                           const StepScalars* sc, hipStream_t s) {
+    const dim3 grid((unsigned)compact_bricks(g));
+    if (g.r == 4)
+        hipLaunchKernelGGL(k_compact_brick<4>, grid, dim3(kKThreads), 0, s, g, offsets_old, offsets_new, dir, ment,
+                           mhdr, src, dst, sc);
+    else
+        hipLaunchKernelGGL(k_compact_brick<8>, grid, dim3(kKThreads), 0, s, g, offsets_old, offsets_new, dir, ment,
+                           mhdr, src, dst, sc);
 }
 
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir, const uint32_t* far_key,

@@ -29,11 +29,12 @@ namespace cube {
 
 namespace {
 
-constexpr int kBX = 32, kBY = 16, kBZ = 8;              // brick, fine cells
+constexpr int kBX = kGBX, kBY = kGBY, kBZ = kGBZ;       // brick, fine cells
 constexpr int kMinR = 4;                                 // coarse cells of >= 4 fine cells
 constexpr int kMaxRows = (kBY / kMinR) * (kBZ / kMinR);
 constexpr int kMaxRowLen = kBX / kMinR;
 static_assert(kMaxRows <= 8 && kMaxRowLen <= 8, "fixed three-step searches of rows and cells");
+static_assert(kMaxRows <= kGMaxRows, "mover headers hold kGMaxRows row segments per brick");
 constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
 constexpr int kGatherThreads = 256;
 
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     __shared__ int s_scan[kGatherThreads / kWave + 1];
     __shared__ double s_red[kGatherThreads / kWave];
     __shared__ float s_vc[3][VC ? kMaxRows * kMaxRowLen : 1];   // cell means of the brick's cells
+    __shared__ int s_mfront[kMaxRows], s_mback[kMaxRows];       // movers staying in / leaving the brick, per row
 
     // a halted step (see StepScalars) writes nothing
     if (MODE == GATHER_STEP && *(volatile const int32_t*)&A.sc->halt) return;
@@ -244,8 +246,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         if (e < nrowoff) s_rowoff[e / (BXc + 1)][e % (BXc + 1)] = rv[u];
     }
     const int HX = BXc + 2, HY = BYc + 2, HZ = BZc + 2;
-    if (MODE == GATHER_STEP)
+    if (MODE == GATHER_STEP) {
         for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) s_hist[e] = 0;
+        if ((int)threadIdx.x < kMaxRows) {
+            s_mfront[threadIdx.x] = 0;
+            s_mback[threadIdx.x] = 0;
+        }
+    }
     if constexpr (VC) {
         const int nbc = BXc * BYc * BZc;
         for (int e = threadIdx.x; e < 3 * nbc; e += kGatherThreads) {
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             for (int a = 0; a < 3; ++a) A.acc[3 * (int64_t)p + a] = acc[a];
             continue;
         }
-        int un[3], carry[3];
+        int un[3] = {0, 0, 0}, carry[3], mnew[3];
         if constexpr (VC) {
             // decode v_c + sigma tan(u pi / 255), kick in FP64 (one rounding per
             // operation), hold in FP32, drift by it (exact FP64)
@@ -360,7 +367,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
                 const double X = ((double)m[a] + 0.5) + ((double)v32 * q256H) * drift;
                 const int qq = (int)floor(X);
                 carry[a] = qq >> 8;
-                A.out.m[a][p] = (uint8_t)(qq & 255);
+                mnew[a] = qq & 255;
+                A.out.m[a][p] = (uint8_t)mnew[a];
                 cmax = max(cmax, abs(carry[a]));
             }
         } else {
@@ -376,7 +384,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             const double X = ((double)m[a] + 0.5) + (((double)un[a] * s_next) * q256H) * drift;
             const int qq = (int)floor(X);
             carry[a] = qq >> 8;                  // floor division by 256
-            A.out.m[a][p] = (uint8_t)(qq & 255);
+            mnew[a] = qq & 255;
+            A.out.m[a][p] = (uint8_t)mnew[a];
             A.out.u[a][p] = (int8_t)un[a];
             cmax = max(cmax, abs(carry[a]));
         }
@@ -384,9 +393,31 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         if (A.out.ids) A.out.ids[p] = A.in.ids[p];
         const bool near = abs(carry[0]) <= 1 && abs(carry[1]) <= 1 && abs(carry[2]) <= 1;
         if (near) {
-            A.dir[p] = (uint8_t)((carry[0] + 1) + 3 * (carry[1] + 1) + 9 * (carry[2] + 1));
+            const int code = (carry[0] + 1) + 3 * (carry[1] + 1) + 9 * (carry[2] + 1);
+            A.dir[p] = (uint8_t)code;
             const int hx = lcell[0] + carry[0] + 1, hy = lcell[1] + carry[1] + 1, hz = lcell[2] + carry[2] + 1;
             atomicAdd(&s_hist[(hz * HY + hy) * HX + hx], 1);
+            if (code != 13) {
+                // mover record in its row segment's own slots: movers that
+                // stay in the brick from the front, the others from the back
+                const int nx = hx - 1, ny = hy - 1, nz = hz - 1;          // brick-relative new cell, -1..B
+                const int bdx = nx < 0 ? -1 : (nx >= BXc ? 1 : 0), bdy = ny < 0 ? -1 : (ny >= BYc ? 1 : 0);
+                const int bdz = nz < 0 ? -1 : (nz >= BZc ? 1 : 0);
+                const int cls = (bdx + 1) + 3 * (bdy + 1) + 9 * (bdz + 1);
+                const int dl = (nx - bdx * BXc) + BXc * ((ny - bdy * BYc) + BYc * (nz - bdz * BZc));
+                const int row = lcell[1] + BYc * lcell[2];
+                const int slot = cls == 13 ? s_rowoff[row][0] + atomicAdd(&s_mfront[row], 1)
+                                           : s_rowoff[row][BXc] - 1 - atomicAdd(&s_mback[row], 1);
+                uint4 rec;
+                rec.x = (uint32_t)p;
+                rec.y = (uint32_t)dl | ((uint32_t)cls << 8);
+                rec.z = (uint32_t)mnew[0] | ((uint32_t)mnew[1] << 8) | ((uint32_t)mnew[2] << 16);
+                rec.w = 0;
+                if constexpr (!VC)
+                    rec.w = (uint32_t)(uint8_t)un[0] | ((uint32_t)(uint8_t)un[1] << 8) |
+                            ((uint32_t)(uint8_t)un[2] << 16);
+                A.ment[slot] = rec;
+            }
         } else {
             const int64_t cn = canon(g, wrapi(gc[0] + lcell[0] + carry[0], g.Nc),
                                      wrapi(gc[1] + lcell[1] + carry[1], g.Nc),
@@ -400,6 +431,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
 
     if (MODE == GATHER_STEP) {
         __syncthreads();
+        if ((int)threadIdx.x < kGMaxRows) {
+            // this brick's row segments: [start, start + front) and [end - back, end)
+            const int r = threadIdx.x;
+            int4 h = make_int4(0, 0, 0, 0);
+            if (r < nrows) h = make_int4(s_rowoff[r][0], s_mfront[r], s_rowoff[r][BXc], s_mback[r]);
+            A.mhdr[((int64_t)tile * gridDim.x + b) * kGMaxRows + r] = h;
+        }
         for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) {
             const int c = s_hist[e];
             if (c) {

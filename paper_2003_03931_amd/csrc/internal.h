@@ -68,6 +68,10 @@ __host__ __device__ inline int wrapi(int x, int n) {
 //      spectra than the host planned for the next step; the step itself is
 //      complete, the following ones are enqueued again.
 struct StepScalars {
+    // read by every block of a step's kernels; kept off the lines that the
+    // per-block atomics below update, or each read queues behind them
+    int32_t halt;        // see above; 0 while steps run normally
+    int32_t pad_[63];
     double s;            // velocity scale of the state
     double s_next;       // scale after the coming kick
     int32_t max_u;       // max |u| of the state
@@ -81,7 +85,6 @@ struct StepScalars {
     int32_t max_block8;  // largest count of a 2x2x2 block of coarse cells of the state
     int32_t new_max_count;   // the same two of the step's new counts (set by the scan, adjacent)
     int32_t new_max_block8;
-    int32_t halt;        // see above; 0 while steps run normally
     int64_t steps_done;  // steps committed since the context was made
     // per-block maxima land in 64 slots (spreads atomic contention); the
     // epilogue folds them into max_u / max_carry
@@ -192,6 +195,13 @@ void build_coarse_green(const Geom& g, double* octant, hipStream_t s);
 void build_fine_green(const Geom& g, float* octant, void* ws, hipStream_t s);
 size_t fine_green_workspace_bytes(const Geom& g);
 
+// ---- gather bricks --------------------------------------------------------
+// The gather and the compaction share one decomposition: bricks of 32 x 16 x 8
+// fine cells, whole coarse cells (r = 4 or 8), kGMaxRows row segments of
+// coarse cells along x at most, numbered tile-major (tile, then x fastest).
+constexpr int kGBX = 32, kGBY = 16, kGBZ = 8;
+constexpr int kGMaxRows = 8;
+
 // ---- gather.hip ---------------------------------------------------------
 // floats allocated after the last fine mesh of a batch: the gather stages
 // rows as aligned float2s and may read one float past a row's end
@@ -212,6 +222,8 @@ struct GatherArgs {
     const float* pp[3];     // GATHER_STEP / GATHER_FORCE: PP accelerations to add (null: none)
     float* acc;             // GATHER_FORCE: [n][3]
     double* partial;        // GATHER_POTENTIAL: per-block partial sums
+    uint4* ment;            // GATHER_STEP: mover records (one slot per particle, see compact.hip)
+    int4* mhdr;             // GATHER_STEP: per brick and row segment: start, stay-in-brick movers, end, leaving movers
     double kick;            // GATHER_STEP: force multiplier of the kick (dt, or K_n comoving)
     float drift;            // GATHER_STEP: velocity multiplier of the drift (dt, or FP32 D_n)
     int tile0;
@@ -231,6 +243,11 @@ bool compact_supported(const Geom& g);
 // the fast path returns at once while sc->halt is set
 void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
                          const uint8_t* dir, Planes src, Planes dst, const StepScalars* sc, hipStream_t s);
+// the brick compaction from the gather's mover records (same result)
+int64_t compact_bricks(const Geom& g);
+void launch_compact_bricks(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
+                           const uint8_t* dir, const uint4* ment, const int4* mhdr, Planes src, Planes dst,
+                           const StepScalars* sc, hipStream_t s);
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir,
                          const uint32_t* far_key, uint32_t* key, uint32_t* idx, hipStream_t s);
 void launch_permute_planes(const uint32_t* perm, Planes src, Planes dst, int64_t n, hipStream_t s);
