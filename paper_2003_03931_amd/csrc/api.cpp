@@ -237,7 +237,8 @@ struct cube_ctx {
     uint8_t* dir = nullptr;
     uint32_t* far_key = nullptr;
     uint4* ment = nullptr;            // mover records, one slot per particle
-    int4* mhdr = nullptr;             // per gather brick: row segments' record counts
+    int32_t* mhdr = nullptr;          // per gather brick: first record slot and per-class offsets
+    int32_t* tcursor = nullptr;       // per tile: record slots taken in the running step
     int32_t* counts = nullptr;
     int32_t* offsets = nullptr;
     int32_t* counts_new = nullptr;
@@ -388,7 +389,8 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
     add(n);
     add(4 * n);
     add(16 * n);                                           // mover records
-    add(16 * compact_bricks(g) * kGMaxRows);               // their brick headers
+    add(4 * compact_bricks(g) * kHdrInts);                 // their brick headers
+    add(4 * g.ntiles);                                     // per-tile record cursors
     for (int i = 0; i < 4; ++i) add(4 * cells);
     add(sizeof(StepScalars));
     add((int64_t)scan_workspace_bytes(cells));
@@ -540,6 +542,7 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt, int64_t step_index
     a.far_key = c->far_key;
     a.ment = c->ment;
     a.mhdr = c->mhdr;
+    a.tcursor = c->tcursor;
     a.counts_new = c->counts_new;
     a.fine_real = c->fine_real;
     a.coarse = c->coarse;
@@ -564,6 +567,7 @@ void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
     StepScalars* sc = c->sc;
     launch_step_prologue(sc, c->desc.v_headroom, s);
     launch_fill_i32(c->counts_new, 0, g.ncells, s, &sc->halt);
+    launch_strided_copy(c->offsets, (int64_t)g.Tc * g.Tc * g.Tc, c->tcursor, g.ntiles, s, &sc->halt);
     coarse_potential(c);
     Profiler& P = c->prof;
     pp_forces(c);
@@ -829,7 +833,8 @@ cube_status cube_init(const cube_box_desc* desc, const cube_allocator* alloc, vo
     CUBE_TRY(c->alloc_n(&c->dir, n));
     CUBE_TRY(c->alloc_n(&c->far_key, n));
     CUBE_TRY(c->alloc_n(&c->ment, n));
-    CUBE_TRY(c->alloc_n(&c->mhdr, compact_bricks(g) * kGMaxRows));
+    CUBE_TRY(c->alloc_n(&c->mhdr, compact_bricks(g) * kHdrInts));
+    CUBE_TRY(c->alloc_n(&c->tcursor, g.ntiles));
     CUBE_TRY(c->alloc_n(&c->counts, g.ncells + 16));
     CUBE_TRY(c->alloc_n(&c->offsets, g.ncells + 16));
     CUBE_TRY(c->alloc_n(&c->counts_new, g.ncells + 16));

@@ -466,45 +466,44 @@ __global__ __launch_bounds__(kCThreads) void k_compact_fast(Geom g, const int32_
     }
 }
 
-// Brick compaction from the gather's mover records.  One workgroup per
-// gather brick D (tile-major numbering, XCD-aware).  The old storage order is
-// the canonical cell order, so for a destination cell c the stable counting
-// sort puts, in order of old index p: the particles arriving from cells
-// stored before c, then c's own stayers, then the arrivals from cells stored
-// after c.  Hence, with every arrival's old index p known,
+// Brick compaction from the gather's mover records.  One wave per gather
+// brick D (tile-major numbering, XCD-aware).  The old storage order is the
+// canonical cell order, so for a destination cell c the stable counting sort
+// puts, in order of old index p: the particles arriving from cells stored
+// before c, then c's own stayers, then the arrivals from cells stored after
+// c.  Hence, with every arrival's old index p known,
 //   stayer of c, k-th among them:  new_offset[c] + #(arrivals with p < off_old[c]) + k
 //   arrival into c:                new_offset[c] + #(arrivals into c with smaller p)
 //                                  + (p >= off_old[c] ? stayers of c : 0)
 // with no distinction between tile faces, periodic wraps and interior cells.
-// The arrivals are D's own stay-in-brick records and the leaving records of
-// the 26 neighbour bricks whose move class points at D; stayers are D's own
-// particles with move code 13, ranked by a block scan per 256-particle chunk.
-// Bricks with more arrivals than the LDS list holds rank them from the
-// records in memory (slower, same result).
-constexpr int kKThreads = 256;
-constexpr int kInCap = 1024;
+// The arrivals are the records of class "towards D" of D and its 26
+// neighbours (the gather groups each brick's records by class); stayers are
+// D's own particles with move code 13, ranked by a wave scan per 64.
+// The work per brick is a handful of short dependent phases, so every load
+// of a phase is issued before the first is used, and a small LDS footprint
+// keeps many bricks in flight per CU.  Bricks with more arrivals than the
+// LDS list holds rank them from the records in memory (slower, same result).
+constexpr int kKThreads = kWave;
+constexpr int kInCap = 192;
 
 template <int R>
 __global__ __launch_bounds__(kKThreads) void k_compact_brick(Geom g, const int32_t* __restrict__ off_old,
                                                              const int32_t* __restrict__ off_new,
                                                              const uint8_t* __restrict__ dir,
                                                              const uint4* __restrict__ ment,
-                                                             const int4* __restrict__ mhdr, Planes src, Planes dst,
-                                                             const StepScalars* sc) {
+                                                             const int32_t* __restrict__ mhdr, Planes src,
+                                                             Planes dst, const StepScalars* sc) {
     if (*(volatile const int32_t*)&sc->halt) return;
     constexpr int BXc = kGBX / R, BYc = kGBY / R, BZc = kGBZ / R;
-    constexpr int NROW = BYc * BZc, NCELL = BXc * NROW, NLIST = 27 * NROW;
-    static_assert(NROW <= kGMaxRows && NCELL <= 64, "brick shape");
+    constexpr int NROW = BYc * BZc, NCELL = BXc * NROW;
+    static_assert(NCELL <= kWave && NROW <= 8 && BXc <= 8, "brick shape");
     __shared__ int s_oo[NROW][BXc + 1], s_on[NROW][BXc + 1];
     __shared__ int s_rowpref[NROW + 1];
     __shared__ int s_abefore[NCELL], s_stay[NCELL];
-    __shared__ int s_lbase[NLIST], s_lpref[NLIST + 1];
-    __shared__ uint8_t s_lcls[NLIST];
+    __shared__ int s_lbase[27], s_lpref[28];
     __shared__ uint4 s_in[kInCap];
-    __shared__ int s_nin;
-    __shared__ int s_incl[kKThreads];
-    __shared__ int s_scan[kKThreads / kWave + 1];
 
+    const int lane = (int)threadIdx.x;
     const int64_t lin = xcd_logical_block();
     const int nbx = g.T / kGBX, nby = g.T / kGBY, nbz = g.T / kGBZ, bpt = nbx * nby * nbz;
     const int tile = (int)(lin / bpt), b = (int)(lin - (int64_t)tile * bpt);
@@ -514,137 +513,157 @@ __global__ __launch_bounds__(kKThreads) void k_compact_brick(Geom g, const int32
     const int c0[3] = {gb[0] * BXc, gb[1] * BYc, gb[2] * BZc};
     const int NB[3] = {g.nt * nbx, g.nt * nby, g.nt * nbz};
 
-    for (int t = threadIdx.x; t < NROW * (BXc + 1); t += kKThreads) {
+    for (int t = lane; t < NROW * (BXc + 1); t += kKThreads) {
         const int r = t / (BXc + 1), j = t - r * (BXc + 1);
         const int64_t c = canon(g, c0[0], c0[1] + r % BYc, c0[2] + r / BYc) + j;
         s_oo[r][j] = off_old[c];
         s_on[r][j] = off_new[c];
     }
-    // the 27 x NROW candidate lists: the own brick's stay-in-brick records
-    // (offset 13) and each neighbour's leaving records of the class pointing here
-    int lcount = 0;
-    if ((int)threadIdx.x < NLIST) {
-        const int o = threadIdx.x / NROW, r = threadIdx.x - o * NROW;
-        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        int sb[3] = {gb[0] + ox, gb[1] + oy, gb[2] + oz};
+    // the brick at offset o sends the records of class 26 - o here
+    int cnt = 0;
+    if (lane < 27) {
+        const int o = lane;
+        int sb[3] = {gb[0] + o % 3 - 1, gb[1] + (o / 3) % 3 - 1, gb[2] + o / 9 - 1};
 #pragma unroll
         for (int k = 0; k < 3; ++k) sb[k] = sb[k] < 0 ? sb[k] + NB[k] : (sb[k] >= NB[k] ? sb[k] - NB[k] : sb[k]);
         const int stile = sb[0] / nbx + g.nt * (sb[1] / nby + g.nt * (sb[2] / nbz));
         const int sbl = sb[0] % nbx + nbx * (sb[1] % nby + nby * (sb[2] % nbz));
-        const int4 h = mhdr[((int64_t)stile * bpt + sbl) * kGMaxRows + r];
-        if (o == 13) {
-            s_lbase[threadIdx.x] = h.x;
-            lcount = h.y;
-        } else {
-            s_lbase[threadIdx.x] = h.z - h.w;
-            lcount = h.w;
-        }
-        s_lcls[threadIdx.x] = (uint8_t)(26 - o);
+        const int32_t* h = mhdr + ((int64_t)stile * bpt + sbl) * kHdrInts;
+        const int c = 26 - o;
+        const int lo = h[1 + c], hi = h[2 + c];
+        s_lbase[o] = h[0] + lo;
+        cnt = hi - lo;
     }
     {
-        int tot;
-        const int pre = block_exclusive_scan(lcount, s_scan, &tot);
-        if ((int)threadIdx.x < NLIST) s_lpref[threadIdx.x] = pre;
-        if (threadIdx.x == 0) {
-            s_lpref[NLIST] = tot;
-            s_nin = 0;
-        }
+        const int incl = wave_inclusive_scan(cnt);
+        if (lane < 27) s_lpref[lane] = incl - cnt;
+        if (lane == 26) s_lpref[27] = incl;
     }
-    if ((int)threadIdx.x < NCELL) {
-        s_abefore[threadIdx.x] = 0;
-        s_stay[threadIdx.x] = 0;
+    if (lane < NCELL) {
+        s_abefore[lane] = 0;
+        s_stay[lane] = 0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         s_rowpref[0] = 0;
         for (int r = 0; r < NROW; ++r) s_rowpref[r + 1] = s_rowpref[r] + (s_oo[r][BXc] - s_oo[r][0]);
     }
-    // candidate records -> arrivals (those of the class pointing at this brick)
-    const int ncand = s_lpref[NLIST];
-    auto cand = [&](int i, uint4& rec) -> bool {
-        const int l = find_cell_fixed<(NLIST > 128 ? 8 : 7)>(s_lpref, NLIST, i);
-        rec = ment[s_lbase[l] + (i - s_lpref[l])];
-        return (int)((rec.y >> 8) & 31) == (int)s_lcls[l];
+    const int nin = s_lpref[27];
+    const bool listed = nin <= kInCap;
+    auto arrival = [&](int i) -> uint4 {
+        const int l = find_cell_fixed<5>(s_lpref, 27, i);
+        return ment[s_lbase[l] + (i - s_lpref[l])];
     };
-    for (int i = threadIdx.x; i < ncand; i += kKThreads) {
-        uint4 rec;
-        if (cand(i, rec)) {
-            const int k = atomicAdd(&s_nin, 1);
-            if (k < kInCap) s_in[k] = rec;
+    if (listed) {
+        constexpr int UC = 3;                      // record loads in flight per lane
+        for (int i0 = 0; i0 < nin; i0 += UC * kKThreads) {
+            uint4 rec[UC];
+#pragma unroll
+            for (int u = 0; u < UC; ++u) {
+                const int i = i0 + u * kKThreads + lane;
+                if (i < nin) rec[u] = arrival(i);
+            }
+#pragma unroll
+            for (int u = 0; u < UC; ++u) {
+                const int i = i0 + u * kKThreads + lane;
+                if (i < nin) s_in[i] = rec[u];
+            }
         }
     }
     __syncthreads();
-    const int nin = s_nin;
-    const bool listed = nin <= kInCap;
-    // oo / on of a brick cell d (row-major in the brick)
     auto oo_of = [&](int d) { return s_oo[d / BXc][d % BXc]; };
     // arrivals from cells stored before each destination cell
-    if (listed) {
-        for (int i = threadIdx.x; i < nin; i += kKThreads) {
-            const int d = (int)(s_in[i].y & 255);
-            if ((int)s_in[i].x < oo_of(d)) atomicAdd(&s_abefore[d], 1);
-        }
-    } else {
-        for (int i = threadIdx.x; i < ncand; i += kKThreads) {
-            uint4 rec;
-            if (cand(i, rec)) {
-                const int d = (int)(rec.y & 255);
-                if ((int)rec.x < oo_of(d)) atomicAdd(&s_abefore[d], 1);
-            }
-        }
+    for (int i = lane; i < nin; i += kKThreads) {
+        const uint4 rec = listed ? s_in[i] : arrival(i);
+        const int d = (int)(rec.y & 255);
+        if ((int)rec.x < oo_of(d)) atomicAdd(&s_abefore[d], 1);
     }
     __syncthreads();
 
-    // own particles, 256 at a time in storage order: stayers keep their
-    // order within their cell and are written straight to their new slot
+    // own particles in storage order, U chunks of 64 per round with every
+    // load of the round in flight before the first is used: stayers keep
+    // their order within their cell and are written straight to their slot
     const int nown = s_rowpref[NROW];
     const bool cp_u = src.u[0] != nullptr, cp_v = src.v[0] != nullptr, cp_id = dst.ids != nullptr;
-    for (int base = 0; base < nown; base += kKThreads) {
-        const int e = base + (int)threadIdx.x;
-        int row = 0, x = 0, p = -1, stay = 0, first = 0, cl = 0;
-        if (e < nown) {
-            row = find_cell_fixed<3>(s_rowpref, NROW, e);
-            p = s_oo[row][0] + (e - s_rowpref[row]);
-            x = find_cell_fixed<3>(s_oo[row], BXc, p);
-            cl = x + BXc * row;
-            stay = dir[p] == 13 ? 1 : 0;
-            // first chunk position of this particle's cell
-            const int cell_e = s_rowpref[row] + (s_oo[row][x] - s_oo[row][0]);
-            first = max(cell_e, base) - base;
-        }
-        int tot;
-        const int excl = block_exclusive_scan(stay, s_scan, &tot);
-        s_incl[threadIdx.x] = excl + stay;
-        __syncthreads();
-        if (e < nown && stay) {
-            const int before = first > 0 ? s_incl[first - 1] : 0;
-            const int k = s_stay[cl] + (excl - before);
-            const int o = s_on[row][x] + s_abefore[cl] + k;
-            if (o >= 0 && o < g.n)
+    constexpr int U = 4;
+    for (int base0 = 0; base0 < nown; base0 += U * kKThreads) {
+        int pv[U], rowv[U], xv[U], code[U];
+        uint32_t mb[U], ub[U];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dst.m[a][o] = src.m[a][p];
-                if (cp_u) dst.u[a][o] = src.u[a][p];
-                if (cp_v) dst.v[a][o] = src.v[a][p];
+        for (int u = 0; u < U; ++u) {
+            const int e = base0 + u * kKThreads + lane;
+            pv[u] = -1;
+            rowv[u] = 0;
+            xv[u] = 0;
+            code[u] = 0;
+            mb[u] = 0;
+            ub[u] = 0;
+            if (e < nown) {
+                const int row = find_cell_fixed<3>(s_rowpref, NROW, e);
+                const int p = s_oo[row][0] + (e - s_rowpref[row]);
+                pv[u] = p;
+                rowv[u] = row;
+                xv[u] = find_cell_fixed<3>(s_oo[row], BXc, p);
+                code[u] = dir[p];
+                // the planes are read for every particle: waiting for the code
+                // first would cost a round trip, and movers are few
+                mb[u] = (uint32_t)src.m[0][p] | ((uint32_t)src.m[1][p] << 8) | ((uint32_t)src.m[2][p] << 16);
+                if (cp_u)
+                    ub[u] = (uint32_t)(uint8_t)src.u[0][p] | ((uint32_t)(uint8_t)src.u[1][p] << 8) |
+                            ((uint32_t)(uint8_t)src.u[2][p] << 16);
             }
-            if (cp_id && o >= 0 && o < g.n) dst.ids[o] = src.ids[p];
         }
-        __syncthreads();
-        // the last particle of each cell's run in this chunk carries the count on
-        if (e < nown) {
-            const int cell_end_e = s_rowpref[row] + (s_oo[row][x + 1] - s_oo[row][0]);
-            const bool last = e == nown - 1 || e == base + kKThreads - 1 || e + 1 == cell_end_e;
-            if (last) s_stay[cl] += s_incl[threadIdx.x] - (first > 0 ? s_incl[first - 1] : 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int base = base0 + u * kKThreads;
+            if (base >= nown) break;
+            const int e = base + lane;
+            const int row = rowv[u], x = xv[u], p = pv[u];
+            const int cl = x + BXc * row;
+            int stay = 0, first = 0, cell_end = 0;
+            if (e < nown) {
+                stay = code[u] == 13 ? 1 : 0;
+                // chunk positions of this particle's cell
+                const int cell_e = s_rowpref[row] + (s_oo[row][x] - s_oo[row][0]);
+                cell_end = s_rowpref[row] + (s_oo[row][x + 1] - s_oo[row][0]);
+                first = max(cell_e, base) - base;
+            }
+            const int incl = wave_inclusive_scan(stay);
+            const int before_first = __shfl(incl, max(first - 1, 0), kWave);
+            const int before = first > 0 ? before_first : 0;
+            const int k = s_stay[cl] + (incl - stay - before);
+            if (e < nown && stay) {
+                const int o = s_on[row][x] + s_abefore[cl] + k;
+                if (o >= 0 && o < g.n) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        dst.m[a][o] = (uint8_t)(mb[u] >> (8 * a));
+                        if (cp_u) dst.u[a][o] = (int8_t)(ub[u] >> (8 * a));
+                        if (cp_v) dst.v[a][o] = src.v[a][p];
+                    }
+                    if (cp_id) dst.ids[o] = src.ids[p];
+                }
+            }
+            __syncthreads();
+            // the last particle of each cell's run in this chunk carries the count on
+            if (e < nown && (e == nown - 1 || lane == kKThreads - 1 || e + 1 == cell_end))
+                s_stay[cl] += incl - before;
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // arrivals: rank among the arrivals into the same cell by old index
-    auto place = [&](const uint4& rec, int rank) {
+    for (int i = lane; i < nin; i += kKThreads) {
+        const uint4 rec = listed ? s_in[i] : arrival(i);
         const int d = (int)(rec.y & 255), p = (int)rec.x;
+        int rank = 0;
+        for (int j = 0; j < nin; ++j) {
+            const uint4 q = listed ? s_in[j] : arrival(j);
+            rank += ((int)(q.y & 255) == d && q.x < rec.x) ? 1 : 0;
+        }
         const int row = d / BXc, x = d - row * BXc;
         const int o = s_on[row][x] + rank + (p >= s_oo[row][x] ? s_stay[d] : 0);
-        if (o < 0 || o >= g.n || p < 0 || p >= g.n) return;
+        if (o < 0 || o >= g.n || p < 0 || p >= g.n) continue;
         dst.m[0][o] = (uint8_t)(rec.z & 255);
         dst.m[1][o] = (uint8_t)((rec.z >> 8) & 255);
         dst.m[2][o] = (uint8_t)((rec.z >> 16) & 255);
@@ -657,30 +676,6 @@ __global__ __launch_bounds__(kKThreads) void k_compact_brick(Geom g, const int32
 #pragma unroll
             for (int a = 0; a < 3; ++a) dst.v[a][o] = src.v[a][p];
         if (cp_id) dst.ids[o] = src.ids[p];
-    };
-    if (listed) {
-        for (int i = threadIdx.x; i < nin; i += kKThreads) {
-            const uint4 rec = s_in[i];
-            const int d = (int)(rec.y & 255);
-            int rank = 0;
-            for (int j = 0; j < nin; ++j) {
-                const uint4 q = s_in[j];
-                rank += ((int)(q.y & 255) == d && q.x < rec.x) ? 1 : 0;
-            }
-            place(rec, rank);
-        }
-    } else {
-        for (int i = threadIdx.x; i < ncand; i += kKThreads) {
-            uint4 rec;
-            if (!cand(i, rec)) continue;
-            const int d = (int)(rec.y & 255);
-            int rank = 0;
-            for (int j = 0; j < ncand; ++j) {
-                uint4 q;
-                if (cand(j, q)) rank += ((int)(q.y & 255) == d && q.x < rec.x) ? 1 : 0;
-            }
-            place(rec, rank);
-        }
     }
 }
 
@@ -766,7 +761,7 @@ int64_t compact_bricks(const Geom& g) {
 }
 
 void launch_compact_bricks(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
-                           const uint8_t* dir, const uint4* ment, const int4* mhdr, Planes src, Planes dst,
+                           const uint8_t* dir, const uint4* ment, const int32_t* mhdr, Planes src, Planes dst,
                            const StepScalars* sc, hipStream_t s) {
     const dim3 grid((unsigned)compact_bricks(g));
     if (g.r == 4)

@@ -34,9 +34,9 @@ constexpr int kMinR = 4;                                 // coarse cells of >= 4
 constexpr int kMaxRows = (kBY / kMinR) * (kBZ / kMinR);
 constexpr int kMaxRowLen = kBX / kMinR;
 static_assert(kMaxRows <= 8 && kMaxRowLen <= 8, "fixed three-step searches of rows and cells");
-static_assert(kMaxRows <= kGMaxRows, "mover headers hold kGMaxRows row segments per brick");
 constexpr int kMaxHist = (kBX / kMinR + 2) * (kBY / kMinR + 2) * (kBZ / kMinR + 2);
 constexpr int kGatherThreads = 256;
+constexpr int kGatherMovCap = 480;                       // movers of a brick listed in LDS
 
 // extents of the staged potentials for a halo of H cells
 template <int H>
@@ -44,6 +44,14 @@ struct Halo {
     static constexpr int LX = kBX + 2 * H, LY = kBY + 2 * H, LZ = kBZ + 2 * H;
     static constexpr int COARSE = (kBX / kMinR + 2 * H) * (kBY / kMinR + 2 * H) * (kBZ / kMinR + 2 * H);
 };
+
+// class 0..26 of the brick that a brick-relative cell (x, y, z), each in
+// [-1, extent], lies in: (dx + 1) + 3 (dy + 1) + 9 (dz + 1), 13 = this brick
+__device__ __forceinline__ int move_class(int x, int y, int z, int bx, int by, int bz) {
+    const int dx = x < 0 ? -1 : (x >= bx ? 1 : 0), dy = y < 0 ? -1 : (y >= by ? 1 : 0);
+    const int dz = z < 0 ? -1 : (z >= bz ? 1 : 0);
+    return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
 
 struct LdsGrid {
     const float* p;
@@ -137,7 +145,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     __shared__ int s_scan[kGatherThreads / kWave + 1];
     __shared__ double s_red[kGatherThreads / kWave];
     __shared__ float s_vc[3][VC ? kMaxRows * kMaxRowLen : 1];   // cell means of the brick's cells
-    __shared__ int s_mfront[kMaxRows], s_mback[kMaxRows];       // movers staying in / leaving the brick, per row
+    __shared__ int s_ccount[28], s_crun[27];                    // movers per destination-brick class
+    __shared__ int s_hist_base;
+    __shared__ int s_nmov, s_mov[MODE == GATHER_STEP ? kGatherMovCap : 1];   // the brick's movers, if they fit
 
     // a halted step (see StepScalars) writes nothing
     if (MODE == GATHER_STEP && *(volatile const int32_t*)&A.sc->halt) return;
@@ -248,10 +258,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     const int HX = BXc + 2, HY = BYc + 2, HZ = BZc + 2;
     if (MODE == GATHER_STEP) {
         for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) s_hist[e] = 0;
-        if ((int)threadIdx.x < kMaxRows) {
-            s_mfront[threadIdx.x] = 0;
-            s_mback[threadIdx.x] = 0;
-        }
+        if ((int)threadIdx.x < 28) s_ccount[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_nmov = 0;
+        if ((int)threadIdx.x < 27) s_crun[threadIdx.x] = 0;
     }
     if constexpr (VC) {
         const int nbc = BXc * BYc * BZc;
@@ -292,6 +301,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     int umax = 0, sat = 0, cmax = 0, nfar = 0;
     double esum = 0.0;
     const int total = s_rowpref[nrows];
+    // the brick's slots in its tile's region of the mover-record array: one
+    // per particle, reserved now so the atomic's latency hides behind the loop
+    int rbase = 0;
+    if (MODE == GATHER_STEP && threadIdx.x == 0 && total > 0) rbase = atomicAdd(&A.tcursor[tile], total);
     // software pipeline: the next particle's bytes are in flight while the
     // current one is computed
     auto locate = [&](int e, int& p, int& lx, int& ly, int& lz) {
@@ -398,25 +411,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             const int hx = lcell[0] + carry[0] + 1, hy = lcell[1] + carry[1] + 1, hz = lcell[2] + carry[2] + 1;
             atomicAdd(&s_hist[(hz * HY + hy) * HX + hx], 1);
             if (code != 13) {
-                // mover record in its row segment's own slots: movers that
-                // stay in the brick from the front, the others from the back
-                const int nx = hx - 1, ny = hy - 1, nz = hz - 1;          // brick-relative new cell, -1..B
-                const int bdx = nx < 0 ? -1 : (nx >= BXc ? 1 : 0), bdy = ny < 0 ? -1 : (ny >= BYc ? 1 : 0);
-                const int bdz = nz < 0 ? -1 : (nz >= BZc ? 1 : 0);
-                const int cls = (bdx + 1) + 3 * (bdy + 1) + 9 * (bdz + 1);
-                const int dl = (nx - bdx * BXc) + BXc * ((ny - bdy * BYc) + BYc * (nz - bdz * BZc));
-                const int row = lcell[1] + BYc * lcell[2];
-                const int slot = cls == 13 ? s_rowoff[row][0] + atomicAdd(&s_mfront[row], 1)
-                                           : s_rowoff[row][BXc] - 1 - atomicAdd(&s_mback[row], 1);
-                uint4 rec;
-                rec.x = (uint32_t)p;
-                rec.y = (uint32_t)dl | ((uint32_t)cls << 8);
-                rec.z = (uint32_t)mnew[0] | ((uint32_t)mnew[1] << 8) | ((uint32_t)mnew[2] << 16);
-                rec.w = 0;
-                if constexpr (!VC)
-                    rec.w = (uint32_t)(uint8_t)un[0] | ((uint32_t)(uint8_t)un[1] << 8) |
-                            ((uint32_t)(uint8_t)un[2] << 16);
-                A.ment[slot] = rec;
+                atomicAdd(&s_ccount[move_class(hx - 1, hy - 1, hz - 1, BXc, BYc, BZc)], 1);
+                const int k = atomicAdd(&s_nmov, 1);
+                if (k < kGatherMovCap) s_mov[k] = p;
             }
         } else {
             const int64_t cn = canon(g, wrapi(gc[0] + lcell[0] + carry[0], g.Nc),
@@ -431,12 +428,61 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
 
     if (MODE == GATHER_STEP) {
         __syncthreads();
-        if ((int)threadIdx.x < kGMaxRows) {
-            // this brick's row segments: [start, start + front) and [end - back, end)
-            const int r = threadIdx.x;
-            int4 h = make_int4(0, 0, 0, 0);
-            if (r < nrows) h = make_int4(s_rowoff[r][0], s_mfront[r], s_rowoff[r][BXc], s_mback[r]);
-            A.mhdr[((int64_t)tile * gridDim.x + b) * kGMaxRows + r] = h;
+        // Mover records, grouped by the class of their destination brick, in
+        // the brick's reserved slots: the movers listed in LDS (or, too many,
+        // all particles again) with the codes and bytes just written.
+        if (threadIdx.x < kWave) {
+            const int lane = threadIdx.x;
+            const int v = lane < 27 ? s_ccount[lane] : 0;
+            const int incl = wave_inclusive_scan(v);
+            int32_t* h = A.mhdr + ((int64_t)tile * gridDim.x + b) * kHdrInts;
+            if (lane < 27) {
+                s_ccount[lane] = incl - v;
+                h[1 + lane] = incl - v;
+            }
+            if (lane == 26) {
+                s_ccount[27] = incl;
+                h[28] = incl;
+            }
+            if (lane == 0) {
+                h[0] = rbase;
+                s_hist_base = rbase;
+            }
+        }
+        __syncthreads();
+        if (s_ccount[27] > 0) {
+            const int rslot = s_hist_base;
+            // the listed movers, or (too many to list) every particle again
+            const bool listed = s_nmov <= kGatherMovCap;
+            const int nwalk = listed ? s_nmov : total;
+            for (int e = threadIdx.x; e < nwalk; e += kGatherThreads) {
+                int p, lx, ly, lz;
+                if (listed) {
+                    p = s_mov[e];
+                    int row = 0;                   // the last row starting at or before p
+                    for (int r2 = 1; r2 < nrows; ++r2) row = s_rowoff[r2][0] <= p ? r2 : row;
+                    lx = find_cell_fixed<3>(s_rowoff[row], BXc, p);
+                    ly = row % BYc;
+                    lz = row / BYc;
+                } else {
+                    locate(e, p, lx, ly, lz);
+                }
+                const int code = A.dir[p];
+                if (code == 13 || code >= 27) continue;
+                const int nx = lx + code % 3 - 1, ny = ly + (code / 3) % 3 - 1, nz = lz + code / 9 - 1;
+                const int cls = move_class(nx, ny, nz, BXc, BYc, BZc);
+                const int bdx = cls % 3 - 1, bdy = (cls / 3) % 3 - 1, bdz = cls / 9 - 1;
+                const int dl = (nx - bdx * BXc) + BXc * ((ny - bdy * BYc) + BYc * (nz - bdz * BZc));
+                uint4 rec;
+                rec.x = (uint32_t)p;
+                rec.y = (uint32_t)dl | ((uint32_t)cls << 8);
+                rec.z = (uint32_t)A.out.m[0][p] | ((uint32_t)A.out.m[1][p] << 8) | ((uint32_t)A.out.m[2][p] << 16);
+                rec.w = 0;
+                if constexpr (!VC)
+                    rec.w = (uint32_t)(uint8_t)A.out.u[0][p] | ((uint32_t)(uint8_t)A.out.u[1][p] << 8) |
+                            ((uint32_t)(uint8_t)A.out.u[2][p] << 16);
+                A.ment[rslot + s_ccount[cls] + atomicAdd(&s_crun[cls], 1)] = rec;
+            }
         }
         for (int e = threadIdx.x; e < HX * HY * HZ; e += kGatherThreads) {
             const int c = s_hist[e];

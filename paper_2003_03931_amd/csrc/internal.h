@@ -197,10 +197,13 @@ size_t fine_green_workspace_bytes(const Geom& g);
 
 // ---- gather bricks --------------------------------------------------------
 // The gather and the compaction share one decomposition: bricks of 32 x 16 x 8
-// fine cells, whole coarse cells (r = 4 or 8), kGMaxRows row segments of
-// coarse cells along x at most, numbered tile-major (tile, then x fastest).
+// fine cells, whole coarse cells (r = 4 or 8), numbered tile-major (tile,
+// then x fastest).  Each brick's header holds kHdrInts ints: the first slot
+// of its mover records, then for the 27 classes of destination brick
+// (dx + 1) + 3 (dy + 1) + 9 (dz + 1) the offset of the class's records and
+// at [28] their total.
 constexpr int kGBX = 32, kGBY = 16, kGBZ = 8;
-constexpr int kGMaxRows = 8;
+constexpr int kHdrInts = 32;
 
 // ---- gather.hip ---------------------------------------------------------
 // floats allocated after the last fine mesh of a batch: the gather stages
@@ -223,7 +226,9 @@ struct GatherArgs {
     float* acc;             // GATHER_FORCE: [n][3]
     double* partial;        // GATHER_POTENTIAL: per-block partial sums
     uint4* ment;            // GATHER_STEP: mover records (one slot per particle, see compact.hip)
-    int4* mhdr;             // GATHER_STEP: per brick and row segment: start, stay-in-brick movers, end, leaving movers
+    int32_t* mhdr;          // GATHER_STEP: per brick, kHdrInts ints (see the brick decomposition)
+    int32_t* tcursor;       // GATHER_STEP: next free record slot of each tile's region (its first particle's
+                            // old index at the step's start)
     double kick;            // GATHER_STEP: force multiplier of the kick (dt, or K_n comoving)
     float drift;            // GATHER_STEP: velocity multiplier of the drift (dt, or FP32 D_n)
     int tile0;
@@ -246,7 +251,7 @@ void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_
 // the brick compaction from the gather's mover records (same result)
 int64_t compact_bricks(const Geom& g);
 void launch_compact_bricks(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
-                           const uint8_t* dir, const uint4* ment, const int4* mhdr, Planes src, Planes dst,
+                           const uint8_t* dir, const uint4* ment, const int32_t* mhdr, Planes src, Planes dst,
                            const StepScalars* sc, hipStream_t s);
 void launch_general_keys(const Geom& g, const int32_t* offsets_old, const uint8_t* dir,
                          const uint32_t* far_key, uint32_t* key, uint32_t* idx, hipStream_t s);
@@ -269,6 +274,9 @@ void launch_commit_cells(const int32_t* counts_new, const int32_t* offsets_new, 
 void launch_step_epilogue(StepScalars* sc, const Geom& g, int vcodec, bool planned_wide, bool planned_f16,
                           hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s, const int32_t* gate = nullptr);
+// out[i] = in[i * stride], i < n
+void launch_strided_copy(const int32_t* in, int64_t stride, int32_t* out, int64_t n, hipStream_t s,
+                         const int32_t* gate = nullptr);
 void launch_moments(const Geom& g, const int32_t* offsets, Planes p, const StepScalars* sc,
                     const VelCells& vcell, double* partial, int nblocks, hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblocks, int width, double* out,

@@ -84,6 +84,13 @@ __global__ void k_epilogue(StepScalars* sc, int vcodec, int planned_wide, int pl
     if ((!planned_wide && b8 >= wide_cut) || (planned_f16 && f3 * b8 + 1.0 >= f16_cut)) sc->halt = 3;
 }
 
+__global__ void k_strided_copy(const int32_t* __restrict__ in, int64_t stride, int32_t* __restrict__ out, int64_t n,
+                               const int32_t* gate) {
+    if (gate && *(volatile const int32_t*)gate) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i * stride];
+}
+
 __global__ void k_fill(int32_t* p, int32_t v, int64_t n, const int32_t* gate) {
     if (gate && *(volatile const int32_t*)gate) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,6 +207,13 @@ void launch_step_epilogue(StepScalars* sc, const Geom& g, int vcodec, bool plann
     const double f3 = (double)g.f * g.f * g.f;
     hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, sc, vcodec, planned_wide ? 1 : 0, planned_f16 ? 1 : 0,
                        wide_cut, 32768.0, f3);
+}
+
+void launch_strided_copy(const int32_t* in, int64_t stride, int32_t* out, int64_t n, hipStream_t s,
+                         const int32_t* gate) {
+    unsigned blocks = grid1d(n, 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_strided_copy, dim3(blocks), dim3(256), 0, s, in, stride, out, n, gate);
 }
 
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s, const int32_t* gate) {
