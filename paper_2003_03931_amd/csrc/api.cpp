@@ -347,7 +347,6 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (g.Nc % 4 || g.Nc < 10) return fail(CUBE_INVALID, "coarse mesh side must be a multiple of 4 and >= 12");
     if (!fft_supported(g.Nc) || !fft_tiles_supported(g.F))
         return fail(CUBE_UNSUPPORTED, "mesh side not supported by the FFT radix plans");
-    if (!compact_supported(g)) return fail(CUBE_UNSUPPORTED, "coarse mesh too small for the compaction bricks");
     if (!gather_supported(g))
         return fail(CUBE_UNSUPPORTED, "tile side must be a multiple of 32 fine cells and r in {4, 8, 16}");
     if (!(d->dt > 0.0f) || !(d->v_headroom >= 1.0f)) return fail(CUBE_INVALID, "need dt > 0 and v_headroom >= 1");

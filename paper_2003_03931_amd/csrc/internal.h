@@ -244,11 +244,8 @@ bool gather_supported(const Geom& g);
 void launch_pp(const Geom& g, const int32_t* offsets, Planes in, float* const acc[3], hipStream_t s);
 
 // ---- compact.hip --------------------------------------------------------
-bool compact_supported(const Geom& g);
-// the fast path returns at once while sc->halt is set
-void launch_compact_fast(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
-                         const uint8_t* dir, Planes src, Planes dst, const StepScalars* sc, hipStream_t s);
-// the brick compaction from the gather's mover records (same result)
+// fast path: the brick compaction from the gather's mover records (returns at
+// once while sc->halt is set)
 int64_t compact_bricks(const Geom& g);
 void launch_compact_bricks(const Geom& g, const int32_t* offsets_old, const int32_t* offsets_new,
                            const uint8_t* dir, const uint4* ment, const int32_t* mhdr, Planes src, Planes dst,

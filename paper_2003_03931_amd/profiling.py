@@ -36,7 +36,7 @@ STAGE_KERNEL = {
     "fine_c2r_xy": "k_c2r_plane",
     "gather_kick_drift": "k_gather<0,",
     "scan_counts": "k_tile_scan",
-    "compact": "k_compact_fast",
+    "compact": "k_compact_brick",
     "pp_force": "k_pp",
 }
 COPY_KERNELS = ("elementwise", "copyBuffer")

@@ -220,10 +220,10 @@ def test_many_one_cell_movers():
 
 def _dense_state(n_dense, seed=77):
     """t4 box with n_dense particles packed into one coarse cell (the rest
-    uniform): 300 keeps the 32-bit fine deposit and the staged compaction,
-    1500 overflows the compaction's staged window (per-cell walks from
-    memory), 70000 needs the wide (64-bit) fine deposit and the sorted
-    compaction."""
+    uniform): 300 keeps the 32-bit fine deposit and the compaction's LDS
+    lists, 1500 overflows its arrival list (ranks from the records in
+    memory), 70000 needs the wide (64-bit) fine deposit and more than 65535
+    particles in one cell."""
     import oracle
     from oracle import codec
     spec = config("t4")
