@@ -9,8 +9,8 @@ a compressed state byte by byte (a fixed lattice plus random runs) for tests
 at sizes where the oracle cannot encode a billion particles in seconds.
 """
 
-from .configs import BoxSpec, CONFIGS, config
+from .configs import BoxSpec, CONFIGS, config, served_box
 from .lattice import lattice_run_state
 from .zeldovich import zeldovich_ics, plane_wave_ics
 
-__all__ = ["BoxSpec", "CONFIGS", "config", "zeldovich_ics", "plane_wave_ics", "lattice_run_state"]
+__all__ = ["BoxSpec", "CONFIGS", "config", "served_box", "zeldovich_ics", "plane_wave_ics", "lattice_run_state"]

@@ -75,3 +75,19 @@ CONFIGS = {
 
 def config(name: str) -> BoxSpec:
     return CONFIGS[name]
+
+
+def served_box(n_side: int, spectral_index: float, seed: int, name: str = "served", rms_disp: float = 0.5,
+               steps: int = 1) -> BoxSpec:
+    """A periodic box of the ensemble and serving workloads: f = 2, r = 4
+    (coarse mesh at 1/4 of the fine resolution), tiles of 64^3 particles
+    (48^3 for a 96^3 box, whose tile box is then 128^3), a 16-cell buffer and
+    a 12-cell split radius; one periodic tile at 64^3."""
+    if n_side == 64:
+        nt, b = 1, 0
+    elif n_side == 96:
+        nt, b = 2, 16
+    else:
+        assert n_side % 64 == 0, "sides are 64, 96 or multiples of 64"
+        nt, b = n_side // 64, 16
+    return BoxSpec(name, n_side, nt, 2, 4, b, 12, DT, 2.0, spectral_index, rms_disp, seed, steps)

@@ -427,6 +427,68 @@ cube_status cube_poll(cube_server* srv, uint64_t ticket, cube_result* out);
  * is ignored. */
 void cube_server_destroy(cube_server* srv);
 
+/*
+ * Batched ensembles: many independent boxes of different sizes advanced
+ * together (the two-level PM step of Sec. II on the compressed particles of
+ * Sec. III-A, box by box, with the boxes' tile work merged).  Boxes whose
+ * tiles share one FFT geometry (tile box, tile side, buffer, split radius,
+ * resolution, precision) share a fine workspace of `tiles_in_flight` tile
+ * meshes: their tiles pass through it in waves, and each wave's three fine
+ * FFT sweeps are single persistent launches over the tiles of every box in
+ * the wave.  The boxes' own stages run on `streams` HIP streams (boxes
+ * assigned round robin, default priority), joined around every shared FFT.
+ * One ensemble step is captured into a hipGraph once and replayed; nothing
+ * synchronises with the host inside a step.  Each box's result is the one it
+ * gets alone (same kernels, same order of arithmetic).
+ *   streams          1..4, or 0: chosen by the autotuner.
+ *   tiles_in_flight  tile meshes per shared workspace, or 0: chosen by the
+ *                    autotuner (the workspace is sized for up to 256 tiles,
+ *                    or the largest class).
+ *   use_graph        0: captured hipGraph steps (default); -1: eager launches.
+ *   device           HIP device of every box.
+ * Boxes must be static (comoving = 0), use the linear velocity codec and
+ * CUBE_FP32 or CUBE_MIXED_BF16 (CUBE_UNSUPPORTED otherwise).
+ */
+typedef struct {
+    int32_t streams;
+    int32_t tiles_in_flight;
+    int32_t use_graph;
+    int32_t device;
+} cube_ensemble_desc;
+
+typedef struct cube_ensemble cube_ensemble;
+
+/* Create the boxes (empty states, each one's own context with a one-tile
+ * fine workspace) and the shared workspaces.  Errors as cube_init, and
+ * CUBE_UNSUPPORTED for the box kinds above. */
+cube_status cube_ensemble_create(const cube_box_desc* boxes, int32_t nboxes, const cube_ensemble_desc* opts,
+                                 cube_ensemble** out);
+
+/* Borrow box i's context for cube_compress / cube_set_state /
+ * cube_get_state / cube_diagnostics (it stays owned by the ensemble; do not
+ * destroy it, and do not use it while cube_ensemble_step runs). */
+cube_status cube_ensemble_box(cube_ensemble* e, int32_t i, cube_ctx** out);
+
+/* Advance every box by nsteps steps.  On the first call of an ensemble whose
+ * schedule is left to the autotuner (and not yet cached for this set of box
+ * geometries in the process), the tuner runs first.  A box that needs the
+ * host (see cube_pm_step) finishes its steps on its own after the others. */
+cube_status cube_ensemble_step(cube_ensemble* e, int32_t nsteps);
+
+/* Autotuner: time one ensemble step of every candidate schedule (streams 1,
+ * 2, 4 x tiles in flight 16, 32, ... up to the workspace) on the current
+ * states, restore the states after each, keep the fastest and cache it for
+ * this set of box geometries.  The chosen schedule is written to *chosen
+ * when not NULL.  Only non-numerical knobs change: results are identical
+ * under every schedule. */
+cube_status cube_ensemble_tune(cube_ensemble* e, cube_ensemble_desc* chosen);
+
+/* The schedule in use. */
+cube_status cube_ensemble_schedule(cube_ensemble* e, cube_ensemble_desc* out);
+
+/* Destroy the boxes, workspaces, streams and graph (NULL is ignored). */
+void cube_ensemble_destroy(cube_ensemble* e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -128,6 +128,15 @@ class Result(ctypes.Structure):
     ]
 
 
+class EnsembleDesc(ctypes.Structure):
+    _fields_ = [
+        ("streams", ctypes.c_int32),
+        ("tiles_in_flight", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
 # exported symbol -> (restype, argtypes); mirrors include/cube.h
 SIGNATURES = {
     "cube_last_error": (ctypes.c_char_p, []),
@@ -158,6 +167,13 @@ SIGNATURES = {
     "cube_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
     "cube_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "cube_server_destroy": (None, [ctypes.c_void_p]),
+    "cube_ensemble_create": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.c_int32, ctypes.POINTER(EnsembleDesc),
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_ensemble_box": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "cube_ensemble_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cube_ensemble_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(EnsembleDesc)]),
+    "cube_ensemble_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(EnsembleDesc)]),
+    "cube_ensemble_destroy": (None, [ctypes.c_void_p]),
 }
 
 _lib = None

@@ -103,6 +103,28 @@ class CubeBox:
         check(self.lib.cube_init(ctypes.byref(self.desc), al, ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx)))
         self.ctx = ctx
+        self._owned = True
+        self._set_sizes(spec)
+
+    @classmethod
+    def borrowed(cls, ctx, spec, with_ids=False, device=0):
+        """A handle on a context owned elsewhere (an ensemble's box): the same
+        calls, and close() leaves the context alone."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.stream = None
+        self.desc = desc_from(spec, with_ids)
+        self.with_ids = with_ids
+        self.allocator = None
+        self.ctx = ctx
+        self._owned = False
+        self._set_sizes(spec)
+        return self
+
+    def _set_sizes(self, spec):
         n = spec.n_side
         self.n = n ** 3
         nc = n * spec.fine_per_spacing // spec.coarse_ratio
@@ -114,7 +136,7 @@ class CubeBox:
 
     # ------------------------------------------------------------ lifetime
     def close(self):
-        if self.ctx is not None and self.ctx.value:
+        if getattr(self, "_owned", True) and self.ctx is not None and self.ctx.value:
             self.lib.cube_destroy(self.ctx)
         self.ctx = None
 

@@ -24,8 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cube.h"
-#include "internal.h"
+#include "ctx.h"
 
 using namespace cube;
 
@@ -33,24 +32,16 @@ namespace {
 
 thread_local std::string g_err;
 
-cube_status fail(cube_status st, const std::string& msg) {
+}  // namespace
+
+cube_status cube::fail(cube_status st, const std::string& msg) {
     g_err = msg;
     return st;
 }
 
-}  // namespace
-
 void cube::set_last_error(const char* msg) { g_err = msg ? msg : ""; }
 
 namespace {
-
-#define CUBE_HIP(expr)                                                                         \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) {                                                                \
-            return fail(CUBE_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
-        }                                                                                      \
-    } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -108,181 +99,16 @@ int ilog2(int v) {
     return l;
 }
 
-enum Stage {
-    ST_COARSE_DEP, ST_COARSE_FFT, ST_FINE_DEP, ST_FFT_R2C, ST_FFT_ZG, ST_FFT_C2R,
-    ST_GATHER, ST_SCAN, ST_COMPACT, ST_VENC, ST_PP, NSTAGES
-};
 const char* const kStageNames[NSTAGES] = {
     "coarse_deposit", "coarse_fft_green", "fine_deposit", "fine_r2c_xy", "fine_z_green",
     "fine_c2r_xy", "gather_kick_drift", "scan_counts", "compact", "velocity_encode", "pp_force"};
-
-// HIP events around every launch of a stage, resolved at the next sync.
-struct Profiler {
-    bool on = false;
-    struct Pending {
-        int stage;
-        hipEvent_t a, b;
-        double bytes;
-    };
-    std::vector<hipEvent_t> pool;
-    std::vector<Pending> pending;
-    int64_t launches[NSTAGES] = {};
-    double ms[NSTAGES] = {};
-    double bytes[NSTAGES] = {};
-
-    hipEvent_t get() {
-        if (pool.empty()) {
-            hipEvent_t e;
-            hipEventCreate(&e);
-            return e;
-        }
-        hipEvent_t e = pool.back();
-        pool.pop_back();
-        return e;
-    }
-    hipEvent_t mark(hipStream_t s) {
-        hipEvent_t e = get();
-        hipEventRecord(e, s);
-        return e;
-    }
-    void add(int stage, hipEvent_t a, hipEvent_t b, double by) { pending.push_back({stage, a, b, by}); }
-    // call only after the stream has been synchronised
-    void flush() {
-        std::vector<hipEvent_t> done;
-        for (const Pending& p : pending) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
-                ms[p.stage] += t;
-                launches[p.stage] += 1;
-                bytes[p.stage] += p.bytes;
-            }
-            done.push_back(p.a);
-            done.push_back(p.b);
-        }
-        pending.clear();
-        std::sort(done.begin(), done.end());
-        done.erase(std::unique(done.begin(), done.end()), done.end());
-        for (hipEvent_t e : done) pool.push_back(e);
-    }
-    void reset() {
-        for (int i = 0; i < NSTAGES; ++i) { launches[i] = 0; ms[i] = 0.0; bytes[i] = 0.0; }
-    }
-    ~Profiler() {
-        for (const Pending& p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-        for (hipEvent_t e : pool) hipEventDestroy(e);
-    }
-};
 
 }  // namespace
 
 namespace {
 
-size_t round256(size_t bytes) { return std::max<size_t>((bytes + 255) / 256 * 256, 256); }
-
-// Device memory: the caller's callbacks, or hipMalloc / hipFree.  Sizes are
-// rounded up to 256 bytes, and the same rounded size is passed to free.
-struct DevMem {
-    cube_allocator al{};
-    bool custom = false;
-    hipStream_t stream = nullptr;
-    void* get(size_t bytes) {
-        bytes = round256(bytes);
-        if (custom) return al.alloc(al.user, bytes, stream);
-        void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        return p;
-    }
-    void put(void* p, size_t bytes) {
-        if (!p) return;
-        if (custom) al.free(al.user, p, round256(bytes), stream);
-        else hipFree(p);
-    }
-};
-
-// Buffers that live for one call; released (stream-ordered) at scope exit.
-struct Temp {
-    DevMem& mem;
-    std::vector<std::pair<void*, size_t>> held;
-    explicit Temp(DevMem& m) : mem(m) {}
-    template <class T>
-    bool get(T** p, size_t bytes) {
-        void* q = mem.get(bytes);
-        *p = static_cast<T*>(q);
-        if (!q) return false;
-        held.push_back({q, bytes});
-        return true;
-    }
-    ~Temp() {
-        for (auto& e : held) mem.put(e.first, e.second);
-    }
-};
-
 }  // namespace
 
-struct cube_ctx {
-    Profiler prof;
-    Geom g{};
-    cube_box_desc desc{};
-    hipStream_t stream = nullptr;
-    bool poisoned = false;
-    bool has_state = false;
-    DevMem mem;
-    std::vector<std::pair<void*, size_t>> allocs;
-
-    Planes A{}, B{};
-    VelCells vcell{};                 // cell-mean velocity codec: means and tan table
-    uint8_t* dir = nullptr;
-    uint32_t* far_key = nullptr;
-    uint4* ment = nullptr;            // mover records, one slot per particle
-    int32_t* mhdr = nullptr;          // per gather brick: first record slot and per-class offsets
-    int32_t* tcursor = nullptr;       // per tile: record slots taken in the running step
-    int32_t* counts = nullptr;
-    int32_t* offsets = nullptr;
-    int32_t* counts_new = nullptr;
-    int32_t* offsets_new = nullptr;
-    StepScalars* sc = nullptr;
-    StepScalars* sc_host = nullptr;   // pinned
-
-    float2* coarse = nullptr;
-    double* coarse_green = nullptr;
-    float2* tw_coarse = nullptr;
-    float* fine_real = nullptr;       // batch x F^3 real meshes (density, then potential)
-    void* fine_spec = nullptr;        // batch x F^2 (F/2+1) half spectra (FP32 size: FP16 may fall back)
-    float* fine_green = nullptr;
-    float2* tw_fine = nullptr;
-    void* scan_ws = nullptr;
-    double* partial = nullptr;
-    double* reduced = nullptr;
-    float* pp[3] = {nullptr, nullptr, nullptr};   // extended PP accelerations, [3][n]
-    int batch = 1;
-
-    int64_t step = 0;
-    double last_step_ms = 0.0;
-    int32_t max_count = 0;            // largest cell count of the current state
-    int32_t max_block8 = 0;           // largest count of a 2x2x2 block of coarse cells
-    bool halted_recently = false;     // the last cube_pm_step met a halt: enqueue one step per sync
-    int dbg_force[4] = {0, 0, 0, 0};  // cube_debug_force: steps still to receive each forced condition
-    void* noalloc_scratch = nullptr;  // this device's fixed scratch region (cube_pm_step_noalloc)
-
-    ~cube_ctx() {
-        if (sc_host) hipHostFree(sc_host);
-        for (auto& e : allocs) mem.put(e.first, e.second);
-    }
-
-    cube_status alloc(void** p, size_t bytes) {
-        *p = mem.get(bytes);
-        if (!*p) return fail(CUBE_OOM, "device allocation of " + std::to_string(round256(bytes)) + " bytes failed");
-        allocs.push_back({*p, bytes});
-        return CUBE_OK;
-    }
-    template <class T>
-    cube_status alloc_n(T** p, int64_t n) {
-        return alloc(reinterpret_cast<void**>(p), (size_t)n * sizeof(T));
-    }
-};
 
 namespace {
 
@@ -417,6 +243,10 @@ Footprint footprint_of(const Geom& g, const cube_box_desc& d) {
     return {p, std::max(std::max(t_green, t_compress), std::max(t_general, t_pk))};
 }
 
+}  // namespace
+
+namespace cube {
+
 cube_status check_ctx(cube_ctx* c) {
     if (!c) return fail(CUBE_INVALID, "null context");
     if (c->poisoned) return fail(CUBE_DEVICE, "context poisoned by an earlier device error");
@@ -459,20 +289,7 @@ void coarse_potential(cube_ctx* c) {
     }
 }
 
-// What the host fixes when it enqueues a step, from the state's counts as of
-// its last synchronisation: the fine-deposit accumulator width and the
-// storage format of the tile half spectra.  The mixed FP16 mode falls back to
-// FP32 while a fine-cell density could exceed the FP16 range (a fine cell
-// gathers the particles of at most one 2x2x2 block of coarse cells, density
-// f^3 per particle; the plane transform's gain is divided out), and after a
-// potential spectrum value left it (force_fp32).  The epilogue of every step
-// checks that the new state still fits the plan (halt 3 otherwise).
-struct StepPlan {
-    bool wide;
-    int fmt;
-};
-
-StepPlan plan_of(const cube_ctx* c, bool force_fp32 = false) {
+StepPlan plan_of(const cube_ctx* c, bool force_fp32) {
     StepPlan p;
     p.wide = fine_deposit_needs_wide(c->g, c->max_block8);
     switch (c->desc.precision) {
@@ -483,6 +300,12 @@ StepPlan plan_of(const cube_ctx* c, bool force_fp32 = false) {
     return p;
 }
 
+void fine_window(const Geom& g, bool full, int* lo, int* hi) {
+    const bool whole = full || g.periodic;
+    *lo = whole ? 0 : g.b - 1 - g.fdr;
+    *hi = whole ? g.F : g.b + g.T + 1 + g.fdr;
+}
+
 // fine potentials of tiles [t0, t0 + nt) into ctx->fine_real: over the
 // whole box when `full`, else over the tile plus the 1 + fdr cells the
 // gather's interpolation and differences reach (all of the box for a
@@ -491,8 +314,8 @@ void fine_potential(cube_ctx* c, const StepPlan& plan, int t0, int nt, bool full
     const Geom& g = c->g;
     Profiler& P = c->prof;
     const int fmt = plan.fmt;
-    const bool whole = full || g.periodic;
-    const int lo = whole ? 0 : g.b - 1 - g.fdr, hi = whole ? g.F : g.b + g.T + 1 + g.fdr;
+    int lo, hi;
+    fine_window(g, full, &lo, &hi);
     hipEvent_t e0 = P.on ? P.mark(c->stream) : nullptr;
     launch_fine_deposit(g, c->offsets, c->A, t0, nt, c->fine_real, plan.wide, c->stream);
     if (!P.on) {
@@ -557,37 +380,40 @@ GatherArgs gather_args(cube_ctx* c, int mode, int t0, int nt, int64_t step_index
     return a;
 }
 
-// Enqueue one step (no host synchronisation, no allocation): `plan` fixes
-// the deposit width and spectrum format of this step and of the next one
-// (checked by the epilogue), `step_index` the comoving factors.
-void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
+void step_pre(cube_ctx* c) {
     const Geom& g = c->g;
     hipStream_t s = c->stream;
     StepScalars* sc = c->sc;
     launch_step_prologue(sc, c->desc.v_headroom, s);
     launch_fill_i32(c->counts_new, 0, g.ncells, s, &sc->halt);
+    // the mover records of each tile go to the slots of its particles
     launch_strided_copy(c->offsets, (int64_t)g.Tc * g.Tc * g.Tc, c->tcursor, g.ntiles, s, &sc->halt);
     coarse_potential(c);
-    Profiler& P = c->prof;
     pp_forces(c);
-    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
-        const int nt = std::min(c->batch, g.ntiles - t0);
-        fine_potential(c, plan, t0, nt);
-        if (t0 == 0 && c->dbg_force[1] > 0) {
-            --c->dbg_force[1];
-            launch_fill_i32(&sc->overflow, 1, 1, s, &sc->halt);
-        }
-        GatherArgs a = gather_args(c, GATHER_STEP, t0, nt, step_index);
-        hipEvent_t e0 = P.on ? P.mark(s) : nullptr;
-        launch_gather(a, s);
-        if (P.on) {
-            const double np = (double)g.n * nt / g.ntiles;
-            const double t4 = (double)(g.T + 4) * (g.T + 4) * (g.T + 4);
-            const double c4 = (double)(g.Tc + 4) * (g.Tc + 4) * (g.Tc + 4);
-            // 6 B in, 7 B out (m', u', move code), one count update, potentials read once
-            P.add(ST_GATHER, e0, P.mark(s), 21.0 * np + 4.0 * nt * (t4 + c4));
-        }
+}
+
+void step_gather(cube_ctx* c, int t0, int nt, const float* mesh, int64_t step_index) {
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    Profiler& P = c->prof;
+    GatherArgs a = gather_args(c, GATHER_STEP, t0, nt, step_index);
+    a.fine_real = mesh;
+    hipEvent_t e0 = P.on ? P.mark(s) : nullptr;
+    launch_gather(a, s);
+    if (P.on) {
+        const double np = (double)g.n * nt / g.ntiles;
+        const double t4 = (double)(g.T + 4) * (g.T + 4) * (g.T + 4);
+        const double c4 = (double)(g.Tc + 4) * (g.Tc + 4) * (g.Tc + 4);
+        // 6 B in, 7 B out (m', u', move code), one count update, potentials read once
+        P.add(ST_GATHER, e0, P.mark(s), 21.0 * np + 4.0 * nt * (t4 + c4));
     }
+}
+
+void step_post(cube_ctx* c, const StepPlan& plan) {
+    const Geom& g = c->g;
+    hipStream_t s = c->stream;
+    StepScalars* sc = c->sc;
+    Profiler& P = c->prof;
     hipEvent_t es = P.on ? P.mark(s) : nullptr;
     launch_fill_i32(&sc->new_max_count, 0, 2, s, &sc->halt);     // new_max_count and new_max_block8
     exclusive_scan_i32(c->counts_new, c->offsets_new, g.ncells, c->scan_ws, s, &sc->new_max_count, &sc->halt);
@@ -619,6 +445,24 @@ void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
         --c->dbg_force[3];
         launch_fill_i32(&sc->halt, 3, 1, s, &sc->halt);
     }
+}
+
+// Enqueue one step (no host synchronisation, no allocation): `plan` fixes
+// the deposit width and spectrum format of this step and of the next one
+// (checked by the epilogue), `step_index` the comoving factors.
+void enqueue_step(cube_ctx* c, const StepPlan& plan, int64_t step_index) {
+    const Geom& g = c->g;
+    step_pre(c);
+    for (int t0 = 0; t0 < g.ntiles; t0 += c->batch) {
+        const int nt = std::min(c->batch, g.ntiles - t0);
+        fine_potential(c, plan, t0, nt);
+        if (t0 == 0 && c->dbg_force[1] > 0) {
+            --c->dbg_force[1];
+            launch_fill_i32(&c->sc->overflow, 1, 1, c->stream, &c->sc->halt);
+        }
+        step_gather(c, t0, nt, c->fine_real, step_index);
+    }
+    step_post(c, plan);
 }
 
 // Temporaries of the sorted general compaction: four key/index arrays of n
@@ -669,6 +513,28 @@ cube_status read_scalars(cube_ctx* c) {
     return CUBE_OK;
 }
 
+cube_status resolve_halt(cube_ctx* c, void* scratch, bool* force_fp32, int64_t base_done) {
+    const int halt = c->sc_host->halt;
+    if (halt == 1) {
+        cube_status st = finish_general(c, plan_of(c, *force_fp32), scratch);
+        if (st == CUBE_OK) st = read_scalars(c);
+        if (st != CUBE_OK) {
+            launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+            sync(c);
+            return st;
+        }
+        if (c->sc_host->steps_done != base_done + 1) return fail(CUBE_DEVICE, "general compaction did not commit");
+        c->step += 1;
+        if (c->sc_host->halt == 3) launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+    } else if (halt != 0) {
+        // 2: FP16 overflow, the step is run again with FP32 spectra;
+        // 3: the committed state needs another plan for the next step
+        if (halt == 2) *force_fp32 = true;
+        launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
+    }
+    return CUBE_OK;
+}
+
 // nsteps steps: enqueue them all (one at a time after a recent halt), read
 // the scalars once, resolve a halt, and continue with the rest.  scratch:
 // optional region for the general compaction's temporaries.
@@ -687,27 +553,12 @@ cube_status run_steps(cube_ctx* c, int32_t nsteps, void* scratch) {
         const int64_t done = c->sc_host->steps_done - base;
         c->step += done;
         done_total += done;
-        const int halt = c->sc_host->halt;
-        if (halt == 0) continue;
+        if (c->sc_host->halt == 0) continue;
         met_halt = true;
-        if (halt == 1) {
-            st = finish_general(c, plan_of(c, force_fp32), scratch);
-            if (st == CUBE_OK) st = read_scalars(c);
-            if (st != CUBE_OK) {
-                launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
-                sync(c);
-                return st;
-            }
-            if (c->sc_host->steps_done != base + done + 1) return fail(CUBE_DEVICE, "general compaction did not commit");
-            c->step += 1;
-            done_total += 1;
-            if (c->sc_host->halt == 3) launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
-        } else {
-            // 2: FP16 overflow, the step is run again with FP32 spectra;
-            // 3: the committed state needs another plan for the next step
-            if (halt == 2) force_fp32 = true;
-            launch_fill_i32(&c->sc->halt, 0, 1, c->stream);
-        }
+        const int64_t before = c->step;
+        st = resolve_halt(c, scratch, &force_fp32, base + done);
+        if (st != CUBE_OK) return st;
+        done_total += c->step - before;
     }
     c->halted_recently = met_halt;
     return CUBE_OK;

@@ -167,7 +167,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         pytest.skip("no host C compiler")
     pairs = {"cube_box_desc": _lib.BoxDesc, "cube_state_view": _lib.StateView, "cube_diag": _lib.Diag,
              "cube_stage_stat": _lib.StageStat, "cube_allocator": _lib.Allocator,
-             "cube_server_desc": _lib.ServerDesc, "cube_request": _lib.Request, "cube_result": _lib.Result}
+             "cube_server_desc": _lib.ServerDesc, "cube_request": _lib.Request, "cube_result": _lib.Result,
+             "cube_ensemble_desc": _lib.EnsembleDesc}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cube.h"', "int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'    printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -188,3 +189,24 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[cname, "sizeof"] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[cname, fname] == getattr(py, fname).offset, (cname, fname)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcube.so not built")
+def test_ensemble_rejects_unsupported_boxes_without_a_gpu():
+    """Ensemble validation runs before any device call: comoving boxes, the
+    cell-mean codec and FP16 spectra are refused, as are bad options."""
+    from cube_inputs import config
+    from paper_2003_03931_amd._lib import EnsembleDesc, load
+    from paper_2003_03931_amd import desc_from
+    lib = load()
+    h = ctypes.c_void_p()
+    spec = config("c1")
+    for bad in (spec.with_(comoving=1, omega_m=0.3, omega_l=0.7, a_start=0.1), spec.with_(vel_codec=1)):
+        arr = (type(desc_from(spec)) * 1)(desc_from(bad))
+        assert lib.cube_ensemble_create(arr, 1, None, ctypes.byref(h)) == 6      # CUBE_UNSUPPORTED
+    arr = (type(desc_from(spec)) * 1)(desc_from(spec, precision=2))
+    assert lib.cube_ensemble_create(arr, 1, None, ctypes.byref(h)) == 6
+    assert b"FP16" in lib.cube_last_error()
+    arr = (type(desc_from(spec)) * 1)(desc_from(spec))
+    assert lib.cube_ensemble_create(arr, 1, ctypes.byref(EnsembleDesc(5, 0, 0, 0)), ctypes.byref(h)) == 1
+    assert lib.cube_ensemble_create(arr, 0, None, ctypes.byref(h)) == 1
