@@ -14,8 +14,9 @@ PP force on the same input beside it), the dominant
 kernel's achieved bandwidth against the 8 TB/s HBM peak (HIP events on the
 library stream over the timed region), the FP64 oracle timed on the host
 cores on a bounded sample of the same tile geometry, and a served stream of
-boxes (p50/p99 time to completion, aggregate particle-steps/s).  --batched N
-adds an ensemble of N boxes run concurrently against one at a time.
+boxes at 4 and 40 requests per second (p50/p99 time to completion,
+admission waits, aggregate particle-steps/s), and a batched ensemble of 96
+boxes against the same boxes run one at a time.
 """
 
 import argparse
@@ -85,58 +86,57 @@ def cpu_baseline(sample="c3cpu", sample_one="c3s"):
             "note": "unoptimised FP64 numpy reference, not the paper's tuned CPU code"}
 
 
-def served_spec(n_side, spectral_index, seed, name):
-    """Periodic box for the serving / batched workloads: f = 2, r = 4, tiles of
-    64^3 particles (48^3 for the 96^3 box, whose tile box is then 128^3), a
-    16-cell buffer and a 12-cell split radius; one periodic tile at 64^3."""
-    from cube_inputs import BoxSpec
-    from cube_inputs.configs import DT
-    if n_side == 64:
-        nt, b = 1, 0
-    elif n_side == 96:
-        nt, b = 2, 16
-    else:
-        nt, b = n_side // 64, 16
-    return BoxSpec(name, n_side, nt, 2, 4, b, 12, DT, 2.0, spectral_index, 0.5, seed, 1)
-
-
-def make_requests(kind, count, rng_seed):
-    """(spec, pos, vel, steps, arrival_s) per request.
-    serving: sides log-uniform over [64, 256] rounded to multiples of 64,
-    steps uniform in [5, 50], exponential inter-arrivals at 4 per second.
-    batched: sides from {64, 96, 128, 192, 256}, 16 steps, all at t = 0.
-    Both: P(k) ~ k^n with n uniform in [-2.5, -1], rms displacement 0.5."""
+def serving_requests(count, rng_seed=5000, rate=4.0):
+    """The served stream: Poisson arrivals at `rate` per second, sides
+    log-uniform over [64, 512] rounded to multiples of 64, steps uniform in
+    [5, 50], P(k) ~ k^n with n uniform in [-2.5, -1], rms displacement 0.5,
+    IC seed 5001 + i.  Returns (spec, steps, arrival_s) per request."""
     import numpy as np
-    from cube_inputs import zeldovich_ics
+    from cube_inputs import served_box
     rng = np.random.default_rng(rng_seed)
     out, t = [], 0.0
     for i in range(count):
-        if kind == "serving":
-            side = int(np.clip(64 * round(np.exp(rng.uniform(np.log(64), np.log(256))) / 64), 64, 256))
-            steps = int(rng.integers(5, 51))
-            t += rng.exponential(1.0 / 4.0)
-        else:
-            side = int(rng.choice([64, 96, 128, 192, 256]))
-            steps = 16
+        side = int(np.clip(64 * round(np.exp(rng.uniform(np.log(64), np.log(512))) / 64), 64, 512))
+        steps = int(rng.integers(5, 51))
+        t += rng.exponential(1.0 / rate)
         n_index = float(rng.uniform(-2.5, -1.0))
-        spec = served_spec(side, n_index, rng_seed + 1 + i, f"{kind}{i}")
-        pos, vel = zeldovich_ics(side, n_index, 0.5, spec.seed, spec.dt)
-        out.append((spec, pos, vel, steps, t if kind == "serving" else 0.0))
+        out.append((served_box(side, n_index, rng_seed + 1 + i, f"req{i}"), steps, t))
     return out
 
 
-def run_server(reqs, slots, budget, precision, realtime):
-    """Submit the requests (at their arrival times when realtime) to one
-    server; returns per-request results and the wall time."""
+def ensemble_boxes(count, rng_seed=4000):
+    """The batched ensemble: sides drawn uniformly from {64, 96, 128, 192,
+    256}, P(k) ~ k^n with n uniform in [-2.5, -1], rms displacement 0.5, IC
+    seed 4001 + b."""
+    import numpy as np
+    from cube_inputs import served_box
+    rng = np.random.default_rng(rng_seed)
+    specs = []
+    for b in range(count):
+        side = int(rng.choice([64, 96, 128, 192, 256]))
+        n_index = float(rng.uniform(-2.5, -1.0))
+        specs.append(served_box(side, n_index, rng_seed + 1 + b, f"ens{b}"))
+    return specs
+
+
+def host_ics(spec):
+    """Float ICs of a served box as host arrays (generated on the GPU)."""
+    from cube_inputs import zeldovich_ics_device
+    p, v = zeldovich_ics_device(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
+    return p.cpu().numpy(), v.cpu().numpy()
+
+
+def run_server(reqs, ics, slots, budget, precision, rate_scale=1.0):
+    """Submit the requests to one server at their arrival times (divided by
+    rate_scale); returns per-request results and the wall time."""
     from paper_2003_03931_amd import CubeServer
     with CubeServer(budget, max_slots=slots, precision=precision) as srv:
         t0 = time.perf_counter()
         tickets = []
-        for spec, pos, vel, steps, at in reqs:
-            if realtime:
-                delay = at - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
+        for (spec, steps, at), (pos, vel) in zip(reqs, ics):
+            delay = at / rate_scale - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
             tickets.append(srv.submit(spec, pos, vel, steps))
         res = [srv.wait(t) for t in tickets]
         wall = time.perf_counter() - t0
@@ -146,19 +146,65 @@ def run_server(reqs, slots, budget, precision, realtime):
     return res, wall
 
 
-def serving_report(reqs, res, wall, slots, budget, precision):
+def serving_report(reqs, res, wall, slots, budget, precision, rate):
     import numpy as np
     ttc = np.array([r["done_ms"] - r["submit_ms"] for r in res])
     wait = np.array([r["start_ms"] - r["submit_ms"] for r in res])
-    ps = sum(spec.n_side ** 3 * steps for spec, _, _, steps, _ in reqs)
+    ps = sum(spec.n_side ** 3 * steps for spec, steps, _ in reqs)
     span_s = (max(r["done_ms"] for r in res) - min(r["submit_ms"] for r in res)) * 1e-3
+    sides = sorted(spec.n_side for spec, _, _ in reqs)
     return {"requests": len(res), "slots": slots, "hbm_budget_gb": budget / 1e9, "precision": precision,
+            "arrival_rate_per_s": rate,
             "p50_ms": float(np.percentile(ttc, 50)), "p99_ms": float(np.percentile(ttc, 99)),
             "admission_wait_p50_ms": float(np.percentile(wait, 50)),
             "admission_wait_p99_ms": float(np.percentile(wait, 99)),
+            "queued_requests": int(np.sum(wait > 1.0)),
             "particle_steps_per_s": ps / span_s, "wall_s": wall,
-            "workload": "Poisson arrivals at 4/s; sides log-uniform in [64, 256] (multiples of 64); steps "
-                        "uniform in [5, 50]; Zel'dovich ICs, n uniform in [-2.5, -1], rms 0.5"}
+            "sides": {str(k): sides.count(k) for k in sorted(set(sides))},
+            "workload": f"Poisson arrivals at {rate:g}/s; sides log-uniform in [64, 512] (multiples of 64); steps "
+                        "uniform in [5, 50]; Zel'dovich ICs, n uniform in [-2.5, -1], rms 0.5; ICs made before the clock"}
+
+
+def run_ensemble_bench(count, steps):
+    """The batched ensemble against the same boxes run one at a time."""
+    import torch
+    from cube_inputs import zeldovich_ics_device
+    from paper_2003_03931_amd import CubeBox, CubeEnsemble
+    specs = ensemble_boxes(count)
+    ics = [zeldovich_ics_device(s.n_side, s.spectral_index, s.rms_disp, s.seed, s.dt) for s in specs]
+    torch.cuda.synchronize()
+    n_total = sum(s.n_side ** 3 for s in specs)
+    with CubeEnsemble(specs) as e:
+        for b, (p, v) in zip(e.boxes, ics):
+            b.compress(p, v)
+        t = time.perf_counter()
+        e.step(1)                  # schedule (autotuner), graph capture, warm-up
+        tune_s = time.perf_counter() - t
+        sched = e.schedule()
+        t = time.perf_counter()
+        e.step(steps)
+        wall_e = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    wall_1 = 0.0
+    for s, (p, v) in zip(specs, ics):
+        with CubeBox(s) as b:
+            b.compress(p, v)
+            b.step(1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            b.step(steps)
+            wall_1 += time.perf_counter() - t
+    del ics
+    torch.cuda.empty_cache()
+    ps = n_total * steps
+    sides = sorted(s.n_side for s in specs)
+    return {"boxes": count, "particles": n_total, "steps_per_box": steps,
+            "sides": {str(k): sides.count(k) for k in sorted(set(sides))},
+            "schedule": sched, "first_step_with_tuning_s": tune_s,
+            "ensemble_particle_steps_per_s": ps / wall_e, "ensemble_ms_per_step": 1e3 * wall_e / steps,
+            "one_at_a_time_particle_steps_per_s": ps / wall_1, "speedup": wall_1 / wall_e,
+            "workload": "sides from {64,96,128,192,256}, P(k)~k^n with n uniform in [-2.5,-1], rms 0.5, FP32; "
+                        "tile FFTs of all boxes of one tile geometry in shared launches, hipGraph steps"}
 
 
 def main():
@@ -180,9 +226,9 @@ def main():
     ap.add_argument("--pp-range", type=int, default=4, help="PP range in fine cells of that run")
     ap.add_argument("--serving", type=int, default=40, help="requests of the serving run (0 skips it)")
     ap.add_argument("--serving-slots", type=int, default=4)
-    ap.add_argument("--batched", type=int, default=0,
-                    help="boxes of the batched-ensemble run (slots vs one at a time); 0 skips it")
-    ap.add_argument("--batched-slots", type=int, default=8)
+    ap.add_argument("--batched", type=int, default=96,
+                    help="boxes of the batched-ensemble run (against one box at a time); 0 skips it")
+    ap.add_argument("--batched-steps", type=int, default=16)
     ap.add_argument("--allocator", default="torch", choices=["torch", "hip"],
                     help="device memory of the boxes: torch's caching allocator or the library's hipMalloc")
     args = ap.parse_args()
@@ -308,29 +354,29 @@ def main():
 
     serving = None
     if args.serving > 0:
-        log(f"serving: {args.serving} requests ...")
-        reqs = make_requests("serving", args.serving, 5000)
+        log(f"serving: {args.serving} requests, ICs ...")
+        reqs = serving_requests(args.serving)
+        ics = [host_ics(spec) for spec, _, _ in reqs]
+        torch.cuda.empty_cache()
         budget = 240 * 10 ** 9
-        res, wall = run_server(reqs, args.serving_slots, budget, 2, realtime=True)
-        serving = serving_report(reqs, res, wall, args.serving_slots, budget, "fp16")
-        del reqs
+        log("serving at 4 requests/s ...")
+        res, wall = run_server(reqs, ics, args.serving_slots, budget, 2)
+        serving = serving_report(reqs, res, wall, args.serving_slots, budget, "fp16", 4.0)
         log(f"serving p50 {serving['p50_ms']:.0f} ms, p99 {serving['p99_ms']:.0f} ms, "
             f"{serving['particle_steps_per_s']:.3e} particle-steps/s")
+        log("serving stress: the same stream at 40 requests/s ...")
+        res, wall = run_server(reqs, ics, args.serving_slots, budget, 2, rate_scale=10.0)
+        serving["stress"] = serving_report(reqs, res, wall, args.serving_slots, budget, "fp16", 40.0)
+        log(f"stress p50 {serving['stress']['p50_ms']:.0f} ms, p99 {serving['stress']['p99_ms']:.0f} ms, "
+            f"admission wait p99 {serving['stress']['admission_wait_p99_ms']:.0f} ms")
+        del reqs, ics
 
     batched = None
     if args.batched > 0:
         log(f"batched ensemble: {args.batched} boxes ...")
-        reqs = make_requests("batched", args.batched, 4000)
-        budget = 240 * 10 ** 9
-        res_k, wall_k = run_server(reqs, args.batched_slots, budget, -1, realtime=False)
-        res_1, wall_1 = run_server(reqs, 1, budget, -1, realtime=False)
-        ps = sum(sp.n_side ** 3 * st for sp, _, _, st, _ in reqs)
-        batched = {"boxes": len(reqs), "slots": args.batched_slots, "particles": sum(sp.n_side ** 3 for sp, *_ in reqs),
-                   "steps_per_box": 16, "concurrent_particle_steps_per_s": ps / wall_k,
-                   "one_at_a_time_particle_steps_per_s": ps / wall_1, "speedup": wall_1 / wall_k,
-                   "workload": "sides from {64,96,128,192,256}, n uniform in [-2.5,-1], rms 0.5, FP32"}
-        del reqs
-        log(f"batched: {batched['speedup']:.2f}x over one at a time")
+        batched = run_ensemble_bench(args.batched, args.batched_steps)
+        log(f"batched: {batched['ensemble_particle_steps_per_s']:.3e} particle-steps/s, "
+            f"{batched['speedup']:.2f}x over one box at a time, schedule {batched['schedule']}")
 
     total_stage_ms = sum(s["total_ms"] for s in stages)
     for s in sorted(stages, key=lambda s: -s["total_ms"]):

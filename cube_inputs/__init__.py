@@ -11,6 +11,6 @@ at sizes where the oracle cannot encode a billion particles in seconds.
 
 from .configs import BoxSpec, CONFIGS, config, served_box
 from .lattice import lattice_run_state
-from .zeldovich import zeldovich_ics, plane_wave_ics
+from .zeldovich import zeldovich_ics, zeldovich_ics_device, plane_wave_ics
 
-__all__ = ["BoxSpec", "CONFIGS", "config", "served_box", "zeldovich_ics", "plane_wave_ics", "lattice_run_state"]
+__all__ = ["BoxSpec", "CONFIGS", "config", "served_box", "zeldovich_ics", "zeldovich_ics_device", "plane_wave_ics", "lattice_run_state"]

@@ -99,3 +99,59 @@ def plane_wave_ics(n: int, amplitude: float, dt: float, mode: int = 1):
     pos = np.mod(q + psi, float(n))
     vel = psi * np.exp(-0.5 * dt)
     return q, pos, vel
+
+
+def zeldovich_ics_device(n: int, spectral_index: float, rms_disp: float, seed: int, dt: float,
+                         device="cuda"):
+    """The recipe of zeldovich_ics (the same seeded white noise, drawn on the
+    host) with the transforms on a GPU through torch, for workloads of many
+    boxes: float64 up to 256^3, float32 above.  Returns float32 (pos, vel)
+    tensors of shape (n^3, 3) on `device`, lattice order.  Rounding differs
+    from the host version in the last bits: use one or the other for inputs
+    that are compared."""
+    import torch
+    real_np = np.float64 if n <= 256 else np.float32
+    real_t = torch.float64 if n <= 256 else torch.float32
+    rng = np.random.default_rng(seed)
+    noise = torch.from_numpy(rng.standard_normal((n, n, n), dtype=real_np)).to(device)   # axes (z, y, x)
+    dk = torch.fft.rfftn(noise)
+    del noise
+    kz = torch.fft.fftfreq(n, d=1.0 / n, dtype=real_t, device=device)
+    kx = torch.fft.rfftfreq(n, d=1.0 / n, dtype=real_t, device=device)
+    s = 2.0 * np.pi / n
+    KZ = (kz * s)[:, None, None]
+    KY = (kz * s)[None, :, None]
+    KX = (kx * s)[None, None, :]
+    k2 = KX * KX + KY * KY + KZ * KZ
+    k2[0, 0, 0] = 1.0
+    amp = k2 ** (spectral_index / 4.0)
+    amp[0, 0, 0] = 0.0
+    if n % 2 == 0:
+        nyq = n // 2
+        amp[nyq, :, :] = 0.0
+        amp[:, nyq, :] = 0.0
+        amp[:, :, nyq] = 0.0
+    dk = dk * amp
+    del amp
+    inv_k2 = 1.0 / k2
+    del k2
+    psi = torch.empty((3, n, n, n), dtype=real_t, device=device)
+    for c, K in enumerate((KX, KY, KZ)):
+        psi[c] = torch.fft.irfftn(dk * (1j * K * inv_k2), s=(n, n, n))
+    del dk, inv_k2
+    rms = torch.sqrt(sum(torch.sum(psi[c].double() ** 2) for c in range(3)) / n ** 3)
+    psi *= (rms_disp / rms).to(real_t)
+    N = n ** 3
+    pos = torch.empty((N, 3), dtype=torch.float32, device=device)
+    vel = torch.empty((N, 3), dtype=torch.float32, device=device)
+    lattice = torch.arange(n, dtype=torch.float64, device=device) + 0.5
+    shape = [(1, 1, n), (1, n, 1), (n, 1, 1)]
+    damp = float(np.exp(-0.5 * dt))
+    for c in range(3):
+        comp = psi[c].double()
+        x = torch.remainder(comp + lattice.reshape(shape[c]), float(n)).float()
+        x[x >= float(n)] = 0.0
+        pos[:, c] = x.reshape(-1)
+        vel[:, c] = (comp * damp).float().reshape(-1)
+        del comp, x
+    return pos, vel
