@@ -2,7 +2,8 @@
 times (64 tiles per batch), on outputs the oracle can compute tile by tile:
 forces on 32 sampled tiles (the tiles holding the runs, their face
 neighbours, whose buffers hold run particles, and seeded others), the whole
-512^3 coarse potential, and one step on a run tile.
+512^3 coarse potential, and one step on a run tile -- in the plain mode, the
+comoving background and the cell-mean velocity codec.
 
 Input: the 2-per-axis lattice (8 particles per coarse cell) whose CIC density
 is exactly uniform on both meshes, with runs of cells whose particles are
@@ -136,21 +137,9 @@ def test_full_size_forces_on_sampled_tiles(full):
         assert np.abs(full.got[t] - a_ref).max() <= 1e-4 * scale, t
 
 
-def test_full_size_step_on_sampled_tile(full):
-    """One step: velocity scale exact, mass conserved, and the particles that
-    land in the interior cells of the run tile arrive with the oracle's bytes,
-    in the oracle's stable order."""
-    from oracle import codec, step
-    box, st = full.box, full.state
-    assert st["counts"].sum() == box.n_side ** 3
-    assert st["s"] == codec.next_velocity_scale(box, S_V, full.M)
-
-    t = full.ta
-    tgt, Qt, a = full.ref[t]
-    old = types.SimpleNamespace(u=full.u[:, tgt], s=S_V, M=full.M, m=full.m[:, tgt], quanta=lambda: Qt)
-    u_new, s_new, _, _ = step.kick(box, old, a)
-    Q_new, carry = step.drift(box, old, u_new, s_new)
-    assert np.abs(carry).max() <= 1
+def _interior(box, t, Q_new, tgt):
+    """Particles of tile t that land in its interior cells: their new
+    canonical cells, and the stable new order (by cell, then old index)."""
     cx, cy, cz = (Q_new // 256).T
     Tc = box.Tc
     tx, ty, tz = box.tile_coords(t)
@@ -158,27 +147,129 @@ def test_full_size_step_on_sampled_tile(full):
     inner = (lx >= 1) & (lx <= Tc - 2) & (ly >= 1) & (ly <= Tc - 2) & (lz >= 1) & (lz <= Tc - 2)
     dest = box.canon(cx, cy, cz)[inner]
     order = np.lexsort((tgt[inner], dest))          # new order: by cell, then old order (stable)
-    dest = dest[order]
-    exp_m = (Q_new[inner] % 256)[order].T
-    exp_u = u_new[inner][order].T
-
     r = np.arange(1, Tc - 1)
     zz, yy, xx = np.meshgrid(r + tz * Tc, r + ty * Tc, r + tx * Tc, indexing="ij")
     cells = np.sort(box.canon(xx.ravel(), yy.ravel(), zz.ravel()))
+    return inner, dest[order], order, cells
+
+
+def _matched(st, cells, dest):
+    """Storage positions of the library's and the oracle's particles of the
+    interior cells whose counts agree (>= 99.9% of the cells must)."""
+    from oracle.pm import _expand_ranges
     cnt_g = st["counts"][cells].astype(np.int64)
     cnt_o = np.bincount(np.searchsorted(cells, dest), minlength=cells.size)
     same_cells = cnt_g == cnt_o
     assert np.mean(same_cells) >= 0.999
     off_new = np.zeros(st["counts"].size + 1, np.int64)
     np.cumsum(st["counts"], out=off_new[1:])
-    from oracle.pm import _expand_ranges
     gi = _expand_ranges(off_new[cells[same_cells]], cnt_g[same_cells])
     oi = _expand_ranges((np.cumsum(cnt_o) - cnt_o)[same_cells], cnt_o[same_cells])
+    return gi, oi, same_cells
+
+
+def _check_linear_step(full, box, st):
+    """The particles that land in the interior cells of the run tile arrive
+    with the oracle's bytes, in the oracle's stable order."""
+    from oracle import codec, step
+    assert st["counts"].sum() == box.n_side ** 3
+    assert st["s"] == codec.next_velocity_scale(box, S_V, full.M)
+    t = full.ta
+    tgt, Qt, a = full.ref[t]
+    old = types.SimpleNamespace(u=full.u[:, tgt], s=S_V, M=full.M, m=full.m[:, tgt], quanta=lambda: Qt, step=0)
+    u_new, s_new, _, _ = step.kick(box, old, a)
+    Q_new, carry = step.drift(box, old, u_new, s_new)
+    assert np.abs(carry).max() <= 1
+    inner, dest, order, cells = _interior(box, t, Q_new, tgt)
+    exp_m = (Q_new[inner] % 256)[order].T
+    exp_u = u_new[inner][order].T
+    gi, oi, _ = _matched(st, cells, dest)
     dm = np.abs(st["m"][:, gi].astype(np.int64) - exp_m[:, oi]).max(axis=0)
     du = np.abs(st["u"][:, gi].astype(np.int64) - exp_u[:, oi]).max(axis=0)
     print(f"step: {gi.size} particles compared, exact {np.mean((dm == 0) & (du == 0)):.6f}")
     assert np.mean((dm == 0) & (du == 0)) >= 0.999
     assert dm.max() <= 1 and du.max() <= 1
+
+
+def test_full_size_step_on_sampled_tile(full):
+    """One step: velocity scale exact, mass conserved, and the particles that
+    land in the interior cells of the run tile arrive with the oracle's bytes,
+    in the oracle's stable order."""
+    _check_linear_step(full, full.box, full.state)
+
+
+def test_full_size_comoving_step_on_sampled_tile(full):
+    """The comoving background (kick by K_n, drift by D_n of the step in the
+    scale factor) at 1024^3 in the benchmark's launch configuration: the same
+    forces, and the run tile's particles arrive with the oracle's bytes."""
+    import oracle
+    from paper_2003_03931_amd import CubeBox
+    spec = full.spec.with_(comoving=1, omega_m=0.3, omega_l=0.7, a_start=0.05, dt=float(np.float32(0.0025)))
+    box = oracle.Box.from_spec(spec).validate()
+    with CubeBox(spec, tiles_per_batch=BATCH) as g:
+        g.set_state(full.counts, full.m, full.u, S_V, full.M)
+        g.step(1)
+        st = g.get_state()
+    _check_linear_step(full, box, st)
+
+
+def test_full_size_cell_mean_codec(full):
+    """Eq. (3)'s cell-mean velocity codec at 1024^3 in the benchmark's launch
+    configuration, on the run tile: decoded velocities equal the oracle's
+    decode; after one step the interior cells of the tile hold the oracle's
+    FP32 cell means (V1) to the FP32 rounding of the kicked velocities, and
+    their particles the oracle's position bytes and codes (V2, with the
+    library's box-wide sigma, V3), in stable order."""
+    import oracle
+    from oracle import step, vcodec
+    from paper_2003_03931_amd import CubeBox
+    spec = full.spec.with_(vel_codec=1)
+    box = oracle.Box.from_spec(spec).validate()
+    rng = np.random.default_rng(3003)
+    vc = (0.05 * rng.standard_normal((3, box.n_cells))).astype(np.float32)
+    t = full.ta
+    tgt, Qt, a = full.ref[t]
+    with CubeBox(spec, tiles_per_batch=BATCH) as g:
+        g.set_state(full.counts, full.m, full.u, S_V, full.M, vc=vc)
+        _, vel = g.decompress()
+        v_dec = vel[torch.from_numpy(tgt).to(vel.device)].cpu().numpy()
+        del vel
+        torch.cuda.empty_cache()
+        g.step(1)
+        st = g.get_state()
+    cells_t = box.canon(*(Qt // 256).T)
+    v = vc.T[cells_t].astype(np.float64) + vcodec.decode_deviation(full.u[:, tgt].T, S_V)
+    assert np.array_equal(v_dec, v.astype(np.float32))
+    # the kick (FP64, held in FP32) and the exact drift of V4
+    old = types.SimpleNamespace(m=full.m[:, tgt], quanta=lambda: Qt, step=0,
+                                velocities=lambda: v)
+    v32 = step.kick_cell_mean(box, old, a)
+    Q_new, carry = step.drift_velocity(box, old, v32)
+    assert np.abs(carry).max() <= 1
+    inner, dest, order, cells = _interior(box, t, Q_new, tgt)
+    vs = v32[inner][order].astype(np.float64)
+    # new cell means of the interior cells (sequential FP64 sums in the new order)
+    cnt_o = np.bincount(np.searchsorted(cells, dest), minlength=cells.size)
+    vc_new = vcodec.cell_means(cnt_o, vs)
+    sigma = st["s"]
+    assert sigma > 0 and np.frexp(sigma)[0] == 0.5          # a power of two (V3)
+    cell_of = np.repeat(np.arange(cells.size), cnt_o)
+    u_exp, _ = vcodec.encode_deviation(vs - vc_new[cell_of].astype(np.float64), sigma)
+    gi, oi, same_cells = _matched(st, cells, dest)
+    # the kicked FP32 velocities carry the FP32 force's rounding in their last
+    # bits, so a cell mean matches to a few FP32 ulps of the velocities
+    vc_gpu = st["vc"][:, cells].T.astype(np.float64)
+    vscale = np.abs(vs).max()
+    dvc = np.abs(vc_gpu - vc_new.astype(np.float64)).max(axis=1)[same_cells]
+    print(f"cell-mean codec: cell means max |diff| {dvc.max():.3e} (velocity scale {vscale:.3e}), "
+          f"{np.mean(dvc == 0):.4f} of the cells identical")
+    assert dvc.max() <= 1e-6 * vscale
+    exp_m = (Q_new[inner] % 256)[order].T
+    dm = np.abs(st["m"][:, gi].astype(np.int64) - exp_m[:, oi]).max(axis=0)
+    du = np.abs(st["u"][:, gi].astype(np.int64) - u_exp.T[:, oi].astype(np.int64)).max(axis=0)
+    print(f"cell-mean codec step: {gi.size} particles, exact {np.mean((dm == 0) & (du == 0)):.6f}")
+    assert np.mean((dm == 0) & (du == 0)) >= 0.999
+    assert dm.max() <= 1
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16", 2.0 ** -8), ("fp16", 2.0 ** -11)])
