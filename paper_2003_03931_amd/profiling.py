@@ -37,6 +37,7 @@ STAGE_KERNEL = {
     "gather_kick_drift": "k_gather<0,",
     "scan_counts": "k_tile_scan",
     "compact": "k_compact_brick",
+    "velocity_encode": "k_vc_encode",
     "pp_force": "k_pp",
 }
 COPY_KERNELS = ("elementwise", "copyBuffer")
@@ -44,8 +45,8 @@ COPY_KERNELS = ("elementwise", "copyBuffer")
 
 # sources whose kernels the profiled plain step never launches: the
 # extended PP force (pp_range > 0), the cell-mean velocity codec
-# (vel_codec = 1) and the request server
-NOT_IN_STEP = ("pp.hip", "vcodec.hip", "server.cpp")
+# (vel_codec = 1), the request server and the ensemble runner
+NOT_IN_STEP = ("pp.hip", "vcodec.hip", "server.cpp", "ensemble.cpp")
 
 
 def source_digest():
