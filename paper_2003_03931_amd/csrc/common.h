@@ -167,6 +167,17 @@ __device__ __forceinline__ int64_t xcd_logical_block() {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also releases
+// global memory, which makes every wave wait for its own outstanding global
+// stores at the barrier; a persistent loop that stores one item's results
+// and meets at the top of the next item would expose the store latency on
+// every item.  Use this where the barrier protects LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace cube
 
 namespace cube {

@@ -218,15 +218,31 @@ struct Dft<10, INV> {
 // consecutive threads take consecutive pencils (strided pencils), otherwise
 // consecutive butterflies of one pencil (contiguous pencils), so that lanes
 // touch consecutive LDS words either way.  NS = product of the radices of
-// the passes already done.
-template <int P_, int SE_, int SP_, bool WFAST_, int NT_>
+// the passes already done.  WAVE: the pencils belong to one wave (NT = 64),
+// which synchronises only with itself, so the waves of a workgroup need not
+// run their passes in step; the first npen of the P pencils are live.
+template <int P_, int SE_, int SP_, bool WFAST_, int NT_, bool WAVE_ = false>
 struct Lay {
     static constexpr int P = P_, SE = SE_, SP = SP_, NT = NT_;
-    static constexpr bool WFAST = WFAST_;
+    static constexpr bool WFAST = WFAST_, WAVE = WAVE_;
 };
 
+// LDS ordering among the lanes of one wave: its LDS operations complete in
+// issue order, so it is enough to keep the compiler from moving them across
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class L>
+__device__ __forceinline__ void lay_sync() {
+    if (L::WAVE) wave_sync();
+    else lds_barrier();
+}
+
 template <int N, class L, bool INV, int NS, int R>
-__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ tw, int tid, int npen) {
     constexpr int NB = N / R;
     constexpr int TOTAL = NB * L::P;
     constexpr int IT = (TOTAL + L::NT - 1) / L::NT;
@@ -234,9 +250,9 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = tid + it * L::NT;
-        if (TOTAL % L::NT == 0 || b < TOTAL) {
-            const int j = L::WFAST ? b / L::P : b % NB;
-            const int w = L::WFAST ? b % L::P : b / NB;
+        const int j = L::WFAST ? b / L::P : b % NB;
+        const int w = L::WFAST ? b % L::P : b / NB;
+        if ((TOTAL % L::NT == 0 || b < TOTAL) && (!L::WAVE || w < npen)) {
             const float2* col = lds + w * L::SP;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[it][r] = col[(j + r * NB) * L::SE];
@@ -251,29 +267,29 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
             Dft<R, INV>::run(v[it]);
         }
     }
-    __syncthreads();
+    lay_sync<L>();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = tid + it * L::NT;
-        if (TOTAL % L::NT == 0 || b < TOTAL) {
-            const int j = L::WFAST ? b / L::P : b % NB;
-            const int w = L::WFAST ? b % L::P : b / NB;
+        const int j = L::WFAST ? b / L::P : b % NB;
+        const int w = L::WFAST ? b % L::P : b / NB;
+        if ((TOTAL % L::NT == 0 || b < TOTAL) && (!L::WAVE || w < npen)) {
             const int k = j % NS;
             float2* col = lds + w * L::SP + ((j / NS) * NS * R + k) * L::SE;
 #pragma unroll
             for (int r = 0; r < R; ++r) col[r * NS * L::SE] = v[it][r];
         }
     }
-    __syncthreads();
+    lay_sync<L>();
 }
 
 template <int N, class L, bool INV, int NS>
-__device__ __forceinline__ void run_passes(float2*, const float2*, int) {}
+__device__ __forceinline__ void run_passes(float2*, const float2*, int, int) {}
 
 template <int N, class L, bool INV, int NS, int R, int... Rest>
-__device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw, int tid) {
-    stockham_pass<N, L, INV, NS, R>(lds, tw, tid);
-    run_passes<N, L, INV, NS * R, Rest...>(lds, tw, tid);
+__device__ __forceinline__ void run_passes(float2* lds, const float2* __restrict__ tw, int tid, int npen) {
+    stockham_pass<N, L, INV, NS, R>(lds, tw, tid, npen);
+    run_passes<N, L, INV, NS * R, Rest...>(lds, tw, tid, npen);
 }
 
 // Radix plan per supported size.
@@ -285,8 +301,9 @@ struct Plan;
         template <class L, bool INV>                                             \
         __device__ __forceinline__ static void run(float2* lds,                  \
                                                    const float2* __restrict__ tw, \
-                                                   int tid = threadIdx.x) {      \
-            run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw, tid);                \
+                                                   int tid = threadIdx.x,        \
+                                                   int npen = L::P) {            \
+            run_passes<NN, L, INV, 1, __VA_ARGS__>(lds, tw, tid, npen);          \
         }                                                                        \
     };
 CUBE_FFT_PLAN(16, 4, 4)
@@ -315,8 +332,9 @@ struct PlanZ : Plan<N> {};
 template <>
 struct PlanZ<160> {
     template <class L, bool INV>
-    __device__ __forceinline__ static void run(float2* lds, const float2* __restrict__ tw, int tid = threadIdx.x) {
-        run_passes<160, L, INV, 1, 5, 4, 8>(lds, tw, tid);
+    __device__ __forceinline__ static void run(float2* lds, const float2* __restrict__ tw, int tid = threadIdx.x,
+                                               int npen = L::P) {
+        run_passes<160, L, INV, 1, 5, 4, 8>(lds, tw, tid, npen);
     }
 };
 
@@ -365,7 +383,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
             const int i = KIND == 0 ? e % N : e / W, w = KIND == 0 ? e / N : e % W;
             return w * LDN + i;
         });
-    __syncthreads();
+    lds_barrier();
     using L = Lay<W, 1, LDN, false, kFftThreads>;
     if (MODE == 1) {
         Plan<N>::template run<L, true>(lds, tw);
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(float2* __restrict__ data, 
             }
             lds[w * LDN + i] = v;
         }
-        __syncthreads();
+        lds_barrier();
         Plan<N>::template run<L, true>(lds, tw);
     }
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
@@ -500,13 +518,13 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __rest
     int plane = blockIdx.x;
     if (plane < nplanes) prefetch(plane);
     for (; plane < nplanes; plane += gridDim.x) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
             if (TOT % kPlaneThreads == 0 || e < TOT) lds[(e / N) * RS + e % N] = make_float2(re[u], im[u]);
         }
-        __syncthreads();
+        lds_barrier();
         if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
         // a fresh, opaque thread index per plane keeps the passes' LDS
         // address arithmetic from being hoisted out of the plane loop
@@ -537,7 +555,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane(const float* __rest
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         Plan<N>::template run<Lay<NH, NH, 1, true, kPlaneThreads>, false>(lds, tw, tid);
         typename S::T* dst = spec_tiles + (int64_t)(plane / N) * N * N * NH + (int64_t)(plane % N) * N * NH;
         bool bad = false;
@@ -581,13 +599,13 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
     int plane = blockIdx.x;
     if (plane < nplanes) prefetch(plane);
     for (; plane < nplanes; plane += gridDim.x) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
             if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = S::get(pv[u], sc_in);
         }
-        __syncthreads();
+        lds_barrier();
         if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
         // a fresh, opaque thread index per plane keeps the passes' LDS
         // address arithmetic from being hoisted out of the plane loop
@@ -615,7 +633,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
                 if (k < N) row[k] = vz[t];
             }
         }
-        __syncthreads();
+        lds_barrier();
         Plan<N>::template run<Lay<HALF, 1, RS, false, kPlaneThreads>, true>(lds, tw, tid);
         float* dst = real_tiles + (int64_t)(plane / W) * N * N * N + (int64_t)(lo + plane % W) * N * N;
         // element e = (y - lo) W + (x - lo), walked with increments instead of divisions
@@ -628,6 +646,232 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane(const typename Spec
             if (x >= hi) {
                 x -= W;
                 ++y;
+            }
+        }
+    }
+}
+
+// Wave-owned variants (N/2 divisible by the 16 waves): wave w owns complex
+// rows [w R, (w+1) R), R = N/32, for the row transforms and the Hermitian
+// step, and up to C = ceil((N/2+1)/16) columns for the column transforms.
+// Inside each phase a wave synchronises only with itself, so one wave's LDS
+// traffic overlaps another's arithmetic; the workgroup meets three times per
+// plane (plane in LDS, rows done, columns done).  The forward kernel loads
+// each wave's own rows from HBM, the inverse one stores each wave's own rows.
+// Makes the compiler wait for a register's pending load here.
+__device__ __forceinline__ void touch_reg(float2 v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+__device__ __forceinline__ void touch_reg(uint32_t v) { asm volatile("" ::"v"(v)); }
+
+template <int N>
+struct PlaneSplit {
+    static constexpr int NW = kPlaneThreads / kWave;
+    static constexpr int HALF = N / 2, NH = N / 2 + 1, RS = N + 2;
+    static constexpr int RPW = HALF / NW;                  // complex rows per wave
+    static constexpr int CPW = (NH + NW - 1) / NW;         // columns per wave (the last waves fewer)
+    static constexpr bool ok = HALF % NW == 0;
+};
+
+template <int N, int FMT>
+__global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane_w(const float* __restrict__ real_tiles,
+                                                               typename SpecStore<FMT>::T* __restrict__ spec_tiles,
+                                                               const float2* __restrict__ tw_g, int nplanes,
+                                                               float sc_out, int32_t* __restrict__ flag) {
+    using S = SpecStore<FMT>;
+    using PS = PlaneSplit<N>;
+    constexpr int NH = PS::NH, RS = PS::RS, RPW = PS::RPW, CPW = PS::CPW;
+    constexpr int EPW = RPW * N;                             // complex elements of a wave's rows
+    constexpr int PER = (EPW + kWave - 1) / kWave;
+    constexpr int KIT = (NH + kWave - 1) / kWave;
+    __shared__ float2 lds[PS::HALF * RS];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += kPlaneThreads) tw[i] = tw_g[i];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int j0 = wv * RPW;
+    const int c0 = wv * CPW, ncol = NH - c0 < CPW ? NH - c0 : CPW;
+    float re[PER], im[PER];
+    // lane indices pass through an opaque copy per use, so that per-element
+    // offsets are recomputed each plane instead of held in registers
+    auto prefetch = [&](int pl) {
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const float* src = real_tiles + (int64_t)(pl / N) * N * N * N + (int64_t)(pl % N) * N * N + 2 * j0 * N;
+        // every lane loads (the last round's idle lanes re-read the wave's
+        // last element): branch-free loads keep the wait counts exact
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            int e = ln + u * kWave;
+            if ((u + 1) * kWave > EPW) e = e < EPW ? e : EPW - 1;
+            const int j = e / N, x = e % N;
+            re[u] = src[(2 * j) * N + x];
+            im[u] = src[(2 * j + 1) * N + x];
+        }
+    };
+    bool bad = false;
+    int plane = blockIdx.x;
+    if (plane < nplanes) prefetch(plane);
+    // the first plane's loads are waited for here, so that no path into the
+    // loop's top has loads pending and the top never waits
+#pragma unroll
+    for (int u = 0; u < PER; ++u) asm volatile("" ::"v"(re[u]), "v"(im[u]));
+    for (; plane < nplanes; plane += gridDim.x) {
+        lds_barrier();                                     // the previous plane's spectrum is stored
+        float2* rows = lds + j0 * RS;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = lane + u * kWave;
+            if ((u + 1) * kWave <= EPW || e < EPW) rows[(e / N) * RS + e % N] = make_float2(re[u], im[u]);
+        }
+        wave_sync();
+        if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
+        asm volatile("" ::: "memory");                       // keep the prefetch loads here, ahead of the passes
+        int tid = lane;
+        asm volatile("" : "+v"(tid));
+        Plan<N>::template run<Lay<RPW, 1, RS, false, kWave, true>, false>(rows, tw, tid);
+        // A(k) = (Z(k) + conj Z(N-k)) / 2, B(k) = (Z(k) - conj Z(N-k)) / 2i, k = 0..N/2
+        for (int j = 0; j < RPW; ++j) {
+            float2* row = rows + j * RS;
+            float2 va[KIT], vb[KIT];
+#pragma unroll
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < NH) {
+                    const float2 z1 = row[k];
+                    const float2 z2 = row[k == 0 ? 0 : N - k];
+                    va[t] = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+                    vb[t] = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < KIT; ++t) {
+                const int k = lane + t * kWave;
+                if (k < NH) {
+                    row[k] = va[t];
+                    row[NH + k] = vb[t];
+                }
+            }
+            wave_sync();
+        }
+        lds_barrier();                                     // every row transformed
+        if (ncol > 0)
+            Plan<N>::template run<Lay<CPW, NH, 1, true, kWave, true>, false>(lds + c0, tw, tid, ncol);
+        lds_barrier();                                     // every column transformed
+        // Loads and stores share one in-order counter: wait for the next
+        // plane's loads (issued long before, so this costs nothing) ahead of
+        // the stores, so that the top of the next iteration does not wait
+        // for these stores to complete.
+#pragma unroll
+        for (int u = 0; u < PER; ++u) asm volatile("" ::"v"(re[u]), "v"(im[u]));
+        typename S::T* dst = spec_tiles + (int64_t)(plane / N) * N * N * NH + (int64_t)(plane % N) * N * NH;
+        constexpr int SPT = (N * NH + kPlaneThreads - 1) / kPlaneThreads;
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int e = t + u * kPlaneThreads;
+            if ((u + 1) * kPlaneThreads <= N * NH || e < N * NH) dst[e] = S::put(lds[e], sc_out, bad);
+        }
+    }
+    if (FMT == SPEC_F16) raise_flag(bad, flag);
+}
+
+template <int N, int FMT>
+__global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename SpecStore<FMT>::T* __restrict__ spec_tiles,
+                                                               float* __restrict__ real_tiles,
+                                                               const float2* __restrict__ tw_g, int nplanes,
+                                                               float sc_in, int lo, int hi) {
+    using S = SpecStore<FMT>;
+    using PS = PlaneSplit<N>;
+    constexpr int NH = PS::NH, RS = PS::RS, RPW = PS::RPW, CPW = PS::CPW, HALF = PS::HALF;
+    constexpr int TOT = N * NH;
+    constexpr int PER = (TOT + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int KIT = (N + kWave - 1) / kWave;
+    // only the window [lo, hi)^3 of each tile is produced: planes lo..hi-1,
+    // and in each plane the rows and columns lo..hi-1
+    const int W = hi - lo;
+    __shared__ float2 lds[HALF * RS];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += kPlaneThreads) tw[i] = tw_g[i];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int j0 = wv * RPW;
+    const int c0 = wv * CPW, ncol = NH - c0 < CPW ? NH - c0 : CPW;
+    // the wave's real rows [2 j0, 2 j0 + 2 RPW) that fall in the window
+    const int ya = 2 * j0 > lo ? 2 * j0 : lo, yb = 2 * (j0 + RPW) < hi ? 2 * (j0 + RPW) : hi;
+    const bool rows_live = ya < yb;
+    typename S::T pv[PER];
+    auto prefetch = [&](int pl) {
+        const typename S::T* src = spec_tiles + (int64_t)(pl / W) * N * N * NH + (int64_t)(lo + pl % W) * N * NH;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) pv[u] = src[e];
+        }
+    };
+    int plane = blockIdx.x;
+    if (plane < nplanes) prefetch(plane);
+    // the first plane's loads are waited for here, so that no path into the
+    // loop's top has loads pending and the top never waits
+#pragma unroll
+    for (int u = 0; u < PER; ++u) touch_reg(pv[u]);
+    for (; plane < nplanes; plane += gridDim.x) {
+        lds_barrier();                                     // the previous plane's rows are stored
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * kPlaneThreads;
+            if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = S::get(pv[u], sc_in);
+        }
+        lds_barrier();                                     // the plane's spectrum is in LDS
+        if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
+        int tid = lane;
+        asm volatile("" : "+v"(tid));
+        if (ncol > 0)
+            Plan<N>::template run<Lay<CPW, NH, 1, true, kWave, true>, true>(lds + c0, tw, tid, ncol);
+        lds_barrier();                                     // every column transformed
+        // Loads and stores share one in-order counter: wait for the next
+        // plane's loads (issued long before) ahead of this plane's stores, so
+        // that the top of the next iteration does not wait for the stores.
+#pragma unroll
+        for (int u = 0; u < PER; ++u) touch_reg(pv[u]);
+        if (rows_live) {
+            float2* rows = lds + j0 * RS;
+            // complex row Z(k) = A(k) + i B(k) over k = 0..N-1 (Hermitian extension of A, B)
+            for (int j = 0; j < RPW; ++j) {
+                float2* row = rows + j * RS;
+                float2 vz[KIT];
+#pragma unroll
+                for (int t = 0; t < KIT; ++t) {
+                    const int k = lane + t * kWave;
+                    if (k < N) {
+                        const int kk = k <= HALF ? k : N - k;
+                        const float sg = k <= HALF ? 1.0f : -1.0f;
+                        const float2 a = row[kk], b = row[NH + kk];
+                        vz[t] = make_float2(a.x - sg * b.y, sg * a.y + b.x);
+                    }
+                }
+                wave_sync();
+#pragma unroll
+                for (int t = 0; t < KIT; ++t) {
+                    const int k = lane + t * kWave;
+                    if (k < N) row[k] = vz[t];
+                }
+                wave_sync();
+            }
+            Plan<N>::template run<Lay<RPW, 1, RS, false, kWave, true>, true>(rows, tw, tid);
+            float* dst = real_tiles + (int64_t)(plane / W) * N * N * N + (int64_t)(lo + plane % W) * N * N;
+            // elements (y, x) of rows [ya, yb), x in [lo, hi), walked with increments
+            int y = ya, x = lo + lane;
+            while (x >= hi) {
+                x -= W;
+                ++y;
+            }
+            while (y < yb) {
+                const float2 v = lds[(y >> 1) * RS + x];
+                dst[y * N + x] = (y & 1) ? v.y : v.x;
+                x += kWave;
+                while (x >= hi) {
+                    x -= W;
+                    ++y;
+                }
             }
         }
     }
@@ -676,7 +920,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
             if (e < W * N) lds[(e % W) * LDN + e / W] = S::get(tmp[u], sc_in);
         }
     }
-    __syncthreads();
+    lds_barrier();
     using L = Lay<W, 1, LDN, false, kFftThreads>;
     PlanZ<N>::template run<L, false>(lds, tw);
     for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
@@ -685,7 +929,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
         const float2 v = lds[w * LDN + i];
         lds[w * LDN + i] = make_float2(v.x * gv, v.y * gv);
     }
-    __syncthreads();
+    lds_barrier();
     PlanZ<N>::template run<L, true>(lds, tw);
     bool bad = false;
     for (int e = threadIdx.x; e < W * (hi - lo); e += kFftThreads) {       // only z in [lo, hi) is used
@@ -727,15 +971,23 @@ void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* t
     if (ev) hipEventRecord(ev[0], s);
     const int nplanes = N * ntiles;
     const int blocks = std::min(nplanes, device_cus());
-    hipLaunchKernelGGL((k_r2c_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles, tw,
-                       nplanes, rho_store, flag);
+    if (PlaneSplit<N>::ok)
+        hipLaunchKernelGGL((k_r2c_plane_w<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles,
+                           tw, nplanes, rho_store, flag);
+    else
+        hipLaunchKernelGGL((k_r2c_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles,
+                           tw, nplanes, rho_store, flag);
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw,
                        green, rho_load, phi_store, flag, lo, hi);
     if (ev) hipEventRecord(ev[2], s);
     const int out_planes = (hi - lo) * ntiles;
-    hipLaunchKernelGGL((k_c2r_plane<N, FMT>), dim3(std::min(out_planes, device_cus())), dim3(kPlaneThreads), 0, s,
-                       spec_tiles, real_tiles, tw, out_planes, phi_load, lo, hi);
+    if (PlaneSplit<N>::ok)
+        hipLaunchKernelGGL((k_c2r_plane_w<N, FMT>), dim3(std::min(out_planes, device_cus())), dim3(kPlaneThreads),
+                           0, s, spec_tiles, real_tiles, tw, out_planes, phi_load, lo, hi);
+    else
+        hipLaunchKernelGGL((k_c2r_plane<N, FMT>), dim3(std::min(out_planes, device_cus())), dim3(kPlaneThreads), 0,
+                           s, spec_tiles, real_tiles, tw, out_planes, phi_load, lo, hi);
     if (ev) hipEventRecord(ev[3], s);
 }
 
