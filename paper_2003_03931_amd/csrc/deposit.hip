@@ -204,6 +204,118 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
     }
 }
 
+// Coarse-mesh deposit (one mesh cell per storage cell): a workgroup owns a
+// BW^3 cube of mesh cells and walks the (BW+2)^3 storage cells that can reach
+// it, one cell per thread.  Along each axis a particle at in-cell byte m
+// weighs (in 1/512 of a cell) 255 - 2m and 2m + 257 on the cells at offsets
+// -1 and 0 when m < 128, and 767 - 2m and 2m - 255 on offsets 0 and +1
+// otherwise; the thread sums the 27 products over its cell's particles in
+// 32-bit registers (each product is below 2^27, so a sum of 24 is exact;
+// larger cells are summed 24 particles at a time) and adds each sum that
+// lands in the cube to a 64-bit LDS accumulator: one LDS atomic per cell and
+// slot instead of eight per particle, and no two lanes of an atomic on one
+// address.  The bytes of 8 particles are loaded together and the next cell's
+// range is fetched while the current cell is summed.  Integer sums: the
+// result does not depend on the order and equals the particle-by-particle
+// deposit bit for bit.
+template <int BW>
+__global__ __launch_bounds__(kDepThreads) void k_coarse_deposit(Geom g, const int32_t* __restrict__ offsets,
+                                                                 Planes p, float2* __restrict__ out, double scale) {
+    constexpr int SW = BW + 2;
+    constexpr int NS = SW * SW * SW;
+    constexpr int U = 8;                          // particles whose bytes are in flight together
+    constexpr int CH = 3 * U;                     // particles per exact 32-bit partial sum
+    __shared__ __align__(16) unsigned long long acc[BW * BW * BW];
+    const int M = g.Nc;
+    const int nbx = (M + BW - 1) / BW;
+    const int b = (int)xcd_logical_block();
+    const int T0[3] = {(b % nbx) * BW, ((b / nbx) % nbx) * BW, (b / (nbx * nbx)) * BW};
+    const int bw[3] = {min(BW, M - T0[0]), min(BW, M - T0[1]), min(BW, M - T0[2])};
+    for (int i = threadIdx.x; i < BW * BW * BW / 2; i += kDepThreads)
+        reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
+    // particle range of window cell s (storage cell T0 - 1 + r); cells past a
+    // partial cube's reach are empty
+    auto range = [&](int s, int& st, int& en) {
+        const int rx = s % SW, ry = (s / SW) % SW, rz = s / (SW * SW);
+        st = en = 0;
+        if (s < NS && rx <= bw[0] + 1 && ry <= bw[1] + 1 && rz <= bw[2] + 1) {
+            const int64_t c = canon(g, wrapi(T0[0] - 1 + rx, M), wrapi(T0[1] - 1 + ry, M), wrapi(T0[2] - 1 + rz, M));
+            st = offsets[c];
+            en = offsets[c + 1];
+        }
+    };
+    int nst, nen;
+    range(threadIdx.x, nst, nen);
+    __syncthreads();
+    for (int s = threadIdx.x; s < NS; s += kDepThreads) {
+        const int st = nst, en = nen;
+        range(s + kDepThreads, nst, nen);                         // next cell's range in flight
+        const int r[3] = {s % SW, (s / SW) % SW, s / (SW * SW)};
+        for (int q0 = st; q0 < en; q0 += CH) {
+            const int q1 = min(en, q0 + CH);
+            unsigned a[27];
+#pragma unroll
+            for (int k = 0; k < 27; ++k) a[k] = 0u;
+            for (int qb = q0; qb < q1; qb += U) {
+                unsigned mm[U][3];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = min(qb + u, q1 - 1);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) mm[u][k] = p.m[k][q];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool live = qb + u < q1;
+                    unsigned w[3][3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const unsigned m = mm[u][k];
+                        const bool lo = m < 128u;
+                        w[k][0] = lo ? 255u - 2u * m : 0u;
+                        w[k][1] = lo ? 2u * m + 257u : 767u - 2u * m;
+                        w[k][2] = lo ? 0u : 2u * m - 255u;
+                    }
+                    if (!live) w[2][0] = w[2][1] = w[2][2] = 0u;
+                    unsigned wxy[9];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) wxy[3 * j + i] = (unsigned)__umul24(w[0][i], w[1][j]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int j = 0; j < 9; ++j) a[9 * k + j] += (unsigned)__umul24(wxy[j], w[2][k]);
+                }
+            }
+            // slot (i, j, k) lands on cube cell r + (i, j, k) - 2
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int tz = r[2] + k - 2;
+                if (tz < 0 || tz >= bw[2]) continue;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int ty = r[1] + j - 2;
+                    if (ty < 0 || ty >= bw[1]) continue;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const int tx = r[0] + i - 2;
+                        const unsigned v = a[9 * k + 3 * j + i];
+                        if (tx >= 0 && tx < bw[0] && v) atomicAdd(&acc[(tz * BW + ty) * BW + tx], (unsigned long long)v);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < BW * BW * BW; i += kDepThreads) {
+        const int ix = i % BW, iy = (i / BW) % BW, iz = i / (BW * BW);
+        if (ix >= bw[0] || iy >= bw[1] || iz >= bw[2]) continue;
+        const float v = (float)((double)acc[i] * scale - 1.0);
+        out[(int64_t)(T0[0] + ix) + (int64_t)M * ((T0[1] + iy) + (int64_t)M * (T0[2] + iz))] = make_float2(v, 0.0f);
+    }
+}
+
 // largest particle count of any 2 x 2 x 2 block of coarse cells (periodic).
 // Cells are visited in storage order (the +x, +y, +z neighbours are then
 // mostly 1, Tc and Tc^2 entries ahead); one atomic per workgroup.
@@ -246,12 +358,12 @@ int ilog2(int v) {
 
 void launch_coarse_deposit(const Geom& g, const int32_t* offsets, Planes p, float2* mesh, int32_t* /*overflow*/,
                            hipStream_t s) {
-    constexpr int BW = 8;
+    constexpr int BW = 16;
     const int nb = (g.Nc + BW - 1) / BW;
     // acc in units of 2^-27 particle; density = mass / H^3 with H = r / f
     const double scale = std::ldexp(1.0, -27) * ((double)g.f * g.f * g.f) / ((double)g.r * g.r * g.r);
-    hipLaunchKernelGGL((k_deposit<BW, DEP_COARSE, unsigned long long, 1000, 10240>), dim3(nb * nb * nb),
-                       dim3(kDepThreads), 0, s, g, offsets, p, reinterpret_cast<float*>(mesh), g.Nc, 1, 9, scale, 0);
+    hipLaunchKernelGGL((k_coarse_deposit<BW>), dim3(nb * nb * nb), dim3(kDepThreads), 0, s, g, offsets, p, mesh,
+                       scale);
 }
 
 void launch_fine_deposit(const Geom& g, const int32_t* offsets, Planes p, int tile0, int ntiles,
