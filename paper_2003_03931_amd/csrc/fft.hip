@@ -877,53 +877,61 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename Sp
     }
 }
 
+// Threads of a z-pencil workgroup (16 pencils): 320 at N = 160, where the
+// 5, 4, 8 passes then take 1.6, 2 and 1 butterflies per thread (256 threads
+// would leave 17% and 38% of the lanes idle in the last two).
+template <int N>
+constexpr int zconv_threads() { return N == 160 ? 320 : kFftThreads; }
+constexpr int kZMaxThreads = 320;
+
 // z pencils of the half spectrum: forward, times G (float octant), inverse.
 // Twiddles and the block's Green's values are staged in LDS with the data.
 template <int N, int FMT>
-__global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
+__global__ __launch_bounds__(kZMaxThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                             const float2* __restrict__ tw_g,
                                                             const float* __restrict__ green, float sc_in,
                                                             float sc_out, int32_t* __restrict__ flag, int lo,
                                                             int hi) {
     using S = SpecStore<FMT>;
     using T = typename S::T;
+    constexpr int ZT = zconv_threads<N>();
     constexpr int NH = N / 2 + 1;
     constexpr int W = 16;
     constexpr int LDN = N + 1;
     constexpr int PLANE = N * NH;
-    constexpr int U = 10;
+    constexpr int U = (W * N + ZT - 1) / ZT < 10 ? (W * N + ZT - 1) / ZT : 10;
     __shared__ float2 lds[W * LDN];
     __shared__ float2 tw[N];
     __shared__ float gl[W * NH];                   // G of this block's (ky, kx) pencils, by folded kz
     const int c0 = blockIdx.x * W;                 // flattened (ky, kx) of the first pencil
     T* g = spec_tiles + (int64_t)blockIdx.y * N * PLANE + c0;
-    for (int i = threadIdx.x; i < N; i += kFftThreads) tw[i] = tw_g[i];
+    for (int i = threadIdx.x; i < N; i += ZT) tw[i] = tw_g[i];
     // table is pencil-major ([ky][kx][kz], kz fastest): consecutive lanes read
     // consecutive kz of one pencil and keep that order in LDS (gl[w][kz])
-    for (int e = threadIdx.x; e < W * NH; e += kFftThreads) {
+    for (int e = threadIdx.x; e < W * NH; e += ZT) {
         const int fz = e % NH, w = e / NH;
         const int c = c0 + w;
         const int ky = c / NH, kx = c - ky * NH;
         gl[e] = green[((int64_t)fold(ky, N) * NH + kx) * NH + fz];
     }
     // element e: pencil w = e % W, kz = e / W (16 consecutive words per kz)
-    for (int base = 0; base < W * N; base += kFftThreads * U) {
+    for (int base = 0; base < W * N; base += ZT * U) {
         T tmp[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = base + u * kFftThreads + (int)threadIdx.x;
+            const int e = base + u * ZT + (int)threadIdx.x;
             if (e < W * N) tmp[u] = g[(int64_t)(e / W) * PLANE + (e % W)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = base + u * kFftThreads + (int)threadIdx.x;
+            const int e = base + u * ZT + (int)threadIdx.x;
             if (e < W * N) lds[(e % W) * LDN + e / W] = S::get(tmp[u], sc_in);
         }
     }
     lds_barrier();
-    using L = Lay<W, 1, LDN, false, kFftThreads>;
+    using L = Lay<W, 1, LDN, false, ZT>;
     PlanZ<N>::template run<L, false>(lds, tw);
-    for (int e = threadIdx.x; e < W * N; e += kFftThreads) {
+    for (int e = threadIdx.x; e < W * N; e += ZT) {
         const int w = e % W, i = e / W;
         const float gv = gl[w * NH + fold(i, N)];
         const float2 v = lds[w * LDN + i];
@@ -932,7 +940,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<F
     lds_barrier();
     PlanZ<N>::template run<L, true>(lds, tw);
     bool bad = false;
-    for (int e = threadIdx.x; e < W * (hi - lo); e += kFftThreads) {       // only z in [lo, hi) is used
+    for (int e = threadIdx.x; e < W * (hi - lo); e += ZT) {       // only z in [lo, hi) is used
         const int w = e % W, i = lo + e / W;
         g[(int64_t)i * PLANE + w] = S::put(lds[w * LDN + i], sc_out, bad);
     }
@@ -978,7 +986,7 @@ void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* t
         hipLaunchKernelGGL((k_r2c_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles,
                            tw, nplanes, rho_store, flag);
     if (ev) hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw,
+    hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(zconv_threads<N>()), 0, s, spec_tiles, tw,
                        green, rho_load, phi_store, flag, lo, hi);
     if (ev) hipEventRecord(ev[2], s);
     const int out_planes = (hi - lo) * ntiles;

@@ -130,7 +130,7 @@ __device__ __forceinline__ float gather_value(const LdsGrid& phi, const int i0[3
 // past the row's end (the mesh allocation is padded for the last row).
 // VC (step mode only): velocities in the cell-mean codec (Eq. (3)); the
 // kicked velocity is written to the FP32 working planes instead of codes.
-template <int MODE, int H, bool PER, bool VC = false>
+template <int MODE, int H, bool PER, bool VC = false, int RC = 0>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     constexpr int kLX = Halo<H>::LX, kLY = Halo<H>::LY, kLZ = Halo<H>::LZ;
     constexpr int kSlack = H & 1;                  // floats staged before the wanted ones
@@ -152,7 +152,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
     // a halted step (see StepScalars) writes nothing
     if (MODE == GATHER_STEP && *(volatile const int32_t*)&A.sc->halt) return;
     const Geom& g = A.g;
-    const int r = g.r;
+    // RC: fine cells per coarse cell fixed at compile time (0: read from g),
+    // which turns the brick's cell-index divisions into shifts
+    const int r = RC ? RC : g.r;
     const int BXc = kBX / r, BYc = kBY / r, BZc = kBZ / r;
     const int nrows = BYc * BZc;
     const int64_t lb = xcd_logical_block();
@@ -319,8 +321,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         locate(threadIdx.x, np_, nlx, nly, nlz);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            nm[a] = A.in.m[a][np_];
-            if (MODE == GATHER_STEP) nu[a] = A.in.u[a][np_];
+            nm[a] = A.in.m[a][(uint32_t)np_];
+            if (MODE == GATHER_STEP) nu[a] = A.in.u[a][(uint32_t)np_];
         }
     }
     for (int e = threadIdx.x; e < total; e += kGatherThreads) {
@@ -333,8 +335,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             locate(e + kGatherThreads, np_, nlx, nly, nlz);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                nm[a] = A.in.m[a][np_];
-                if (MODE == GATHER_STEP) nu[a] = A.in.u[a][np_];
+                nm[a] = A.in.m[a][(uint32_t)np_];
+                if (MODE == GATHER_STEP) nu[a] = A.in.u[a][(uint32_t)np_];
             }
         }
         int fi[3], ci[3];
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
                 const int qq = (int)floor(X);
                 carry[a] = qq >> 8;
                 mnew[a] = qq & 255;
-                A.out.m[a][p] = (uint8_t)mnew[a];
+                A.out.m[a][(uint32_t)p] = (uint8_t)mnew[a];
                 cmax = max(cmax, abs(carry[a]));
             }
         } else {
@@ -398,8 +400,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
             const int qq = (int)floor(X);
             carry[a] = qq >> 8;                  // floor division by 256
             mnew[a] = qq & 255;
-            A.out.m[a][p] = (uint8_t)mnew[a];
-            A.out.u[a][p] = (int8_t)un[a];
+            A.out.m[a][(uint32_t)p] = (uint8_t)mnew[a];
+            A.out.u[a][(uint32_t)p] = (int8_t)un[a];
             cmax = max(cmax, abs(carry[a]));
         }
         }
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
         const bool near = abs(carry[0]) <= 1 && abs(carry[1]) <= 1 && abs(carry[2]) <= 1;
         if (near) {
             const int code = (carry[0] + 1) + 3 * (carry[1] + 1) + 9 * (carry[2] + 1);
-            A.dir[p] = (uint8_t)code;
+            A.dir[(uint32_t)p] = (uint8_t)code;
             const int hx = lcell[0] + carry[0] + 1, hy = lcell[1] + carry[1] + 1, hz = lcell[2] + carry[2] + 1;
             atomicAdd(&s_hist[(hz * HY + hy) * HX + hx], 1);
             if (code != 13) {
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
                 } else {
                     locate(e, p, lx, ly, lz);
                 }
-                const int code = A.dir[p];
+                const int code = A.dir[(uint32_t)p];
                 if (code == 13 || code >= 27) continue;
                 const int nx = lx + code % 3 - 1, ny = ly + (code / 3) % 3 - 1, nz = lz + code / 9 - 1;
                 const int cls = move_class(nx, ny, nz, BXc, BYc, BZc);
@@ -476,11 +478,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs A) {
                 uint4 rec;
                 rec.x = (uint32_t)p;
                 rec.y = (uint32_t)dl | ((uint32_t)cls << 8);
-                rec.z = (uint32_t)A.out.m[0][p] | ((uint32_t)A.out.m[1][p] << 8) | ((uint32_t)A.out.m[2][p] << 16);
+                rec.z = (uint32_t)A.out.m[0][(uint32_t)p] | ((uint32_t)A.out.m[1][(uint32_t)p] << 8) | ((uint32_t)A.out.m[2][(uint32_t)p] << 16);
                 rec.w = 0;
                 if constexpr (!VC)
-                    rec.w = (uint32_t)(uint8_t)A.out.u[0][p] | ((uint32_t)(uint8_t)A.out.u[1][p] << 8) |
-                            ((uint32_t)(uint8_t)A.out.u[2][p] << 16);
+                    rec.w = (uint32_t)(uint8_t)A.out.u[0][(uint32_t)p] | ((uint32_t)(uint8_t)A.out.u[1][(uint32_t)p] << 8) |
+                            ((uint32_t)(uint8_t)A.out.u[2][(uint32_t)p] << 16);
                 A.ment[rslot + s_ccount[cls] + atomicAdd(&s_crun[cls], 1)] = rec;
             }
         }
@@ -544,12 +546,22 @@ bool gather_supported(const Geom& g) {
     return g.T % kBX == 0 && g.T % kBY == 0 && g.r >= kMinR && kBZ % g.r == 0;
 }
 
+template <int H, bool PER, bool VC>
+void launch_gather_step(const GatherArgs& a, const dim3& grid, hipStream_t s) {
+    if (a.g.r == 4)
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER, VC, 4>), grid, dim3(kGatherThreads), 0, s, a);
+    else if (a.g.r == 8)
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER, VC, 8>), grid, dim3(kGatherThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER, VC>), grid, dim3(kGatherThreads), 0, s, a);
+}
+
 template <int H, bool PER>
 void launch_gather_halo(const GatherArgs& a, const dim3& grid, hipStream_t s) {
     if (a.mode == GATHER_STEP && a.g.vcodec)
-        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER, true>), grid, dim3(kGatherThreads), 0, s, a);
+        launch_gather_step<H, PER, true>(a, grid, s);
     else if (a.mode == GATHER_STEP)
-        hipLaunchKernelGGL((k_gather<GATHER_STEP, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
+        launch_gather_step<H, PER, false>(a, grid, s);
     else if (a.mode == GATHER_FORCE)
         hipLaunchKernelGGL((k_gather<GATHER_FORCE, H, PER>), grid, dim3(kGatherThreads), 0, s, a);
     else
