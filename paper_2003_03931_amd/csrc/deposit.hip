@@ -156,12 +156,13 @@ __global__ __launch_bounds__(kDepThreads) void k_deposit(Geom g, const int32_t* 
                 for (int oy = 0; oy < 2; ++oy) {
                     const int iy = i0[1] + oy;
                     if (iy < 0 || iy >= bw[1]) continue;
-                    const unsigned wyz = (oy ? w1[1] : (unsigned)D - w1[1]) * wz;
+                    // weights are at most D <= 512 per axis: 24-bit products
+                    const unsigned wyz = (unsigned)__umul24(oy ? w1[1] : (unsigned)D - w1[1], wz);
 #pragma unroll
                     for (int ox = 0; ox < 2; ++ox) {
                         const int ix = i0[0] + ox;
                         if (ix < 0 || ix >= bw[0]) continue;
-                        const ACC w = (ACC)(ox ? w1[0] : (unsigned)D - w1[0]) * (ACC)wyz;
+                        const ACC w = (ACC)(unsigned)__umul24(ox ? w1[0] : (unsigned)D - w1[0], wyz);
                         if (w) atomicAdd(&acc[(iz * BW + iy) * BW + ix], w);
                     }
                 }
