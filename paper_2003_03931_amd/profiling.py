@@ -28,7 +28,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 # step stage (cube_profile_read name) -> kernel symbol fragment
 STAGE_KERNEL = {
-    "coarse_deposit": "k_deposit<8, 0",
+    "coarse_deposit": "k_coarse_deposit",
     "coarse_fft_green": "k_fft<",
     "fine_deposit": "k_deposit<16, 1",
     "fine_r2c_xy": "k_r2c_plane",
