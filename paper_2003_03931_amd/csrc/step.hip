@@ -150,35 +150,62 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     }
 }
 
-// one block per z-plane: shell sums of |dk|^2 / n^3, mode counts and |k| sums
+// floor(sqrt(v)) of a non-negative integer, exactly
+__device__ __forceinline__ long isqrt_floor(long v) {
+    long q = (long)sqrt((double)v);
+    while (q * q > v) --q;
+    while ((q + 1) * (q + 1) <= v) ++q;
+    return q;
+}
+
+// One block per z-plane: shell sums of |dk|^2 / n^3, mode counts and |k|
+// sums.  A mode with integer |m|^2 = r2 falls in shell j = floor(sqrt(r2) +
+// 1/2) exactly when j^2 - j + 1 <= r2 <= j^2 + j, so each thread owns whole
+// shells and walks a shell's modes of the plane in a fixed order (rows m_y
+// ascending, then |m_x| ascending, + before -): the sums do not depend on
+// scheduling, and the spectrum is reproducible bit for bit.
 __global__ __launch_bounds__(256) void k_power_bins(const float2* __restrict__ dk, int n, int nbins,
                                                     double* __restrict__ partial) {
-    extern __shared__ double sh[];
-    double* ps = sh;
-    double* ks = sh + nbins;
-    double* cs = sh + 2 * nbins;
-    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) sh[i] = 0.0;
-    __syncthreads();
     const int z = blockIdx.x;
-    const int mz = z <= n / 2 - 1 ? z : z - n;
+    const long mz = z <= n / 2 - 1 ? z : z - n;
+    const int half = n / 2;
     const double inv_n3 = 1.0 / ((double)n * n * n);
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int x = e % n, y = e / n;
-        const int mx = x <= n / 2 - 1 ? x : x - n;
-        const int my = y <= n / 2 - 1 ? y : y - n;
-        const long r2 = (long)mx * mx + (long)my * my + (long)mz * mz;
-        const double r = sqrt((double)r2);
-        const int j = (int)floor(r + 0.5);
-        if (j >= 1 && j <= nbins) {
-            const float2 v = dk[((int64_t)z * n + y) * n + x];
-            const double pw = ((double)v.x * v.x + (double)v.y * v.y) * inv_n3;
-            atomicAdd(&ps[j - 1], pw);
-            atomicAdd(&ks[j - 1], r * (2.0 * M_PI / n));
-            atomicAdd(&cs[j - 1], 1.0);
+    const double kf = 2.0 * M_PI / n;
+    for (int j = (int)threadIdx.x + 1; j <= nbins; j += blockDim.x) {
+        double ps = 0.0, ks = 0.0, cs = 0.0;
+        const long A0 = (long)j * j - j + 1 - mz * mz, B0 = (long)j * j + j - mz * mz;
+        if (B0 >= 0) {
+            const long ymax = isqrt_floor(B0);
+            for (long my = -ymax; my <= ymax; ++my) {
+                if (my < -half || my > half - 1) continue;
+                const long A = A0 - my * my, B = B0 - my * my;
+                if (B < 0) continue;
+                long lo = 0;
+                if (A > 0) {
+                    lo = isqrt_floor(A - 1) + 1;                        // ceil(sqrt(A))
+                }
+                const long hi = isqrt_floor(B);
+                const int y = (int)(my >= 0 ? my : my + n);
+                for (long mx = lo; mx <= hi; ++mx) {
+                    const double r = sqrt((double)(mx * mx + my * my + mz * mz));
+#pragma unroll
+                    for (int sgn = 0; sgn < 2; ++sgn) {
+                        if (sgn == 1 && mx == 0) break;
+                        const long sx = sgn ? -mx : mx;
+                        if (sx < -half || sx > half - 1) continue;
+                        const int x = (int)(sx >= 0 ? sx : sx + n);
+                        const float2 v = dk[((int64_t)z * n + y) * n + x];
+                        ps += ((double)v.x * v.x + (double)v.y * v.y) * inv_n3;
+                        ks += r * kf;
+                        cs += 1.0;
+                    }
+                }
+            }
         }
+        partial[(int64_t)z * 3 * nbins + (j - 1)] = ps;
+        partial[(int64_t)z * 3 * nbins + nbins + (j - 1)] = ks;
+        partial[(int64_t)z * 3 * nbins + 2 * nbins + (j - 1)] = cs;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) partial[(int64_t)z * 3 * nbins + i] = sh[i];
 }
 
 }  // namespace
@@ -233,7 +260,7 @@ void launch_reduce_partials(const double* partial, int nblocks, int width, doubl
 }
 
 void launch_power_bins(const float2* dk, int n, int nbins, double* partial, int /*nparts*/, hipStream_t s) {
-    hipLaunchKernelGGL(k_power_bins, dim3(n), dim3(256), 3 * nbins * sizeof(double), s, dk, n, nbins, partial);
+    hipLaunchKernelGGL(k_power_bins, dim3(n), dim3(256), 0, s, dk, n, nbins, partial);
 }
 
 }  // namespace cube

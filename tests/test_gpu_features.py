@@ -53,7 +53,10 @@ def test_mixed_precision_forces(name, prec):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_mixed_precision_steps(prec):
-    from oracle import pm, step
+    """Three steps with 16-bit spectra against the oracle: the one-quantum
+    fraction, and the power spectrum of the result (every shell within 0.1%,
+    the bound the FP32 spectrum meets)."""
+    from oracle import diag, pm, step
     from tests.test_gpu_parity import _compare_by_id
     name = "t4"
     box, ref = oracle_state(name)
@@ -65,10 +68,16 @@ def test_mixed_precision_steps(prec):
         load_state(g, ref)
         g.step(3)
         st = g.get_state()
+        k_g, p_g, n_g = g.power_spectrum()
     d = _compare_by_id(box, st, o, codes=0.0)    # 16-bit spectra: codes near a half-integer may flip
-    print(f"{prec}: within 1 quantum {np.mean(d <= 1):.5f}, identical {np.mean(d == 0):.5f}")
+    k_o, p_o, n_o = diag.power_spectrum(o)
+    pk_dev = float(np.max(np.abs(p_g / p_o - 1.0)))
+    print(f"{prec}: within 1 quantum {np.mean(d <= 1):.5f}, identical {np.mean(d == 0):.5f}, "
+          f"P(k) max |ratio - 1| {pk_dev:.2e}")
     assert st["counts"].sum() == ref.n
     assert np.mean(d <= 1) >= 0.99
+    assert np.array_equal(n_g, n_o)
+    assert pk_dev <= 1e-3
 
 
 def test_fp16_falls_back_to_fp32_for_dense_cells():

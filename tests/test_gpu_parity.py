@@ -262,7 +262,8 @@ def test_dense_cell_paths(n_dense):
 # ---------------------------------------------------------- diagnostics
 @pytest.mark.parametrize("name,nsteps", [("t4", 0), ("c2s", 2)])
 def test_power_spectrum_matches_oracle(name, nsteps):
-    """P(k) of the same state: every shell with k < k_Ny/2 within 0.1%."""
+    """P(k) of the same state: every shell with k < k_Ny/2 within 0.1%, and
+    bit-identical on a second call."""
     from oracle import diag, pm, step
     box, ref = oracle_state(name)
     o = ref
@@ -272,6 +273,9 @@ def test_power_spectrum_matches_oracle(name, nsteps):
     with gpu_box(name) as g:
         load_state(g, o)
         k_g, p_g, n_g = g.power_spectrum()
+        k_2, p_2, n_2 = g.power_spectrum()
+    # shells are summed in a fixed order: a second call gives the same bits
+    assert np.array_equal(k_2, k_g) and np.array_equal(p_2, p_g) and np.array_equal(n_2, n_g)
     assert np.array_equal(n_g, n_o)
     assert np.allclose(k_g, k_o, rtol=1e-12)
     assert np.max(np.abs(p_g / p_o - 1.0)) <= 1e-3
