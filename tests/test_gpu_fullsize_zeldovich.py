@@ -1,0 +1,148 @@
+"""Parity on the benchmark's own 1024^3 state: the seeded Zel'dovich initial
+conditions the benchmark steps (P(k) ~ k^-1.5, rms displacement 2 spacings),
+compressed by the library in the launch configuration the benchmark times
+(64 tiles per batch), against the oracle on what it can compute piece by
+piece at that size:
+
+* the whole compression's cell counts and the velocity scale (Sec. III-A,
+  R6-R7): the oracle quantises all 2^30 particles in chunks;
+* the bytes, velocity codes and in-cell order of every particle in the
+  windows of three sampled tiles (a corner tile whose window wraps, a middle
+  tile, a seeded one): the oracle compresses exactly those particles, which
+  the cell-local codec allows;
+* the fine density of those tiles (bit-exact) and their fine potentials
+  (relative L2 < 2e-6), from the oracle's particles of each window.
+
+The initial conditions come from the shared seeded generator (on the GPU for
+speed); both sides read the same float32 arrays.
+"""
+
+import types
+
+import numpy as np
+import pytest
+
+from cube_inputs import config, zeldovich_ics_device
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BATCH = 64
+CHUNK = 1 << 26
+
+
+@pytest.fixture(scope="module")
+def zel():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from oracle import codec
+    from paper_2003_03931_amd import CubeBox
+    spec = config("c3")
+    box = oracle.Box.from_spec(spec).validate()
+    n = spec.n_particles
+    pos_d, vel_d = zeldovich_ics_device(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
+    print("initial conditions done", flush=True)
+
+    g = CubeBox(spec, tiles_per_batch=BATCH, with_ids=True)
+    g.compress(pos_d, vel_d)
+    pos = pos_d.cpu().numpy()
+    vel = vel_d.cpu().numpy()
+    del pos_d, vel_d
+    torch.cuda.empty_cache()
+    nt, Tc, Nc = box.tiles_per_dim, box.Tc, box.n_coarse
+    rng = np.random.default_rng(4101)
+    mid = nt // 2 + nt * (nt // 2 + nt * (nt // 2))
+    tiles = [0, mid, int(rng.integers(1, box.n_tiles))]
+    dens = {t: g.debug_mesh(2, t).cpu().numpy() for t in tiles}
+    pots = {t: g.debug_mesh(3, t).cpu().numpy() for t in tiles}
+    st = g.get_state()
+    g.close()
+    print(f"gpu compress done; tiles {tiles}", flush=True)
+
+    # ---- oracle, in chunks of particles: every particle's cell, the maximum
+    # |v|, and the particles of the sampled tiles' windows in index order
+    span, hc = box.F // box.coarse_ratio, box.halo_c
+    origins = [np.array([tx * Tc - hc, ty * Tc - hc, tz * Tc - hc]) % Nc
+               for tx, ty, tz in (box.tile_coords(t) for t in tiles)]
+    counts = np.zeros(box.n_cells, np.int64)
+    vmax = 0.0
+    keep_idx = []
+    for c0 in range(0, n, CHUNK):
+        Q = codec.encode_positions(box, pos[c0:c0 + CHUNK])
+        cell = Q // 256
+        counts += np.bincount(box.canon(cell[:, 0], cell[:, 1], cell[:, 2]), minlength=box.n_cells)
+        vmax = max(vmax, float(np.max(np.abs(vel[c0:c0 + CHUNK].astype(np.float64)))))
+        sel = np.zeros(Q.shape[0], bool)
+        for o in origins:
+            sel |= np.all((cell - o[None, :]) % Nc < span, axis=1)
+        keep_idx.append(c0 + np.nonzero(sel)[0])
+        if (c0 // CHUNK) % 4 == 3:
+            print(f"oracle chunks {c0 // CHUNK + 1}/{(n + CHUNK - 1) // CHUNK}", flush=True)
+    keep = np.concatenate(keep_idx)
+    s0 = codec.pow2ceil(box.v_headroom * vmax / 127.0)
+    u_all_max = 0
+    for c0 in range(0, n, CHUNK):
+        u, _ = codec.encode_velocities(vel[c0:c0 + CHUNK], s0)
+        u_all_max = max(u_all_max, int(np.max(np.abs(u.astype(np.int64)))))
+    u_keep, _ = codec.encode_velocities(vel[keep], s0)
+    part = codec.build_state(box, codec.encode_positions(box, pos[keep]), u_keep, s0, u_all_max,
+                             keep.astype(np.uint32))
+    del pos, vel
+    print(f"oracle window particles: {keep.size}", flush=True)
+    return types.SimpleNamespace(box=box, n=n, tiles=tiles, origins=origins, counts=counts, s0=s0, M=u_all_max,
+                                 part=part, st=st, dens=dens, pots=pots)
+
+
+def _window_cells(box, origin):
+    span, Nc = box.F // box.coarse_ratio, box.n_coarse
+    r = np.arange(span)
+    cz, cy, cx = np.meshgrid((origin[2] + r) % Nc, (origin[1] + r) % Nc, (origin[0] + r) % Nc, indexing="ij")
+    return np.sort(box.canon(cx.ravel(), cy.ravel(), cz.ravel()))
+
+
+def test_zeldovich_counts_and_scale(zel):
+    """Cell counts of all 2^30 particles, the velocity scale and max |u|."""
+    assert zel.st["counts"].sum() == zel.n
+    assert np.array_equal(zel.st["counts"].astype(np.int64), zel.counts)
+    assert zel.st["s"] == zel.s0
+    assert zel.st["M"] == zel.M
+
+
+def test_zeldovich_window_bytes(zel):
+    """Every particle of the sampled windows: cell, in-cell bytes, velocity
+    codes and order within the cell (ids ascending, the stable order)."""
+    box, st, part = zel.box, zel.st, zel.part
+    off_g = np.zeros(box.n_cells + 1, np.int64)
+    np.cumsum(st["counts"], out=off_g[1:])
+    off_o = part.offsets()
+    from oracle.pm import _expand_ranges
+    for t, o in zip(zel.tiles, zel.origins):
+        cells = _window_cells(box, o)
+        assert np.array_equal(st["counts"][cells].astype(np.int64), part.counts[cells]), f"tile {t}"
+        ig = _expand_ranges(off_g[cells], st["counts"][cells].astype(np.int64))
+        io = _expand_ranges(off_o[cells], part.counts[cells])
+        assert np.array_equal(st["ids"][ig], part.ids[io]), f"tile {t}: order"
+        assert np.array_equal(st["m"][:, ig], part.m[:, io]), f"tile {t}: position bytes"
+        assert np.array_equal(st["u"][:, ig], part.u[:, io]), f"tile {t}: velocity codes"
+
+
+def test_zeldovich_fine_meshes(zel):
+    """Fine density of the sampled tiles bit for bit (float32 of the oracle's
+    exact FP64 deposit) and fine potentials to 2e-6."""
+    from oracle import cic, green, pm
+    box, part = zel.box, zel.part
+    Q = part.quanta()
+    off = part.offsets()
+    Gf = green.fine_green(box)
+    for t in zel.tiles:
+        idx, origin = pm.tile_sources(box, part.counts, off, t)
+        X = pm.tile_box_coords(box, Q[idx], origin)
+        rho = cic.deposit(X, box.F, periodic=False) / box.h ** 3 - 1.0
+        assert np.array_equal(zel.dens[t], rho.transpose(2, 1, 0).astype(np.float32)), f"tile {t}: density"
+        phi, _ = pm.fine_potential_tile(box, Q, part.counts, off, t, Gf)
+        err = rel_l2(zel.pots[t], phi.transpose(2, 1, 0))
+        print(f"tile {t}: fine potential relative L2 {err:.3e}")
+        assert err < 2e-6, f"tile {t}"
