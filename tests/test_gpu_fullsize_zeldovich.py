@@ -11,7 +11,12 @@ piece at that size:
   tile, a seeded one): the oracle compresses exactly those particles, which
   the cell-local codec allows;
 * the fine density of those tiles (bit-exact) and their fine potentials
-  (relative L2 < 2e-6), from the oracle's particles of each window.
+  (relative L2 < 2e-6), from the oracle's particles of each window;
+* one step: the oracle's coarse density of all 2^30 particles (deposited in
+  chunks; its sums of multiples of 2^-27 are exact in FP64, so the chunking
+  changes nothing), the fine force of each sampled tile from its window, the
+  kick and the drift; the particles that land in the interior cells of the
+  sampled tiles arrive with the oracle's bytes, in the oracle's stable order.
 
 The initial conditions come from the shared seeded generator (on the GPU for
 speed); both sides read the same float32 arrays.
@@ -30,7 +35,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 BATCH = 64
-CHUNK = 1 << 26
+CHUNK = 1 << 27
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +43,7 @@ def zel():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
-    from oracle import codec
+    from oracle import cic, codec
     from paper_2003_03931_amd import CubeBox
     spec = config("c3")
     box = oracle.Box.from_spec(spec).validate()
@@ -59,8 +64,10 @@ def zel():
     dens = {t: g.debug_mesh(2, t).cpu().numpy() for t in tiles}
     pots = {t: g.debug_mesh(3, t).cpu().numpy() for t in tiles}
     st = g.get_state()
+    g.step(1)
+    st1 = g.get_state()
     g.close()
-    print(f"gpu compress done; tiles {tiles}", flush=True)
+    print(f"gpu compress and step done; tiles {tiles}", flush=True)
 
     # ---- oracle, in chunks of particles: every particle's cell, the maximum
     # |v|, and the particles of the sampled tiles' windows in index order
@@ -68,10 +75,12 @@ def zel():
     origins = [np.array([tx * Tc - hc, ty * Tc - hc, tz * Tc - hc]) % Nc
                for tx, ty, tz in (box.tile_coords(t) for t in tiles)]
     counts = np.zeros(box.n_cells, np.int64)
+    mass_c = np.zeros((Nc,) * 3)
     vmax = 0.0
     keep_idx = []
     for c0 in range(0, n, CHUNK):
         Q = codec.encode_positions(box, pos[c0:c0 + CHUNK])
+        mass_c += cic.deposit((Q + 0.5) / 256.0, Nc, periodic=True)
         cell = Q // 256
         counts += np.bincount(box.canon(cell[:, 0], cell[:, 1], cell[:, 2]), minlength=box.n_cells)
         vmax = max(vmax, float(np.max(np.abs(vel[c0:c0 + CHUNK].astype(np.float64)))))
@@ -79,8 +88,7 @@ def zel():
         for o in origins:
             sel |= np.all((cell - o[None, :]) % Nc < span, axis=1)
         keep_idx.append(c0 + np.nonzero(sel)[0])
-        if (c0 // CHUNK) % 4 == 3:
-            print(f"oracle chunks {c0 // CHUNK + 1}/{(n + CHUNK - 1) // CHUNK}", flush=True)
+        print(f"oracle chunk {c0 // CHUNK + 1}/{(n + CHUNK - 1) // CHUNK}", flush=True)
     keep = np.concatenate(keep_idx)
     s0 = codec.pow2ceil(box.v_headroom * vmax / 127.0)
     u_all_max = 0
@@ -92,8 +100,10 @@ def zel():
                              keep.astype(np.uint32))
     del pos, vel
     print(f"oracle window particles: {keep.size}", flush=True)
+    rho_c = mass_c / box.H ** 3 - 1.0
+    del mass_c
     return types.SimpleNamespace(box=box, n=n, tiles=tiles, origins=origins, counts=counts, s0=s0, M=u_all_max,
-                                 part=part, st=st, dens=dens, pots=pots)
+                                 part=part, st=st, st1=st1, dens=dens, pots=pots, rho_c=rho_c)
 
 
 def _window_cells(box, origin):
@@ -146,3 +156,36 @@ def test_zeldovich_fine_meshes(zel):
         err = rel_l2(zel.pots[t], phi.transpose(2, 1, 0))
         print(f"tile {t}: fine potential relative L2 {err:.3e}")
         assert err < 2e-6, f"tile {t}"
+
+
+def test_zeldovich_step(zel):
+    """One step of the benchmark's state: the velocity scale exact, mass
+    conserved, and on every sampled tile the particles that land in its
+    interior cells arrive with the oracle's bytes (>= 99.9% exactly, the
+    rest within one quantum: FP32 against FP64 forces), in stable order."""
+    import types as _t
+    from oracle import codec, green, pm, step
+    from tests.test_gpu_fullsize import _interior, _matched
+    box, part, st1 = zel.box, zel.part, zel.st1
+    assert st1["counts"].sum() == zel.n
+    assert st1["s"] == codec.next_velocity_scale(box, zel.s0, zel.M)
+    Q = part.quanta()
+    off = part.offsets()
+    Gf, Gc = green.fine_green(box), green.coarse_green(box)
+    for t in zel.tiles:
+        tgt, af, _ = pm._tile_force(box, Q, part.counts, off, t, Gf)
+        a = af + pm.coarse_force_at(box, zel.rho_c, Gc, Q[tgt])
+        old = _t.SimpleNamespace(u=part.u[:, tgt], s=zel.s0, M=zel.M, m=part.m[:, tgt],
+                                 quanta=lambda: Q[tgt], step=0)
+        u_new, s_new, _, _ = step.kick(box, old, a)
+        Q_new, carry = step.drift(box, old, u_new, s_new)
+        inner, dest, order, cells = _interior(box, t, Q_new, tgt)
+        exp_m = (Q_new[inner] % 256)[order].T
+        exp_u = u_new[inner][order].T
+        gi, oi, _ = _matched(st1, cells, dest)
+        dm = np.abs(st1["m"][:, gi].astype(np.int64) - exp_m[:, oi]).max(axis=0)
+        du = np.abs(st1["u"][:, gi].astype(np.int64) - exp_u[:, oi]).max(axis=0)
+        exact = np.mean((dm == 0) & (du == 0))
+        print(f"tile {t}: {gi.size} particles compared, exact {exact:.6f}, max carry {np.abs(carry).max()}")
+        assert exact >= 0.999
+        assert dm.max() <= 1 and du.max() <= 1
