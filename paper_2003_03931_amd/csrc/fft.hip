@@ -314,7 +314,7 @@ CUBE_FFT_PLAN(80, 5, 4, 4)
 CUBE_FFT_PLAN(96, 3, 4, 8)
 CUBE_FFT_PLAN(112, 7, 4, 4)
 CUBE_FFT_PLAN(128, 2, 8, 8)
-CUBE_FFT_PLAN(160, 16, 10)
+CUBE_FFT_PLAN(160, 10, 16)
 CUBE_FFT_PLAN(192, 3, 8, 8)
 CUBE_FFT_PLAN(224, 7, 4, 8)
 CUBE_FFT_PLAN(256, 4, 8, 8)

@@ -38,8 +38,19 @@ BATCH = 64
 CHUNK = 1 << 27
 
 
+def _say(request, msg):
+    """Progress to the terminal even when output is captured: the set-up
+    runs for minutes, and a silent run looks hung."""
+    cm = request.config.pluginmanager.getplugin("capturemanager")
+    if cm is None:
+        print(msg, flush=True)
+        return
+    with cm.global_and_fixture_disabled():
+        print(msg, flush=True)
+
+
 @pytest.fixture(scope="module")
-def zel():
+def zel(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
@@ -49,7 +60,7 @@ def zel():
     box = oracle.Box.from_spec(spec).validate()
     n = spec.n_particles
     pos_d, vel_d = zeldovich_ics_device(spec.n_side, spec.spectral_index, spec.rms_disp, spec.seed, spec.dt)
-    print("initial conditions done", flush=True)
+    _say(request, "initial conditions done")
 
     g = CubeBox(spec, tiles_per_batch=BATCH, with_ids=True)
     g.compress(pos_d, vel_d)
@@ -67,7 +78,7 @@ def zel():
     g.step(1)
     st1 = g.get_state()
     g.close()
-    print(f"gpu compress and step done; tiles {tiles}", flush=True)
+    _say(request, f"gpu compress and step done; tiles {tiles}")
 
     # ---- oracle, in chunks of particles: every particle's cell, the maximum
     # |v|, and the particles of the sampled tiles' windows in index order
@@ -88,9 +99,10 @@ def zel():
         for o in origins:
             sel |= np.all((cell - o[None, :]) % Nc < span, axis=1)
         keep_idx.append(c0 + np.nonzero(sel)[0])
-        print(f"oracle chunk {c0 // CHUNK + 1}/{(n + CHUNK - 1) // CHUNK}", flush=True)
+        _say(request, f"oracle chunk {c0 // CHUNK + 1}/{(n + CHUNK - 1) // CHUNK}")
     keep = np.concatenate(keep_idx)
     s0 = codec.pow2ceil(box.v_headroom * vmax / 127.0)
+    _say(request, "oracle: velocity codes")
     u_all_max = 0
     for c0 in range(0, n, CHUNK):
         u, _ = codec.encode_velocities(vel[c0:c0 + CHUNK], s0)
@@ -99,7 +111,7 @@ def zel():
     part = codec.build_state(box, codec.encode_positions(box, pos[keep]), u_keep, s0, u_all_max,
                              keep.astype(np.uint32))
     del pos, vel
-    print(f"oracle window particles: {keep.size}", flush=True)
+    _say(request, f"oracle window particles: {keep.size}")
     rho_c = mass_c / box.H ** 3 - 1.0
     del mass_c
     return types.SimpleNamespace(box=box, n=n, tiles=tiles, origins=origins, counts=counts, s0=s0, M=u_all_max,
@@ -158,7 +170,7 @@ def test_zeldovich_fine_meshes(zel):
         assert err < 2e-6, f"tile {t}"
 
 
-def test_zeldovich_step(zel):
+def test_zeldovich_step(zel, request):
     """One step of the benchmark's state: the velocity scale exact, mass
     conserved, and on every sampled tile the particles that land in its
     interior cells arrive with the oracle's bytes (>= 99.9% exactly, the
@@ -172,9 +184,14 @@ def test_zeldovich_step(zel):
     Q = part.quanta()
     off = part.offsets()
     Gf, Gc = green.fine_green(box), green.coarse_green(box)
-    for t in zel.tiles:
-        tgt, af, _ = pm._tile_force(box, Q, part.counts, off, t, Gf)
-        a = af + pm.coarse_force_at(box, zel.rho_c, Gc, Q[tgt])
+    fine = [pm._tile_force(box, Q, part.counts, off, t, Gf)[:2] for t in zel.tiles]
+    _say(request, "oracle: fine forces of the sampled tiles done")
+    coarse = pm.coarse_force_at(box, zel.rho_c, Gc, Q[np.concatenate([tgt for tgt, _ in fine])])
+    _say(request, "oracle: coarse forces done")
+    k = 0
+    for t, (tgt, af) in zip(zel.tiles, fine):
+        a = af + coarse[k:k + tgt.size]
+        k += tgt.size
         old = _t.SimpleNamespace(u=part.u[:, tgt], s=zel.s0, M=zel.M, m=part.m[:, tgt],
                                  quanta=lambda: Q[tgt], step=0)
         u_new, s_new, _, _ = step.kick(box, old, a)
