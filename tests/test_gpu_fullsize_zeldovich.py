@@ -30,7 +30,9 @@ import pytest
 from cube_inputs import config, zeldovich_ics_device
 from tests.gpu_common import rel_l2
 
-pytestmark = pytest.mark.gpu
+# the set-up (initial conditions of 2^30 particles, the oracle's chunked pass
+# over all of them) takes minutes: it reports progress as it goes
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 torch = pytest.importorskip("torch")
 
