@@ -665,7 +665,11 @@ __device__ __forceinline__ void touch_reg(uint32_t v) { asm volatile("" ::"v"(v)
 template <int N>
 struct PlaneSplit {
     static constexpr int NW = kPlaneThreads / kWave;
-    static constexpr int HALF = N / 2, NH = N / 2 + 1, RS = N + 2;
+    static constexpr int HALF = N / 2, NH = N / 2 + 1;
+    // real row y of the half spectrum sits at y RSH (two per complex row of
+    // stride RS = 2 RSH); RSH = NH + 4 makes 2 RS = 20 (mod 64) dwords, so the
+    // rows a wave's lanes touch together start in different LDS banks
+    static constexpr int RSH = NH % 16 == 1 ? NH + 4 : NH, RS = 2 * RSH;
     static constexpr int RPW = HALF / NW;                  // complex rows per wave
     static constexpr int CPW = (NH + NW - 1) / NW;         // columns per wave (the last waves fewer)
     static constexpr bool ok = HALF % NW == 0;
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane_w(const float* __re
                                                                float sc_out, int32_t* __restrict__ flag) {
     using S = SpecStore<FMT>;
     using PS = PlaneSplit<N>;
-    constexpr int NH = PS::NH, RS = PS::RS, RPW = PS::RPW, CPW = PS::CPW;
+    constexpr int NH = PS::NH, RS = PS::RS, RSH = PS::RSH, RPW = PS::RPW, CPW = PS::CPW;
     constexpr int EPW = RPW * N;                             // complex elements of a wave's rows
     constexpr int PER = (EPW + kWave - 1) / kWave;
     constexpr int KIT = (NH + kWave - 1) / kWave;
@@ -747,14 +751,14 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane_w(const float* __re
                 const int k = lane + t * kWave;
                 if (k < NH) {
                     row[k] = va[t];
-                    row[NH + k] = vb[t];
+                    row[RSH + k] = vb[t];
                 }
             }
             wave_sync();
         }
         lds_barrier();                                     // every row transformed
         if (ncol > 0)
-            Plan<N>::template run<Lay<CPW, NH, 1, true, kWave, true>, false>(lds + c0, tw, tid, ncol);
+            Plan<N>::template run<Lay<CPW, RSH, 1, true, kWave, true>, false>(lds + c0, tw, tid, ncol);
         lds_barrier();                                     // every column transformed
         // Loads and stores share one in-order counter: wait for the next
         // plane's loads (issued long before, so this costs nothing) ahead of
@@ -769,7 +773,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_r2c_plane_w(const float* __re
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
             const int e = t + u * kPlaneThreads;
-            if ((u + 1) * kPlaneThreads <= N * NH || e < N * NH) dst[e] = S::put(lds[e], sc_out, bad);
+            if ((u + 1) * kPlaneThreads <= N * NH || e < N * NH)
+                dst[e] = S::put(lds[(e / NH) * RSH + e % NH], sc_out, bad);
         }
     }
     if (FMT == SPEC_F16) raise_flag(bad, flag);
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename Sp
                                                                float sc_in, int lo, int hi) {
     using S = SpecStore<FMT>;
     using PS = PlaneSplit<N>;
-    constexpr int NH = PS::NH, RS = PS::RS, RPW = PS::RPW, CPW = PS::CPW, HALF = PS::HALF;
+    constexpr int NH = PS::NH, RS = PS::RS, RSH = PS::RSH, RPW = PS::RPW, CPW = PS::CPW, HALF = PS::HALF;
     constexpr int TOT = N * NH;
     constexpr int PER = (TOT + kPlaneThreads - 1) / kPlaneThreads;
     constexpr int KIT = (N + kWave - 1) / kWave;
@@ -818,14 +823,14 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename Sp
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = threadIdx.x + u * kPlaneThreads;
-            if (TOT % kPlaneThreads == 0 || e < TOT) lds[e] = S::get(pv[u], sc_in);
+            if (TOT % kPlaneThreads == 0 || e < TOT) lds[(e / NH) * RSH + e % NH] = S::get(pv[u], sc_in);
         }
         lds_barrier();                                     // the plane's spectrum is in LDS
         if (plane + (int)gridDim.x < nplanes) prefetch(plane + gridDim.x);
         int tid = lane;
         asm volatile("" : "+v"(tid));
         if (ncol > 0)
-            Plan<N>::template run<Lay<CPW, NH, 1, true, kWave, true>, true>(lds + c0, tw, tid, ncol);
+            Plan<N>::template run<Lay<CPW, RSH, 1, true, kWave, true>, true>(lds + c0, tw, tid, ncol);
         lds_barrier();                                     // every column transformed
         // Loads and stores share one in-order counter: wait for the next
         // plane's loads (issued long before) ahead of this plane's stores, so
@@ -844,7 +849,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename Sp
                     if (k < N) {
                         const int kk = k <= HALF ? k : N - k;
                         const float sg = k <= HALF ? 1.0f : -1.0f;
-                        const float2 a = row[kk], b = row[NH + kk];
+                        const float2 a = row[kk], b = row[RSH + kk];
                         vz[t] = make_float2(a.x - sg * b.y, sg * a.y + b.x);
                     }
                 }
