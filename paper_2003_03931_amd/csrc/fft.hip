@@ -325,18 +325,12 @@ CUBE_FFT_PLAN(512, 8, 8, 8)
 CUBE_FFT_PLAN(1024, 4, 4, 8, 8)
 #undef CUBE_FFT_PLAN
 
-// Plan of the z-pencil pass: 16 pencils per 256-thread workgroup, where short
-// radices keep every thread busy (a radix-16 pass would use 160 of 256).
+// Plan of the z-pencil pass (16 pencils per 256-thread workgroup): the same
+// radices.  At N = 160 the 10 x 16 plan takes one radix-10 and 5/8 of a
+// radix-16 butterfly per thread and crosses LDS once less than 5, 4, 8 with
+// every thread busy (31.7 against 33.7 ms per 1024^3 step).
 template <int N>
 struct PlanZ : Plan<N> {};
-template <>
-struct PlanZ<160> {
-    template <class L, bool INV>
-    __device__ __forceinline__ static void run(float2* lds, const float2* __restrict__ tw, int tid = threadIdx.x,
-                                               int npen = L::P) {
-        run_passes<160, L, INV, 1, 5, 4, 8>(lds, tw, tid, npen);
-    }
-};
 
 template <int N>
 constexpr int pencils() { return N <= 256 ? 16 : 8; }
@@ -882,24 +876,17 @@ __global__ __launch_bounds__(kPlaneThreads) void k_c2r_plane_w(const typename Sp
     }
 }
 
-// Threads of a z-pencil workgroup (16 pencils): 320 at N = 160, where the
-// 5, 4, 8 passes then take 1.6, 2 and 1 butterflies per thread (256 threads
-// would leave 17% and 38% of the lanes idle in the last two).
-template <int N>
-constexpr int zconv_threads() { return N == 160 ? 320 : kFftThreads; }
-constexpr int kZMaxThreads = 320;
-
 // z pencils of the half spectrum: forward, times G (float octant), inverse.
 // Twiddles and the block's Green's values are staged in LDS with the data.
 template <int N, int FMT>
-__global__ __launch_bounds__(kZMaxThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
+__global__ __launch_bounds__(kFftThreads) void k_zconv_half(typename SpecStore<FMT>::T* __restrict__ spec_tiles,
                                                             const float2* __restrict__ tw_g,
                                                             const float* __restrict__ green, float sc_in,
                                                             float sc_out, int32_t* __restrict__ flag, int lo,
                                                             int hi) {
     using S = SpecStore<FMT>;
     using T = typename S::T;
-    constexpr int ZT = zconv_threads<N>();
+    constexpr int ZT = kFftThreads;
     constexpr int NH = N / 2 + 1;
     constexpr int W = 16;
     constexpr int LDN = N + 1;
@@ -991,7 +978,7 @@ void launch_tiles_fmt(float* real_tiles, void* spec, int ntiles, const float2* t
         hipLaunchKernelGGL((k_r2c_plane<N, FMT>), dim3(blocks), dim3(kPlaneThreads), 0, s, real_tiles, spec_tiles,
                            tw, nplanes, rho_store, flag);
     if (ev) hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(zconv_threads<N>()), 0, s, spec_tiles, tw,
+    hipLaunchKernelGGL((k_zconv_half<N, FMT>), dim3(N * NH / 16, ntiles), dim3(kFftThreads), 0, s, spec_tiles, tw,
                        green, rho_load, phi_store, flag, lo, hi);
     if (ev) hipEventRecord(ev[2], s);
     const int out_planes = (hi - lo) * ntiles;
