@@ -174,7 +174,7 @@ cube_status validate(const cube_box_desc* d, Geom* out) {
     if (!fft_supported(g.Nc) || !fft_tiles_supported(g.F))
         return fail(CUBE_UNSUPPORTED, "mesh side not supported by the FFT radix plans");
     if (!gather_supported(g))
-        return fail(CUBE_UNSUPPORTED, "tile side must be a multiple of 32 fine cells and r in {4, 8, 16}");
+        return fail(CUBE_UNSUPPORTED, "tile side must be a multiple of 32 fine cells and r in {4, 8}");
     if (!(d->dt > 0.0f) || !(d->v_headroom >= 1.0f)) return fail(CUBE_INVALID, "need dt > 0 and v_headroom >= 1");
     if (d->precision != CUBE_FP32 && d->precision != CUBE_MIXED_BF16 && d->precision != CUBE_MIXED_FP16)
         return fail(CUBE_INVALID, "unknown precision");

@@ -48,6 +48,10 @@ __device__ inline int block_exclusive_scan(int v, int* lds, int* total) {
     return res;
 }
 
+// The same scan with barriers that order LDS alone, for callers whose global
+// stores still in flight need not complete first.  Defined after lds_barrier.
+__device__ inline int block_exclusive_scan_lds(int v, int* lds, int* total);
+
 __device__ inline int wave_max(int v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
@@ -176,6 +180,29 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ inline int block_exclusive_scan_lds(int v, int* lds, int* total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    int inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) lds[wid] = inc;
+    lds_barrier();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            int t = lds[w];
+            lds[w] = acc;
+            acc += t;
+        }
+        lds[nw] = acc;
+    }
+    lds_barrier();
+    int res = inc - v + lds[wid];
+    *total = lds[nw];
+    lds_barrier();
+    return res;
 }
 
 }  // namespace cube

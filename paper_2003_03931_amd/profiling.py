@@ -30,7 +30,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 STAGE_KERNEL = {
     "coarse_deposit": "k_coarse_deposit",
     "coarse_fft_green": "k_fft<",
-    "fine_deposit": "k_deposit<16, 1",
+    "fine_deposit": "k_deposit_zm<",
     "fine_r2c_xy": "k_r2c_plane",
     "fine_z_green": "k_zconv_half",
     "fine_c2r_xy": "k_c2r_plane",
