@@ -281,6 +281,7 @@ __global__ __launch_bounds__(NT) void k_deposit_zm(Geom g, const int32_t* __rest
 
     const int D = 1 << log2D;
     const int halfD = D >> 1;
+    const float scalef = (float)scale;           // a power of two
     constexpr int Q = BW / 4;
     for (int j = 0; j < nch; ++j) {
         const int nsrc = nsx * nsy * min(LC, g.Fc - j * LC);
@@ -376,10 +377,19 @@ __global__ __launch_bounds__(NT) void k_deposit_zm(Geom g, const int32_t* __rest
             if (ix >= bwx || iy >= bwy || z < 0 || z >= M) continue;
             const ACC* a = &acc[(L * BW + iy) * BW + ix];
             float4 v;
-            v.x = (float)fma((double)a[0], scale, -1.0);
-            v.y = (float)fma((double)a[1], scale, -1.0);
-            v.z = (float)fma((double)a[2], scale, -1.0);
-            v.w = (float)fma((double)a[3], scale, -1.0);
+            if (max(max(a[0], a[1]), max(a[2], a[3])) < (ACC)(1u << 24)) {
+                // the sums and the power-of-two scale are exact in FP32, and
+                // the fused multiply-add rounds once: the FP64 result
+                v.x = fmaf((float)a[0], scalef, -1.0f);
+                v.y = fmaf((float)a[1], scalef, -1.0f);
+                v.z = fmaf((float)a[2], scalef, -1.0f);
+                v.w = fmaf((float)a[3], scalef, -1.0f);
+            } else {
+                v.x = (float)fma((double)a[0], scale, -1.0);
+                v.y = (float)fma((double)a[1], scale, -1.0);
+                v.z = (float)fma((double)a[2], scale, -1.0);
+                v.w = (float)fma((double)a[3], scale, -1.0);
+            }
             const int64_t cell = (int64_t)(T0x + ix) + (int64_t)M * ((T0y + iy) + (int64_t)M * z);
             *reinterpret_cast<float4*>(mesh + cell) = v;
         }
