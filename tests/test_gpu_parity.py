@@ -104,6 +104,31 @@ def test_fine_density_is_exact(name, tiles):
             assert np.array_equal(got, rho.transpose(2, 1, 0).astype(np.float32)), f"tile {t}"
 
 
+def test_fine_density_ragged_columns():
+    """A tile mesh whose side is not a multiple of the deposit's 32-cell
+    columns (t4 with an 8-cell buffer: 48 = 32 + 16 fine cells), bit for bit."""
+    import oracle
+    from oracle import cic, codec, pm
+    from paper_2003_03931_amd import CubeBox
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    spec = config("t4").with_(buffer_fine=8, r_cut_fine=5)
+    box = oracle.Box.from_spec(spec).validate()
+    assert box.F == 48
+    pos, vel = ics("t4")
+    ref = codec.compress(box, pos, vel, with_ids=True)
+    Q = ref.quanta()
+    off = ref.offsets()
+    with CubeBox(spec, with_ids=True) as g:
+        load_state(g, ref)
+        for t in (0, 22, 63):
+            idx, origin = pm.tile_sources(box, ref.counts, off, t)
+            X = pm.tile_box_coords(box, Q[idx], origin)
+            rho = cic.deposit(X, box.F, periodic=False) / box.h ** 3 - 1.0
+            got = g.debug_mesh(2, t).cpu().numpy()
+            assert np.array_equal(got, rho.transpose(2, 1, 0).astype(np.float32)), f"tile {t}"
+
+
 @pytest.mark.parametrize("name", ["c1", "c2s"])
 def test_coarse_potential(name):
     from oracle import green, pm
