@@ -232,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_deposit_zm(Geom g, const int32_t* __rest
     __shared__ __align__(16) ACC acc[NP * PL];
     __shared__ int s_start[MAXSRC];
     __shared__ int s_pref[MAXSRC + 1];
-    __shared__ int s_rel[MAXSRC];                // window coordinates (x, y + 1, z), 8 bits each
+    __shared__ int s_rel[MAXSRC];                // source cell: x, y from the column's ring, z in the chunk; 8 bits each
     __shared__ uint16_t s_map[MAPCAP];
     __shared__ int s_scan[NT / kWave + 1];
 

@@ -20,6 +20,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,16 +50,26 @@ COPY_KERNELS = ("elementwise", "copyBuffer")
 NOT_IN_STEP = ("pp.hip", "vcodec.hip", "server.cpp", "ensemble.cpp")
 
 
-def source_digest():
-    """Digest of the sources of the profiled step's kernels: a traffic summary
-    is valid only for them."""
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def _code_of(text):
+    """Source text without comments and blank lines: what the compiler sees,
+    so that a comment edit does not invalidate a summary."""
+    lines = (ln.rstrip() for ln in _COMMENT.sub("", text).splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
+def source_digest(root=None):
+    """Digest of the code of the profiled step's kernels (comments ignored): a
+    traffic summary is valid only for them."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for f in sorted(glob.glob(os.path.join(root or HERE, "csrc", "*"))):
         if os.path.basename(f) in NOT_IN_STEP:
             continue
-        with open(f, "rb") as fh:
+        with open(f, encoding="utf-8") as fh:
             h.update(os.path.basename(f).encode())
-            h.update(fh.read())
+            h.update(_code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
